@@ -1,0 +1,86 @@
+"""The five synthetic workloads, with their seeds.
+
+Each builder returns geometry plus phantom and noise draws only.  Turning a
+phantom into data (b = A x_true plus noise) needs the forward projector, so
+callers do that step with the projector they are testing or timing.
+
+W1  2D parallel beam, 64x64, 90 views over 180 deg, 96 unit bins, 10 ellipses.
+W2  3D circular cone beam, 128^3, 180 views over 360 deg, 192x192 detector,
+    SOD = 4 N, SDD = 8 N (voxel 1), 12 ellipsoids.
+W3  3D cone beam, 256^3, 360 views, 384x384 detector, same ratios, ellipsoids
+    plus 5 % smoothed Gaussian texture, Poisson data at 1e5 photons per ray.
+W4  batch of four 128^3 volumes in the W2 geometry (autograd check).
+W5  64 independent 2D slices of seeded uneven sizes.
+"""
+
+import math
+import numpy as np
+
+from .geometry import parallel2d, cone3d
+from .phantoms import (random_ellipses, rasterize_ellipses, random_ellipsoids,
+                       rasterize_ellipsoids, smooth_texture, gaussian_noise)
+
+
+def w1_geometry():
+    return parallel2d(64, 90, 96)
+
+
+def w1_phantom(seed: int = 101):
+    g = w1_geometry()
+    ells = random_ellipses(seed, 10, g.nx * g.voxel)
+    return rasterize_ellipses(ells, g.nx, g.voxel)
+
+
+def w2_geometry(n: int = 128, views: int = 180):
+    return cone3d(n, views, int(1.5 * n))
+
+
+def w2_phantom(seed: int = 201, n: int = 128) -> np.ndarray:
+    ells = random_ellipsoids(seed, 12, float(n))
+    return rasterize_ellipsoids(ells, n, 1.0, dtype=np.float32)
+
+
+def w3_geometry(n: int = 256, views: int = 360):
+    return cone3d(n, views, int(1.5 * n))
+
+
+def w3_phantom(seed: int = 301, texture_seed: int = 302, n: int = 256) -> np.ndarray:
+    """Ellipsoids plus texture: smoothed white noise (sigma 2 voxels) with a
+    standard deviation of 5 % of the phantom mean over its support, added
+    inside the support and clipped at zero."""
+    ells = random_ellipsoids(seed, 12, float(n))
+    vol = rasterize_ellipsoids(ells, n, 1.0, dtype=np.float32)
+    support = vol > 0
+    mean = float(vol[support].mean()) if support.any() else 0.0
+    tex = smooth_texture(texture_seed, vol.shape, 2.0)
+    vol = vol + np.where(support, (0.05 * mean) * tex, 0.0).astype(np.float32)
+    np.maximum(vol, 0.0, out=vol)
+    return vol.astype(np.float32)
+
+
+def w4_phantoms(n: int = 128):
+    return [w2_phantom(401 + i, n) for i in range(4)]
+
+
+def w5_slices(seed: int = 501, count: int = 64):
+    """List of (geometry, phantom seed, noise seed) for the uneven batch."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice([128, 192, 256, 384, 512], size=count)
+    views = rng.choice([90, 180, 360], size=count)
+    out = []
+    for i in range(count):
+        n = int(sizes[i])
+        g = parallel2d(n, int(views[i]), int(math.ceil(1.5 * n)))
+        out.append((g, 510 + i, 600 + i))
+    return out
+
+
+def w5_phantom(g, seed: int) -> np.ndarray:
+    ells = random_ellipses(seed, 10, g.nx * g.voxel)
+    return rasterize_ellipses(ells, g.nx, g.voxel)
+
+
+def relative_gaussian_noise(clean: np.ndarray, level: float, seed: int) -> np.ndarray:
+    """e = level * ||clean|| * eta / ||eta||, eta ~ N(0, I)."""
+    eta = gaussian_noise(seed, clean.size).reshape(clean.shape)
+    return level * np.linalg.norm(clean) * eta / np.linalg.norm(eta)
