@@ -1,0 +1,199 @@
+/*
+ * ct.h -- C ABI of the MI355X (gfx950) library for the ABBA method:
+ * BA-GMRES and AB-GMRES for CT with unmatched projector / back-projector
+ * pairs, and CGLS for comparison.
+ *
+ * Method: Sidky, Hansen, Jorgensen, Pan, "Iterative image reconstruction for
+ * CT with unmatched projection matrices using the generalized minimal
+ * residual algorithm".
+ *   - the linear CT model A x = b after the negative log (Sec. I, Eq. 1);
+ *   - CGLS for min ||A x - b|| with A^T replaced by B (Sec. I, Eq. 2);
+ *   - AB-GMRES: A B y = b, x = B y (Sec. II, Eq. 4);
+ *   - BA-GMRES: B A x = B b (Sec. II, Eq. 5);
+ *   - zero initial vector; first basis vector b (AB) or B b (BA); one
+ *     orthonormalised basis vector and one least-squares solve per
+ *     iteration; the iteration count is the only parameter (Sec. II);
+ *   - A ray-driven, B_un voxel-driven with linear interpolation on the
+ *     detector, B_FBP = B_un F with F the ramp filter (Sec. III).
+ *
+ * Conventions (all lengths FP64, in the same unit as the voxel size):
+ *   volume   float x[nz][ny][nx] (x fastest); voxel (ix,iy,iz) has centre
+ *            ((ix-(nx-1)/2) d, (iy-(ny-1)/2) d, (iz-(nz-1)/2) d), d = voxel.
+ *   data     y[n_views][nv][nu] (u fastest); 2D uses nz = nv = 1.
+ *   angles   NULL -> uniform: t_p = (pi*p)/P (2D) or (2*pi*p)/P (3D).
+ *   2D       parallel beam. View p: n = (cos t, sin t), d = (-sin t, cos t);
+ *            bin a at s = (a-(nu-1)/2) du; ray { s n + t d }.
+ *   3D       circular cone beam. Source (SOD cos t, SOD sin t, 0); detector
+ *            centre = source - SDD (cos t, sin t, 0); e_u = (-sin t, cos t, 0),
+ *            e_v = (0,0,1); pixel (au,av) at centre + u e_u + v e_v with
+ *            u = (au-(nu-1)/2) du, v = (av-(nv-1)/2) dv.
+ *
+ * Operators:
+ *   A      Joseph: for the dominant axis a of the ray direction r (ties go to
+ *          x, then y; for the uniform 2D view set the choice is x-major iff
+ *          P <= 4p <= 3P), sample the ray in every voxel-centre plane along a,
+ *          interpolate bilinearly (linearly in 2D) in the plane with zero
+ *          outside the grid, sum, multiply by d*|r|/|r_a|.
+ *   A^T    exact transpose of A's weights.
+ *   B_un   voxel-driven: 2D weight d^2/du times the linear interpolation of
+ *          view p at s = x.n; 3D weight d^3 M^2/(du dv) times the bilinear
+ *          interpolation at the voxel's perspective projection
+ *          (M = SDD/U, U = SOD - (x cos t + y sin t)); zero outside the
+ *          detector; summed over views.
+ *   F      Ram-Lak along u: (F q)[a] = du * sum_a' h[a-a'] q[a'],
+ *          h[0] = 1/(4 du^2), h[even] = 0, h[odd j] = -1/(pi^2 j^2 du^2);
+ *          zero-padded linear convolution per view and detector row.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller,
+ * contiguous, 256-byte aligned for workspaces.  The library owns only the
+ * geometry handle (immutable after creation; may be shared across streams
+ * and threads).  Operators and solvers take a caller-provided workspace
+ * sized by the matching *_workspace_bytes query; no entry point below
+ * allocates device memory except ct_geometry_create.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Operators
+ * are asynchronous.  Solvers enqueue all their work on `stream` and then
+ * synchronise that stream once to return the residual history and the
+ * iteration count.
+ *
+ * Errors: every entry point returns a ct_status; nothing throws or aborts
+ * across the ABI.  ct_last_error() returns a thread-local message for the
+ * last failure on the calling thread.  A GMRES breakdown is not an error:
+ * it shows as *iters_done < opts->iters.
+ */
+#ifndef CT_ABBA_H
+#define CT_ABBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ct_geometry ct_geometry;
+
+enum {
+    CT_OK = 0,
+    CT_ERR_ARG = 1,          /* invalid argument, size or workspace          */
+    CT_ERR_ALLOC = 2,        /* device allocation failed (create only)      */
+    CT_ERR_HIP = 3,          /* a HIP runtime call failed                    */
+    CT_ERR_NUMERIC = 4,      /* non-finite value met in a solver             */
+    CT_ERR_UNSUPPORTED = 5   /* valid input outside what the kernels cover  */
+};
+
+enum { CT_PARALLEL_2D = 0, CT_CONE_CIRCULAR_3D = 1 };
+enum { CT_F32 = 0, CT_F16 = 1 };                  /* data storage type    */
+enum { CT_B_UNMATCHED = 0, CT_B_RAMP = 1, CT_B_AT = 2 };
+enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2 };
+enum { CT_OP_A = 0, CT_OP_B = 1, CT_OP_B_RAMP = 2, CT_OP_AT = 3 };
+
+typedef struct {
+    int kind;                 /* CT_PARALLEL_2D or CT_CONE_CIRCULAR_3D      */
+    int nx, ny, nz;           /* nz = 1 for 2D                              */
+    double voxel;             /* isotropic voxel size d > 0                 */
+    int n_views;
+    const double *angles;     /* HOST pointer to n_views radians, or NULL   */
+    int nu, nv;               /* detector columns / rows (nv = 1 for 2D)    */
+    double du, dv;            /* detector pitch (at the detector, cone)     */
+    double sod, sdd;          /* source-isocentre, source-detector (cone)   */
+} ct_geometry_desc;
+
+typedef struct {
+    int iters;                /* number of iterations K >= 0               */
+    int B;                    /* CT_B_UNMATCHED, CT_B_RAMP (B_un F), CT_B_AT */
+    int sino_dtype;           /* CT_F32, or CT_F16 storage of the solver's
+                                 internal projections (FP32 arithmetic) */
+    double breakdown_tol;     /* GMRES: stop when the new vector's norm after
+                                 orthogonalisation is <= tol times its norm
+                                 before; 0 -> 64 * 2^-24                    */
+} ct_solver_opts;
+
+/* Validate the descriptor, build per-view tables (FP64 cos/sin, 2D
+ * dominant-axis flags, Ram-Lak taps) and upload them to the current device.
+ * Errors: CT_ERR_ARG for non-positive sizes or pitches, SDD <= SOD, a volume
+ * that reaches the source circle; CT_ERR_UNSUPPORTED for cone angles at
+ * which a ray could be z-dominant, or for volumes whose padded copy exceeds
+ * 4 GiB; CT_ERR_ALLOC / CT_ERR_HIP on device failures.  *out is NULL on
+ * error.  Caller destroys with ct_geometry_destroy. */
+int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **out);
+
+/* Free the handle and its device tables.  NULL is ignored.  The caller must
+ * make sure no enqueued work still uses the handle. */
+void ct_geometry_destroy(ct_geometry *g);
+
+/* n_vox = nx*ny*nz, n_rays = n_views*nv*nu.  Either pointer may be NULL. */
+int ct_geometry_sizes(const ct_geometry *g, size_t *n_vox, size_t *n_rays);
+
+/* Workspace bytes needed by one operator call over `batch` items
+ * (op = CT_OP_*).  CT_OP_B needs none (0). */
+int ct_op_workspace_bytes(const ct_geometry *g, int op, int batch, size_t *bytes);
+
+/* y = A x (Sec. III, the ray-driven projector; Joseph's discretisation).
+ * x: float[batch][nz][ny][nx]; y: float or half (y_dtype)
+ * [batch][n_views][nv][nu], round-to-nearest-even for half.
+ * ws: >= ct_op_workspace_bytes(CT_OP_A) bytes. */
+int ct_project_A(const ct_geometry *g, const float *x, void *y, int y_dtype,
+                 int batch, void *ws, size_t ws_bytes, void *stream);
+
+/* x = B_un y, or x = B_un F y when ramp_filter != 0 (Sec. III, B_un and
+ * B_FBP).  y: float or half [batch][n_views][nv][nu]; x: float[batch][...].
+ * ws: >= ct_op_workspace_bytes(CT_OP_B or CT_OP_B_RAMP) bytes (may be NULL
+ * when that is 0). */
+int ct_backproject_B(const ct_geometry *g, const void *y, int y_dtype, float *x,
+                     int ramp_filter, int batch, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* x = A^T y, the exact transpose of ct_project_A (Sec. I: CGLS requires
+ * B = A^T).  Scatter form with FP32 atomics: results are deterministic only
+ * up to FP32 summation order.  ws: >= ct_op_workspace_bytes(CT_OP_AT). */
+int ct_backproject_AT(const ct_geometry *g, const void *y, int y_dtype, float *x,
+                      int batch, void *ws, size_t ws_bytes, void *stream);
+
+/* y = F q, the Ram-Lak filter alone (Sec. III).  q, y: float
+ * [batch][n_views][nv][nu]; q == y is not allowed. */
+int ct_ramp_filter(const ct_geometry *g, const float *q, float *y, int batch,
+                   void *stream);
+
+/* Workspace bytes for a solver (CT_SOLVER_*) with the given options. */
+int ct_solver_workspace_bytes(const ct_geometry *g, int solver,
+                              const ct_solver_opts *opts, size_t *bytes);
+
+/* BA-GMRES (Sec. II, Eq. 5): x_K minimises ||B b - B A x|| over the Krylov
+ * space K_K(B A, B b), x0 = 0.  b: float[n_views][nv][nu]; x: float[nz][ny][nx].
+ * Basis FP32 in the workspace; dot products, norms, the Hessenberg matrix,
+ * the Givens rotations and the triangular solve in FP64 on the device.
+ * res_hist: HOST double[iters+1] or NULL; res_hist[k] = ||B b - B A x_k||
+ * as carried by the rotations (res_hist[0] = ||B b||).  iters_done: HOST,
+ * may be NULL; < iters after a breakdown, 0 when B b = 0 (then x = 0).
+ * CT_ERR_NUMERIC if a non-finite value appears (x is then unspecified). */
+int ct_ba_gmres(const ct_geometry *g, const float *b, float *x,
+                const ct_solver_opts *opts, void *ws, size_t ws_bytes,
+                double *res_hist, int *iters_done, void *stream);
+
+/* AB-GMRES (Sec. II, Eq. 4): y_K minimises ||b - A B y|| over
+ * K_K(A B, b), x = B y.  Basis in data space.  res_hist[k] = ||b - A x_k||
+ * as carried by the rotations.  Other arguments as ct_ba_gmres. */
+int ct_ab_gmres(const ct_geometry *g, const float *b, float *x,
+                const ct_solver_opts *opts, void *ws, size_t ws_bytes,
+                double *res_hist, int *iters_done, void *stream);
+
+/* CGLS (Sec. I, Eq. 2) with A^T replaced by opts->B (CT_B_AT gives the
+ * textbook method; CT_B_UNMATCHED / CT_B_RAMP give the unmatched variant the
+ * paper shows diverging).  res_hist[k] = ||b - A x_k|| from the recurrence.
+ * Scalars stay on the device in FP64. */
+int ct_cgls(const ct_geometry *g, const float *b, float *x,
+            const ct_solver_opts *opts, void *ws, size_t ws_bytes,
+            double *res_hist, int *iters_done, void *stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *ct_last_error(void);
+
+/* Library version string. */
+const char *ct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CT_ABBA_H */

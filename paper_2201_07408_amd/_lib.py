@@ -1,0 +1,86 @@
+"""ctypes declarations of the C ABI in include/ct.h."""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libctabba.so")
+
+CT_OK, CT_ERR_ARG, CT_ERR_ALLOC, CT_ERR_HIP, CT_ERR_NUMERIC, CT_ERR_UNSUPPORTED = range(6)
+CT_PARALLEL_2D, CT_CONE_CIRCULAR_3D = 0, 1
+CT_F32, CT_F16 = 0, 1
+CT_B_UNMATCHED, CT_B_RAMP, CT_B_AT = 0, 1, 2
+CT_SOLVER_BA, CT_SOLVER_AB, CT_SOLVER_CGLS = 0, 1, 2
+CT_OP_A, CT_OP_B, CT_OP_B_RAMP, CT_OP_AT = 0, 1, 2, 3
+
+# every symbol the header declares
+EXPORTS = [
+    "ct_geometry_create", "ct_geometry_destroy", "ct_geometry_sizes",
+    "ct_op_workspace_bytes", "ct_project_A", "ct_backproject_B",
+    "ct_backproject_AT", "ct_ramp_filter", "ct_solver_workspace_bytes",
+    "ct_ba_gmres", "ct_ab_gmres", "ct_cgls", "ct_last_error", "ct_version",
+]
+
+
+class GeometryDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("voxel", ctypes.c_double),
+        ("n_views", ctypes.c_int),
+        ("angles", ctypes.POINTER(ctypes.c_double)),
+        ("nu", ctypes.c_int), ("nv", ctypes.c_int),
+        ("du", ctypes.c_double), ("dv", ctypes.c_double),
+        ("sod", ctypes.c_double), ("sdd", ctypes.c_double),
+    ]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("B", ctypes.c_int),
+        ("sino_dtype", ctypes.c_int),
+        ("breakdown_tol", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIBPATH):
+    """Load libctabba.so; raise if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            "libctabba.so not found at %s: build it with "
+            "`python -m paper_2201_07408_amd.build` (no CPU fallback exists)" % path)
+    lib = ctypes.CDLL(path)
+    vp, sz, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    gp = vp
+    sig = {
+        "ct_geometry_create": ([ctypes.POINTER(GeometryDesc), ctypes.POINTER(vp)], i),
+        "ct_geometry_destroy": ([gp], None),
+        "ct_geometry_sizes": ([gp, szp, szp], i),
+        "ct_op_workspace_bytes": ([gp, i, i, szp], i),
+        "ct_project_A": ([gp, vp, vp, i, i, vp, sz, vp], i),
+        "ct_backproject_B": ([gp, vp, i, vp, i, i, vp, sz, vp], i),
+        "ct_backproject_AT": ([gp, vp, i, vp, i, vp, sz, vp], i),
+        "ct_ramp_filter": ([gp, vp, vp, i, vp], i),
+        "ct_solver_workspace_bytes": ([gp, i, ctypes.POINTER(SolverOpts), szp], i),
+        "ct_ba_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_ab_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_cgls": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_last_error": ([], ctypes.c_char_p),
+        "ct_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib

@@ -1,0 +1,217 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Tensors are torch device tensors; the work is enqueued on torch's current
+stream of the tensors' device.  Function names follow include/ct.h.
+"""
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional
+
+import torch
+
+from . import _lib as L
+
+
+class CtError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = ct_last_error()
+        super().__init__("%s failed with status %d: %s" % (where, status, msg))
+        self.status = status
+
+
+def ct_last_error() -> str:
+    v = L.load().ct_last_error()
+    return v.decode() if v else ""
+
+
+def _check(status: int, where: str) -> None:
+    if status != L.CT_OK:
+        raise CtError(status, where)
+
+
+def _stream(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need_device(t: torch.Tensor, name: str, dtype=None) -> None:
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor (no CPU path exists)" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+
+
+_DT = {torch.float32: L.CT_F32, torch.float16: L.CT_F16}
+_B = {"un": L.CT_B_UNMATCHED, "ramp": L.CT_B_RAMP, "AT": L.CT_B_AT}
+
+
+class Geometry:
+    """Owns a ct_geometry handle.  `desc` is any object with the fields of
+    ct_geometry_desc (kind, nx, ny, nz, voxel, n_views, nu, nv, du, dv, sod,
+    sdd, angles)."""
+
+    def __init__(self, desc, device=None):
+        lib = L.load()
+        self.desc = desc
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        angles = getattr(desc, "angles", None)
+        self._angles = None
+        ap = None
+        if angles is not None:
+            self._angles = (ctypes.c_double * len(angles))(*[float(a) for a in angles])
+            ap = ctypes.cast(self._angles, ctypes.POINTER(ctypes.c_double))
+        d = L.GeometryDesc(int(desc.kind), int(desc.nx), int(desc.ny), int(desc.nz),
+                           float(desc.voxel), int(desc.n_views), ap, int(desc.nu),
+                           int(desc.nv), float(desc.du), float(desc.dv),
+                           float(getattr(desc, "sod", 0.0)), float(getattr(desc, "sdd", 0.0)))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)), "ct_geometry_create")
+        self.handle = h
+        nv, nr = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib.ct_geometry_sizes(h, ctypes.byref(nv), ctypes.byref(nr)), "ct_geometry_sizes")
+        self.n_vox, self.n_rays = nv.value, nr.value
+        self.vol_shape = (int(desc.nz), int(desc.ny), int(desc.nx))
+        self.sino_shape = (int(desc.n_views), int(desc.nv), int(desc.nu))
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            L.load().ct_geometry_destroy(h)
+            self.handle = None
+
+    # workspace cache: one buffer per purpose, grown on demand
+    def workspace(self, key: str, nbytes: int) -> torch.Tensor:
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def op_workspace(self, op: int, batch: int = 1) -> torch.Tensor:
+        n = ctypes.c_size_t()
+        _check(L.load().ct_op_workspace_bytes(self.handle, op, batch, ctypes.byref(n)),
+               "ct_op_workspace_bytes")
+        return self.workspace("op%d" % op, n.value)
+
+
+def ct_geometry_create(desc, device=None) -> Geometry:
+    return Geometry(desc, device)
+
+
+def _batch_of(t: torch.Tensor, item_numel: int, name: str) -> int:
+    if t.numel() % item_numel != 0 or t.numel() == 0 and item_numel == 0:
+        raise ValueError("%s has %d elements, not a multiple of %d" % (name, t.numel(), item_numel))
+    return t.numel() // item_numel
+
+
+def ct_project_A(g: Geometry, x: torch.Tensor, y_dtype=torch.float32,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x; x [..., nz, ny, nx] float32 -> y [..., P, nv, nu]."""
+    _need_device(x, "x", torch.float32)
+    batch = _batch_of(x, g.n_vox, "x")
+    lead = x.shape[:-3] if x.dim() >= 3 else ()
+    if out is None:
+        out = torch.empty(tuple(lead) + g.sino_shape, dtype=y_dtype, device=x.device)
+    _need_device(out, "out", y_dtype)
+    ws = g.op_workspace(L.CT_OP_A, batch)
+    _check(L.load().ct_project_A(g.handle, _ptr(x), _ptr(out), _DT[y_dtype], batch, _ptr(ws),
+                                 ws.numel(), _stream(x)), "ct_project_A")
+    return out
+
+
+def ct_backproject_B(g: Geometry, y: torch.Tensor, ramp: bool = False,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = B_un y (ramp=False) or B_un F y (ramp=True)."""
+    _need_device(y, "y")
+    batch = _batch_of(y, g.n_rays, "y")
+    lead = y.shape[:-3] if y.dim() >= 3 else ()
+    if out is None:
+        out = torch.empty(tuple(lead) + g.vol_shape, dtype=torch.float32, device=y.device)
+    _need_device(out, "out", torch.float32)
+    ws = g.op_workspace(L.CT_OP_B_RAMP if ramp else L.CT_OP_B, batch)
+    _check(L.load().ct_backproject_B(g.handle, _ptr(y), _DT[y.dtype], _ptr(out), int(bool(ramp)),
+                                     batch, _ptr(ws), ws.numel(), _stream(y)), "ct_backproject_B")
+    return out
+
+
+def ct_backproject_AT(g: Geometry, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = A^T y (exact transpose of ct_project_A)."""
+    _need_device(y, "y")
+    batch = _batch_of(y, g.n_rays, "y")
+    lead = y.shape[:-3] if y.dim() >= 3 else ()
+    if out is None:
+        out = torch.empty(tuple(lead) + g.vol_shape, dtype=torch.float32, device=y.device)
+    _need_device(out, "out", torch.float32)
+    ws = g.op_workspace(L.CT_OP_AT, batch)
+    _check(L.load().ct_backproject_AT(g.handle, _ptr(y), _DT[y.dtype], _ptr(out), batch, _ptr(ws),
+                                      ws.numel(), _stream(y)), "ct_backproject_AT")
+    return out
+
+
+def ct_ramp_filter(g: Geometry, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _need_device(q, "q", torch.float32)
+    batch = _batch_of(q, g.n_rays, "q")
+    if out is None:
+        out = torch.empty_like(q)
+    _check(L.load().ct_ramp_filter(g.handle, _ptr(q), _ptr(out), batch, _stream(q)), "ct_ramp_filter")
+    return out
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor
+    res: List[float]
+    iters_done: int
+
+
+def _solve(fn_name: str, solver: int, g: Geometry, b: torch.Tensor, iters: int, B: str,
+           sino_dtype, breakdown_tol: float, out: Optional[torch.Tensor]) -> SolveResult:
+    _need_device(b, "b", torch.float32)
+    if b.numel() != g.n_rays:
+        raise ValueError("b must have %d elements" % g.n_rays)
+    lib = L.load()
+    opts = L.SolverOpts(int(iters), _B[B], _DT[sino_dtype], float(breakdown_tol))
+    n = ctypes.c_size_t()
+    _check(lib.ct_solver_workspace_bytes(g.handle, solver, ctypes.byref(opts), ctypes.byref(n)),
+           "ct_solver_workspace_bytes")
+    ws = g.workspace("solver", n.value)
+    if out is None:
+        out = torch.empty(g.vol_shape, dtype=torch.float32, device=b.device)
+    _need_device(out, "out", torch.float32)
+    res = (ctypes.c_double * (int(iters) + 1))()
+    done = ctypes.c_int(0)
+    st = getattr(lib, fn_name)(g.handle, _ptr(b), _ptr(out), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                               res, ctypes.byref(done), _stream(b))
+    _check(st, fn_name)
+    return SolveResult(out, list(res)[: done.value + 1], done.value)
+
+
+def ct_ba_gmres(g: Geometry, b: torch.Tensor, iters: int, B: str = "un", sino_dtype=torch.float32,
+                breakdown_tol: float = 0.0, out: Optional[torch.Tensor] = None) -> SolveResult:
+    """BA-GMRES (Eq. 5): GMRES on B A x = B b, x0 = 0."""
+    return _solve("ct_ba_gmres", L.CT_SOLVER_BA, g, b, iters, B, sino_dtype, breakdown_tol, out)
+
+
+def ct_ab_gmres(g: Geometry, b: torch.Tensor, iters: int, B: str = "un", breakdown_tol: float = 0.0,
+                out: Optional[torch.Tensor] = None) -> SolveResult:
+    """AB-GMRES (Eq. 4): GMRES on A B y = b, x = B y."""
+    return _solve("ct_ab_gmres", L.CT_SOLVER_AB, g, b, iters, B, torch.float32, breakdown_tol, out)
+
+
+def ct_cgls(g: Geometry, b: torch.Tensor, iters: int, B: str = "AT",
+            out: Optional[torch.Tensor] = None) -> SolveResult:
+    """CGLS (Eq. 2) with A^T replaced by B."""
+    return _solve("ct_cgls", L.CT_SOLVER_CGLS, g, b, iters, B, torch.float32, 0.0, out)

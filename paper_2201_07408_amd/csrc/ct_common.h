@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP translation units of libctabba.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ct.h"
+
+namespace ct {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+void clear_error();
+
+#define CT_HIP_CHECK(expr)                                                     \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ::ct::set_error(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return CT_ERR_HIP;                                                 \
+        }                                                                      \
+    } while (0)
+
+#define CT_LAUNCH_CHECK()                                                      \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess) {                                                \
+            ::ct::set_error(std::string("kernel launch: ") + hipGetErrorString(e_)); \
+            return CT_ERR_HIP;                                                 \
+        }                                                                      \
+    } while (0)
+
+#define CT_ARG_CHECK(cond, msg)                                                \
+    do {                                                                       \
+        if (!(cond)) {                                                         \
+            ::ct::set_error(msg);                                              \
+            return CT_ERR_ARG;                                                 \
+        }                                                                      \
+    } while (0)
+
+#define CT_TRY(expr)                                                           \
+    do {                                                                       \
+        int s_ = (expr);                                                       \
+        if (s_ != CT_OK) return s_;                                            \
+    } while (0)
+
+constexpr int kPad = 2;        // zero border of the padded volume copies
+constexpr size_t kAlign = 256; // workspace carve alignment
+
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------- kernel geometry
+// Plain-old-data copy of the geometry passed by value to kernels.
+struct GeomK {
+    int kind;          // 0 = 2D parallel, 1 = 3D cone
+    int nx, ny, nz;
+    int P, nu, nv;
+    double vox, du, dv, sod, sdd;
+    const double *cs;  // device: cos, sin per view (2*P)
+    const int *axis;   // device: per-view dominant axis for 2D (0 = x, 1 = y)
+};
+
+// Padded, axis-permuted volume copies read by the forward projector and
+// accumulated into by the scatter transpose.
+//   Vx[ix][iz+pz][iy+kPad], rows of ny+2*kPad, (nz+2*pz) rows per plane
+//   Vy[iy][iz+pz][ix+kPad], rows of nx+2*kPad
+// with pz = kPad in 3D and 0 in 2D.
+struct PadLayout {
+    int pz;
+    uint32_t rx, sx;   // row / plane stride of Vx (elements)
+    uint32_t ry, sy;   // row / plane stride of Vy
+    size_t nvx, nvy;   // element counts
+};
+
+inline PadLayout pad_layout(const GeomK &g) {
+    PadLayout L;
+    L.pz = (g.kind == 1) ? kPad : 0;
+    L.rx = (uint32_t)(g.ny + 2 * kPad);
+    L.sx = L.rx * (uint32_t)(g.nz + 2 * L.pz);
+    L.ry = (uint32_t)(g.nx + 2 * kPad);
+    L.sy = L.ry * (uint32_t)(g.nz + 2 * L.pz);
+    L.nvx = (size_t)L.sx * g.nx;
+    L.nvy = (size_t)L.sy * g.ny;
+    return L;
+}
+
+}  // namespace ct
+
+struct ct_geometry {
+    ct_geometry_desc d;            // angles pointer cleared
+    int device;
+    int uniform;
+    std::vector<double> h_cs;      // cos, sin per view (host copy)
+    std::vector<int> h_axis;       // 2D dominant axis per view
+    double *d_cs = nullptr;
+    int *d_axis = nullptr;
+    float *d_ramp = nullptr;       // du * h[j], j = 0..nu-1 (FP32)
+    size_t n_vox = 0, n_rays = 0;
+    ct::GeomK k;                   // kernel view
+    ct::PadLayout pad;
+};
+
+namespace ct {
+
+// --------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return CT_OK or CT_ERR_HIP.  `stop`, when
+// non-null, points to a device flag; kernels exit at once when it is set.
+
+int launch_fill(float *p, size_t n, float v, hipStream_t s);
+int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s);
+int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy,
+                    const int *stop, hipStream_t s);
+int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y,
+                   int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
+int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx,
+                     float *vy, const int *stop, hipStream_t s);
+int launch_unpad_sum(const ct_geometry *g, const float *vx, const float *vy, float *x,
+                     const float *scale, const int *stop, hipStream_t s);
+int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *x,
+                       const float *in_scale, const int *stop, hipStream_t s);
+int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out,
+                int out_dtype, size_t rows, const int *stop, hipStream_t s);
+
+// Composite operators used by the solvers and the ABI: x/y of one item.
+struct OpScratch {
+    float *vx = nullptr, *vy = nullptr;   // padded copies (A, A^T)
+    void *filt = nullptr;                  // filtered data (ramp), dtype as data
+};
+size_t op_scratch_bytes(const ct_geometry *g, int op, int data_dtype);
+OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *ws);
+
+// y = A x.  Padding of vx/vy must already be zero (pad_ready) or is zeroed here.
+int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratch &sc,
+            bool pad_ready, const float *out_scale, const int *stop, hipStream_t s);
+// x = B y with B in {B_un, B_un F, A^T}.
+int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *x,
+            OpScratch &sc, const float *in_scale, const int *stop, hipStream_t s);
+
+}  // namespace ct

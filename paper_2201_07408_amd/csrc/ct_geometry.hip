@@ -1,0 +1,159 @@
+// Geometry handle, error state and small shared launchers.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "ct_common.h"
+
+namespace ct {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+__global__ void k_fill(float *__restrict__ p, size_t n, float v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+int launch_fill(float *p, size_t n, float v, hipStream_t s) {
+    if (n == 0) return CT_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+}  // namespace ct
+
+using namespace ct;
+
+extern "C" const char *ct_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *ct_version(void) { return "ctabba 0.1 (gfx950)"; }
+
+extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **out) {
+    clear_error();
+    CT_ARG_CHECK(out != nullptr, "ct_geometry_create: out is NULL");
+    *out = nullptr;
+    CT_ARG_CHECK(desc != nullptr, "ct_geometry_create: desc is NULL");
+    const ct_geometry_desc &d = *desc;
+    CT_ARG_CHECK(d.kind == CT_PARALLEL_2D || d.kind == CT_CONE_CIRCULAR_3D,
+                 "ct_geometry_create: unknown kind");
+    CT_ARG_CHECK(d.nx >= 1 && d.ny >= 1 && d.nz >= 1, "ct_geometry_create: volume sizes must be >= 1");
+    CT_ARG_CHECK(d.n_views >= 1 && d.nu >= 1 && d.nv >= 1, "ct_geometry_create: detector sizes must be >= 1");
+    CT_ARG_CHECK(std::isfinite(d.voxel) && d.voxel > 0, "ct_geometry_create: voxel must be > 0");
+    CT_ARG_CHECK(std::isfinite(d.du) && d.du > 0, "ct_geometry_create: du must be > 0");
+    if (d.kind == CT_PARALLEL_2D) {
+        CT_ARG_CHECK(d.nz == 1 && d.nv == 1, "ct_geometry_create: 2D geometry needs nz = nv = 1");
+    } else {
+        CT_ARG_CHECK(std::isfinite(d.dv) && d.dv > 0, "ct_geometry_create: dv must be > 0");
+        CT_ARG_CHECK(std::isfinite(d.sod) && d.sod > 0, "ct_geometry_create: sod must be > 0");
+        CT_ARG_CHECK(std::isfinite(d.sdd) && d.sdd > d.sod, "ct_geometry_create: sdd must exceed sod");
+        double hx = 0.5 * d.nx * d.voxel, hy = 0.5 * d.ny * d.voxel;
+        CT_ARG_CHECK(std::sqrt(hx * hx + hy * hy) < d.sod,
+                     "ct_geometry_create: the volume reaches the source circle");
+        double vmax = 0.5 * (d.nv - 1) * d.dv;
+        if (!(vmax * std::sqrt(2.0) < d.sdd)) {
+            set_error("ct_geometry_create: cone angle allows z-dominant rays");
+            return CT_ERR_UNSUPPORTED;
+        }
+    }
+    // 32-bit element offsets in the kernels
+    const double lim = 4294967296.0 / 4.0;
+    if ((double)d.nx * (d.ny + 2 * kPad) * (d.nz + 4 * kPad) >= lim ||
+        (double)d.ny * (d.nx + 2 * kPad) * (d.nz + 4 * kPad) >= lim ||
+        (double)d.n_views * d.nv * d.nu >= 2147483647.0) {
+        set_error("ct_geometry_create: volume or data too large for 32-bit offsets");
+        return CT_ERR_UNSUPPORTED;
+    }
+
+    ct_geometry *g = new (std::nothrow) ct_geometry();
+    if (!g) {
+        set_error("ct_geometry_create: host allocation failed");
+        return CT_ERR_ALLOC;
+    }
+    g->d = d;
+    g->d.angles = nullptr;
+    g->uniform = (d.angles == nullptr);
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        set_error("ct_geometry_create: hipGetDevice failed");
+        return CT_ERR_HIP;
+    }
+    const int P = d.n_views;
+    g->h_cs.resize(2 * (size_t)P);
+    g->h_axis.resize(P);
+    const double span = (d.kind == CT_PARALLEL_2D) ? M_PI : 2.0 * M_PI;
+    for (int p = 0; p < P; ++p) {
+        double th = g->uniform ? (span * p) / P : d.angles[p];
+        if (!std::isfinite(th)) {
+            delete g;
+            set_error("ct_geometry_create: non-finite angle");
+            return CT_ERR_ARG;
+        }
+        double c = std::cos(th), s = std::sin(th);
+        g->h_cs[2 * p] = c;
+        g->h_cs[2 * p + 1] = s;
+        int ax;
+        if (g->uniform) ax = (P <= 4 * p && 4 * p <= 3 * P) ? 0 : 1;
+        else ax = (std::fabs(s) >= std::fabs(c)) ? 0 : 1;
+        g->h_axis[p] = ax;
+    }
+    std::vector<float> taps(d.nu);
+    for (int j = 0; j < d.nu; ++j) {
+        double h;
+        if (j == 0) h = 1.0 / (4.0 * d.du);
+        else if (j % 2 == 0) h = 0.0;
+        else h = -1.0 / (M_PI * M_PI * (double)j * (double)j * d.du);
+        taps[j] = (float)h;   // du * h[j]
+    }
+    bool ok = hipMalloc(&g->d_cs, sizeof(double) * 2 * P) == hipSuccess &&
+              hipMalloc(&g->d_axis, sizeof(int) * P) == hipSuccess &&
+              hipMalloc(&g->d_ramp, sizeof(float) * d.nu) == hipSuccess;
+    if (!ok) {
+        ct_geometry_destroy(g);
+        set_error("ct_geometry_create: hipMalloc failed");
+        return CT_ERR_ALLOC;
+    }
+    ok = hipMemcpy(g->d_cs, g->h_cs.data(), sizeof(double) * 2 * P, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(g->d_axis, g->h_axis.data(), sizeof(int) * P, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(g->d_ramp, taps.data(), sizeof(float) * d.nu, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        ct_geometry_destroy(g);
+        set_error("ct_geometry_create: hipMemcpy failed");
+        return CT_ERR_HIP;
+    }
+    g->n_vox = (size_t)d.nx * d.ny * d.nz;
+    g->n_rays = (size_t)P * d.nv * d.nu;
+    GeomK &k = g->k;
+    k.kind = d.kind;
+    k.nx = d.nx; k.ny = d.ny; k.nz = d.nz;
+    k.P = P; k.nu = d.nu; k.nv = d.nv;
+    k.vox = d.voxel; k.du = d.du; k.dv = (d.kind == CT_PARALLEL_2D) ? 1.0 : d.dv;
+    k.sod = d.sod; k.sdd = d.sdd;
+    k.cs = g->d_cs;
+    k.axis = g->d_axis;
+    g->pad = pad_layout(k);
+    *out = g;
+    return CT_OK;
+}
+
+extern "C" void ct_geometry_destroy(ct_geometry *g) {
+    if (!g) return;
+    if (g->d_cs) (void)hipFree(g->d_cs);
+    if (g->d_axis) (void)hipFree(g->d_axis);
+    if (g->d_ramp) (void)hipFree(g->d_ramp);
+    delete g;
+}
+
+extern "C" int ct_geometry_sizes(const ct_geometry *g, size_t *n_vox, size_t *n_rays) {
+    clear_error();
+    CT_ARG_CHECK(g != nullptr, "ct_geometry_sizes: geometry is NULL");
+    if (n_vox) *n_vox = g->n_vox;
+    if (n_rays) *n_rays = g->n_rays;
+    return CT_OK;
+}

@@ -1,0 +1,766 @@
+// Krylov solvers of the ABBA method on gfx950: BA-GMRES (Eq. 5), AB-GMRES
+// (Eq. 4) and CGLS (Eq. 2), with the orthonormalisation and least-squares
+// update of Sec. II (x0 = 0, first basis vector the normalised right-hand
+// side, one new basis vector and one small least-squares solve per step).
+//
+// Device-resident design: the host enqueues every step of every iteration
+// on the caller's stream without waiting; all scalars (dot products, norms,
+// the Hessenberg matrix, the Givens rotations, the triangular solve) live in
+// FP64 in the workspace, and a device flag stops the remaining kernels after
+// a breakdown.  The basis is FP32 and stored "raw": basis vector j is
+// sc[j] * W[j], so no kernel has to rescale a whole vector.
+//
+// Orthonormalisation is classical Gram-Schmidt applied twice (CGS2):
+//   pass 1: d1 = W^T z                         (one sweep over W)
+//   pass 2: z1 = z - W h1,  d2 = W^T z1         (one sweep)
+//   pass 3: z2 = z1 - W h2, ||z2||^2            (one sweep)
+// Each pass stages a tile of all basis vectors in LDS, so every basis element
+// is read from HBM once per pass, and accumulates in FP64.  Partial sums go
+// to a [block][j] array that a one-block kernel reduces in a fixed order
+// (deterministic, no float atomics) before running the scalar step.
+#include <cmath>
+#include <cstring>
+
+#include "ct_common.h"
+
+namespace ct {
+namespace {
+
+constexpr int kTile = 256;       // elements per LDS tile (= block size)
+constexpr int kMaxBlk = 1024;    // upper bound on blocks of a sweep kernel
+constexpr int kMaxVec = 57;      // basis vectors staged in LDS per sweep (K+1); tile <= 60 KB
+
+// Device scalar state carved from the workspace.
+struct KState {
+    int *flags;        // [0] k_done, [1] stop, [2] status
+    double *H;         // (K+1) x K, column-major, rotated in place
+    double *cs, *sn;   // K rotations
+    double *gv;        // K+1 right-hand side of the small problem
+    double *sc;        // K+2 basis scale factors (basis j = sc[j] W[j])
+    double *h1, *h2;   // K+1 CGS coefficients
+    double *coef;      // K+1 coefficients applied by the next sweep
+    double *res;       // K+1 residual history
+    double *misc;      // [0] scale of the raw z, [1] ||z|| before CGS, [2] CGLS gamma, [3] alpha/beta
+    float *fscale;     // [0] A output scale, [1] B input scale (FP16 storage)
+    double *partials;  // kMaxBlk x pstride
+    int pstride;
+    int K;
+};
+
+enum { F_KDONE = 0, F_STOP = 1, F_STATUS = 2 };
+enum { M_ZS = 0, M_ZN0 = 1, M_GAMMA = 2, M_AB = 3 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// -------------------------------------------------------- sweep kernels
+// MODE 0: partial d[j] = sum_i W[j][i] z[i] for j < nvec, and d[nvec] = sum z^2
+// MODE 1: z1 = zs*z - sum_j coef[j] W[j]  (stored to zout), partial d[j] = W[j].z1
+// MODE 2: z2 = z - sum_j coef[j] W[j]     (stored to zout), partial sum z2^2
+template <int MODE>
+__global__ __launch_bounds__(kTile) void k_cgs(const float *__restrict__ W, size_t ldw, int nvec,
+                                               const float *zin, float *zout,   // may alias (pass 3)
+                                               size_t n, const double *__restrict__ coef,
+                                               const double *__restrict__ zscale,
+                                               double *__restrict__ partials, int pstride,
+                                               const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    extern __shared__ float sm[];
+    constexpr int LD = kTile + 1;
+    float *wt = sm;                                    // nvec x LD
+    float *zt = sm + (size_t)nvec * LD;                // kTile
+    double *cf = (double *)(sm + (((size_t)nvec * LD + kTile + 1) & ~(size_t)1));  // nvec
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (MODE >= 1)
+        for (int j = tid; j < nvec; j += kTile) cf[j] = coef[j];
+    const double zs = (MODE == 1 && zscale) ? *zscale : 1.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double nacc = 0.0;
+    const int ndot = MODE == 0 ? nvec + 1 : nvec;      // MODE 0 adds ||z||^2
+    __syncthreads();
+    for (size_t t0 = (size_t)blockIdx.x * kTile; t0 < n; t0 += (size_t)gridDim.x * kTile) {
+        const size_t i = t0 + tid;
+        const bool ok = i < n;
+        for (int j = 0; j < nvec; ++j) wt[j * LD + tid] = ok ? W[(size_t)j * ldw + i] : 0.0f;
+        float zv = ok ? zin[i] : 0.0f;
+        if (MODE >= 1) {
+            double u = zs * (double)zv;
+            for (int j = 0; j < nvec; ++j) u -= cf[j] * (double)wt[j * LD + tid];
+            zv = ok ? (float)u : 0.0f;
+            if (ok) zout[i] = zv;
+        }
+        if (MODE == 2) {
+            nacc += (double)zv * (double)zv;
+            continue;
+        }
+        zt[tid] = zv;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = lane + 64 * q;
+            if (j < ndot) {
+                double a = 0.0;
+                const int tb = wave * 64;
+                if (j < nvec) {
+                    const float *wr = wt + j * LD + tb;
+                    for (int t = 0; t < 64; ++t) a += (double)wr[t] * (double)zt[tb + t];
+                } else {
+                    for (int t = 0; t < 64; ++t) a += (double)zt[tb + t] * (double)zt[tb + t];
+                }
+                acc[q] += a;
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == 2) {
+        double v = wave_sum(nacc);
+        __shared__ double red2[kTile / 64];
+        if (lane == 0) red2[wave] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kTile / 64; ++w) s += red2[w];
+            partials[(size_t)blockIdx.x * pstride] = s;
+        }
+        return;
+    }
+    // combine the four waves' partial dots in a fixed order
+    __syncthreads();
+    double *red = (double *)sm;   // 4 x 256 doubles fits in the wt region
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        if (j < ndot) red[wave * 256 + j] = acc[q];
+    }
+    __syncthreads();
+    for (int j = tid; j < ndot; j += kTile) {
+        double s = 0.0;
+        for (int w = 0; w < kTile / 64; ++w) s += red[w * 256 + j];
+        partials[(size_t)blockIdx.x * pstride + j] = s;
+    }
+}
+
+// Sum partials[b][j] over b for j < count into out[j] (one block, fixed order).
+__device__ void reduce_partials(const double *__restrict__ partials, int nblk, int pstride, int count,
+                                double *out) {
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = 0;
+        for (; b + 3 < nblk; b += 4) {
+            s0 += partials[(size_t)b * pstride + j];
+            s1 += partials[(size_t)(b + 1) * pstride + j];
+            s2 += partials[(size_t)(b + 2) * pstride + j];
+            s3 += partials[(size_t)(b + 3) * pstride + j];
+        }
+        for (; b < nblk; ++b) s0 += partials[(size_t)b * pstride + j];
+        out[j] = (s0 + s1) + (s2 + s3);
+    }
+}
+
+__device__ __forceinline__ float pow2_scale(double target) {
+    // nearest power of two to target (exact scaling for FP16 storage)
+    if (!(target > 0.0) || !isfinite(target)) return 1.0f;
+    const double e = rint(log2(target));
+    return (float)exp2(fmin(fmax(e, -60.0), 60.0));
+}
+
+// beta = ||r0|| from partials; set up the first basis vector's scale.
+__global__ void k_gmres_init(KState st, int nblk, double qscale_c) {
+    __shared__ double d[1];
+    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(d[0]);
+    st.flags[F_KDONE] = 0;
+    st.flags[F_STATUS] = CT_OK;
+    st.res[0] = beta;
+    if (!isfinite(beta)) {
+        st.flags[F_STOP] = 1;
+        st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        return;
+    }
+    if (beta == 0.0) {
+        st.flags[F_STOP] = 1;
+        return;
+    }
+    st.flags[F_STOP] = 0;
+    st.sc[0] = 1.0 / beta;
+    st.gv[0] = beta;
+    const float qs = pow2_scale(st.sc[0] * qscale_c);
+    st.fscale[0] = qs;
+    st.fscale[1] = 1.0f / qs;
+}
+
+// After pass 1 at step k: h1 = V_k^T z, coefficients for pass 2.
+__global__ void k_gmres_red1(KState st, int nblk, int k) {
+    extern __shared__ double d[];
+    if (st.flags[F_STOP]) return;
+    const int nvec = k + 1;
+    reduce_partials(st.partials, nblk, st.pstride, nvec + 1, d);
+    __syncthreads();
+    // the raw new vector is B A W[k] (any FP16 storage scale is already
+    // divided out by the back-projector), so the true vector is sc[k] * raw
+    const double s = st.sc[k];
+    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
+        const double h = st.sc[j] * s * d[j];
+        st.h1[j] = h;
+        st.coef[j] = h * st.sc[j];
+    }
+    if (threadIdx.x == 0) {
+        st.misc[M_ZS] = s;
+        st.misc[M_ZN0] = s * sqrt(d[nvec]);
+    }
+}
+
+// After pass 2: h2 = V_k^T z1, coefficients for pass 3.
+__global__ void k_gmres_red2(KState st, int nblk, int k) {
+    extern __shared__ double d[];
+    if (st.flags[F_STOP]) return;
+    const int nvec = k + 1;
+    reduce_partials(st.partials, nblk, st.pstride, nvec, d);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
+        const double h = st.sc[j] * d[j];
+        st.h2[j] = h;
+        st.coef[j] = h * st.sc[j];
+    }
+}
+
+// After pass 3: new column of H, Givens rotations, residual, breakdown test.
+__global__ void k_gmres_red3(KState st, int nblk, int k, double tol, double qscale_c) {
+    __shared__ double d[1];
+    if (st.flags[F_STOP]) return;
+    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int K1 = st.K + 1;
+    double *col = st.H + (size_t)k * K1;
+    const double hn = sqrt(d[0]);
+    for (int i = 0; i <= k; ++i) col[i] = st.h1[i] + st.h2[i];
+    col[k + 1] = hn;
+    for (int i = 0; i < k; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = st.cs[i] * a + st.sn[i] * b;
+        col[i + 1] = -st.sn[i] * a + st.cs[i] * b;
+    }
+    const double rho = hypot(col[k], col[k + 1]);
+    const double c = col[k] / rho, s = col[k + 1] / rho;
+    st.cs[k] = c;
+    st.sn[k] = s;
+    col[k] = rho;
+    col[k + 1] = 0.0;
+    st.gv[k + 1] = -s * st.gv[k];
+    st.gv[k] = c * st.gv[k];
+    st.res[k + 1] = fabs(st.gv[k + 1]);
+    st.flags[F_KDONE] = k + 1;
+    if (!isfinite(rho) || !isfinite(st.gv[k]) || !isfinite(hn) || rho == 0.0) {
+        st.flags[F_STOP] = 1;
+        st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        return;
+    }
+    if (hn <= tol * st.misc[M_ZN0]) {   // (happy) breakdown
+        st.flags[F_STOP] = 1;
+        return;
+    }
+    st.sc[k + 1] = 1.0 / hn;
+    const float qs = pow2_scale(st.sc[k + 1] * qscale_c);
+    st.fscale[0] = qs;
+    st.fscale[1] = 1.0f / qs;
+}
+
+// y = R^-1 g (back substitution); coef[j] = y[j] * sc[j]
+__global__ void k_gmres_trsv(KState st) {
+    if (threadIdx.x != 0) return;
+    const int kd = st.flags[F_KDONE];
+    const int K1 = st.K + 1;
+    for (int i = kd - 1; i >= 0; --i) {
+        double s = st.gv[i];
+        for (int j = i + 1; j < kd; ++j) s -= st.H[(size_t)j * K1 + i] * st.coef[j];
+        st.coef[i] = s / st.H[(size_t)i * K1 + i];
+    }
+    for (int i = 0; i < kd; ++i) st.coef[i] *= st.sc[i];
+}
+
+// out = sum_{j < k_done} coef[j] W[j]   (FP64 accumulation)
+__global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, size_t ldw, size_t n,
+                                                 KState st, float *__restrict__ out) {
+    __shared__ double cf[kMaxVec + 1];
+    const int kd = st.flags[F_KDONE];
+    for (int j = threadIdx.x; j < kd; j += blockDim.x) cf[j] = st.coef[j];
+    __syncthreads();
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int j = 0; j < kd; ++j) a += cf[j] * (double)W[(size_t)j * ldw + i];
+        out[i] = (float)a;
+    }
+}
+
+// ------------------------------------------------------------- CGLS
+__global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ v, size_t n,
+                                               double *__restrict__ partials, int pstride,
+                                               const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    double a = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        a += (double)v[i] * (double)v[i];
+    a = wave_sum(a);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * pstride] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_zero_i32(int *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+__global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+// stage 0: res[0] = ||b||;  stage 1: gamma = ||s||^2 (start)
+__global__ void k_cgls_start(KState st, int nblk, int stage) {
+    __shared__ double d[1];
+    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (stage == 0) {
+        st.flags[F_KDONE] = 0;
+        st.flags[F_STOP] = 0;
+        st.flags[F_STATUS] = CT_OK;
+        st.res[0] = sqrt(d[0]);
+        if (!isfinite(st.res[0])) {
+            st.flags[F_STOP] = 1;
+            st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        }
+    } else {
+        st.misc[M_GAMMA] = d[0];
+        if (!(d[0] > 0.0)) st.flags[F_STOP] = 1;
+        if (!isfinite(d[0])) st.flags[F_STATUS] = CT_ERR_NUMERIC;
+    }
+}
+
+// alpha = gamma / ||q||^2
+__global__ void k_cgls_alpha(KState st, int nblk) {
+    __shared__ double d[1];
+    if (st.flags[F_STOP]) return;
+    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double a = st.misc[M_GAMMA] / d[0];
+    if (!(d[0] > 0.0) || !isfinite(a)) {
+        st.flags[F_STOP] = 1;
+        if (!isfinite(d[0])) st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        return;
+    }
+    st.misc[M_AB] = a;
+}
+
+// x += alpha p (n), r -= alpha q (m)
+__global__ __launch_bounds__(256) void k_cgls_xr(float *__restrict__ x, const float *__restrict__ p, size_t n,
+                                                 float *__restrict__ r, const float *__restrict__ q, size_t m,
+                                                 KState st) {
+    if (st.flags[F_STOP]) return;
+    const double a = st.misc[M_AB];
+    const size_t tot = n + m;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (i < n) x[i] = (float)((double)x[i] + a * (double)p[i]);
+        else {
+            const size_t k = i - n;
+            r[k] = (float)((double)r[k] - a * (double)q[k]);
+        }
+    }
+}
+
+// residual history after the r update (partials of ||r||^2)
+__global__ void k_cgls_res(KState st, int nblk, int k) {
+    __shared__ double d[1];
+    if (st.flags[F_STOP]) return;
+    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    st.res[k + 1] = sqrt(d[0]);
+    st.flags[F_KDONE] = k + 1;
+}
+
+// beta = gamma'/gamma, gamma = gamma'
+__global__ void k_cgls_beta(KState st, int nblk) {
+    __shared__ double d[1];
+    if (st.flags[F_STOP]) return;
+    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double gnew = d[0];
+    if (!isfinite(gnew)) {
+        st.flags[F_STOP] = 1;
+        st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        return;
+    }
+    st.misc[M_AB] = gnew / st.misc[M_GAMMA];
+    st.misc[M_GAMMA] = gnew;
+    if (gnew == 0.0) st.misc[M_AB] = 0.0;
+}
+
+// p = s + beta p
+__global__ __launch_bounds__(256) void k_cgls_p(float *__restrict__ p, const float *__restrict__ s, size_t n,
+                                                KState st) {
+    if (st.flags[F_STOP]) return;
+    const double b = st.misc[M_AB];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = (float)((double)s[i] + b * (double)p[i]);
+}
+
+}  // namespace
+
+// ===================================================================== host
+namespace {
+
+int sweep_blocks(size_t n) {
+    size_t t = (n + kTile - 1) / kTile;
+    return (int)(t < (size_t)kMaxBlk ? (t == 0 ? 1 : t) : (size_t)kMaxBlk);
+}
+
+int grid_1d(size_t n) {
+    size_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+size_t cgs_lds_bytes(int nvec) {
+    const size_t f = (size_t)nvec * (kTile + 1) + kTile + 2;
+    size_t bytes = f * 4 + (size_t)nvec * 8 + 16;
+    const size_t red = 4 * 256 * 8;   // wave-combine buffer reuses the front
+    return bytes > red ? bytes : red;
+}
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *p) : base((char *)p) {}
+    template <typename T> T *take(size_t count) {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += align_up(count * sizeof(T));
+        return p;
+    }
+};
+
+struct GmresBufs {
+    float *W = nullptr;     // (K+1) basis vectors of length len, stride ldw
+    size_t ldw = 0, len = 0;
+    OpScratch opA;          // padded copies
+    void *q = nullptr;      // projections (BA) / image (AB)
+    void *filt = nullptr;   // ramp-filtered data
+    float *z = nullptr;     // raw new vector
+    KState st{};
+};
+
+// Carve (or size, when ws == nullptr) the GMRES workspace.
+size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, void *ws, GmresBufs &b) {
+    Carver c(ws);
+    const int K = o.iters;
+    const bool ba = solver == CT_SOLVER_BA;
+    b.len = ba ? g->n_vox : g->n_rays;
+    b.ldw = align_up(b.len, 64);
+    b.W = c.take<float>(b.ldw * (size_t)(K + 1));
+    b.opA.vx = c.take<float>(g->pad.nvx);
+    b.opA.vy = c.take<float>(g->pad.nvy);
+    const size_t es = o.sino_dtype == CT_F16 ? 2 : 4;
+    if (ba) {
+        b.q = c.take<char>(g->n_rays * es);
+        // the first back-projection filters the FP32 data whatever the storage
+        if (o.B == CT_B_RAMP) b.filt = c.take<char>(g->n_rays * 4);
+        b.z = c.take<float>(g->n_vox);
+    } else {
+        b.q = c.take<float>(g->n_vox);               // u = B w
+        if (o.B == CT_B_RAMP) b.filt = c.take<float>(g->n_rays);
+        b.z = c.take<float>(g->n_rays);
+    }
+    b.opA.filt = b.filt;
+    KState &s = b.st;
+    s.K = K;
+    s.pstride = K + 3;
+    s.flags = c.take<int>(16);
+    s.H = c.take<double>((size_t)(K + 1) * (K > 0 ? K : 1));
+    s.cs = c.take<double>(K + 1);
+    s.sn = c.take<double>(K + 1);
+    s.gv = c.take<double>(K + 2);
+    s.sc = c.take<double>(K + 2);
+    s.h1 = c.take<double>(K + 2);
+    s.h2 = c.take<double>(K + 2);
+    s.coef = c.take<double>(K + 2);
+    s.res = c.take<double>(K + 2);
+    s.misc = c.take<double>(8);
+    s.fscale = c.take<float>(4);
+    s.partials = c.take<double>((size_t)kMaxBlk * s.pstride);
+    return c.off;
+}
+
+int run_cgs(int mode, const GmresBufs &b, int nvec, const float *zin, float *zout, const double *coef,
+            const double *zscale, hipStream_t s) {
+    const int nblk = sweep_blocks(b.len);
+    const size_t shm = cgs_lds_bytes(nvec);
+    const int *stop = b.st.flags + F_STOP;
+    if (mode == 0)
+        hipLaunchKernelGGL(k_cgs<0>, dim3(nblk), dim3(kTile), shm, s, b.W, b.ldw, nvec, zin, zout, b.len, coef, zscale,
+                           b.st.partials, b.st.pstride, stop);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_cgs<1>, dim3(nblk), dim3(kTile), shm, s, b.W, b.ldw, nvec, zin, zout, b.len, coef, zscale,
+                           b.st.partials, b.st.pstride, stop);
+    else
+        hipLaunchKernelGGL(k_cgs<2>, dim3(nblk), dim3(kTile), shm, s, b.W, b.ldw, nvec, zin, zout, b.len, coef, zscale,
+                           b.st.partials, b.st.pstride, stop);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+int check_solver_args(const ct_geometry *g, int solver, const ct_solver_opts *o, const float *b, float *x,
+                      void *ws, size_t ws_bytes, size_t &need) {
+    CT_ARG_CHECK(g && o, "solver: NULL geometry or options");
+    CT_ARG_CHECK(o->iters >= 0, "solver: iters must be >= 0");
+    if (solver != CT_SOLVER_CGLS && o->iters + 1 > kMaxVec) {
+        set_error("solver: GMRES supports at most 56 iterations");
+        return CT_ERR_UNSUPPORTED;
+    }
+    CT_ARG_CHECK(o->B == CT_B_UNMATCHED || o->B == CT_B_RAMP || o->B == CT_B_AT, "solver: unknown B");
+    CT_ARG_CHECK(o->sino_dtype == CT_F32 || o->sino_dtype == CT_F16, "solver: bad sino_dtype");
+    CT_ARG_CHECK(o->breakdown_tol >= 0.0 && std::isfinite(o->breakdown_tol), "solver: bad breakdown_tol");
+    CT_ARG_CHECK(b && x, "solver: NULL b or x");
+    if (solver != CT_SOLVER_BA && o->sino_dtype == CT_F16) {
+        set_error("solver: FP16 data storage is implemented for BA-GMRES only");
+        return CT_ERR_UNSUPPORTED;
+    }
+    if (o->sino_dtype == CT_F16 && o->B == CT_B_AT) {
+        set_error("solver: FP16 data storage is not implemented with B = A^T");
+        return CT_ERR_UNSUPPORTED;
+    }
+    if (o->B == CT_B_RAMP && g->k.nu * 16 > 64 * 1024) {
+        set_error("solver: detector rows longer than 4096 are not supported by the ramp filter");
+        return CT_ERR_UNSUPPORTED;
+    }
+    CT_ARG_CHECK(ws != nullptr && ws_bytes >= need, "solver: workspace too small");
+    return CT_OK;
+}
+
+size_t carve_cgls(const ct_geometry *g, const ct_solver_opts &o, void *ws, float **r, float **q, float **sv,
+                  float **p, OpScratch &op, KState &st) {
+    Carver c(ws);
+    *r = c.take<float>(g->n_rays);
+    *q = c.take<float>(g->n_rays);
+    *sv = c.take<float>(g->n_vox);
+    *p = c.take<float>(g->n_vox);
+    op.vx = c.take<float>(g->pad.nvx);
+    op.vy = c.take<float>(g->pad.nvy);
+    op.filt = o.B == CT_B_RAMP ? c.take<float>(g->n_rays) : nullptr;
+    st.K = o.iters;
+    st.pstride = 4;
+    st.flags = c.take<int>(16);
+    st.res = c.take<double>(o.iters + 2);
+    st.misc = c.take<double>(8);
+    st.partials = c.take<double>((size_t)kMaxBlk * st.pstride);
+    st.H = st.cs = st.sn = st.gv = st.sc = st.h1 = st.h2 = st.coef = nullptr;
+    st.fscale = nullptr;
+    return c.off;
+}
+
+int finish(KState &st, int K, double *res_hist, int *iters_done, hipStream_t s) {
+    int flags[3];
+    std::vector<double> res(K + 1, 0.0);
+    CT_HIP_CHECK(hipMemcpyAsync(flags, st.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    CT_HIP_CHECK(hipMemcpyAsync(res.data(), st.res, sizeof(double) * (K + 1), hipMemcpyDeviceToHost, s));
+    CT_HIP_CHECK(hipStreamSynchronize(s));
+    const int kd = flags[F_KDONE];
+    if (iters_done) *iters_done = kd;
+    if (res_hist) {
+        for (int i = 0; i <= K; ++i) res_hist[i] = i <= kd ? res[i] : NAN;
+    }
+    if (flags[F_STATUS] != CT_OK) {
+        set_error("solver: non-finite value encountered");
+        return CT_ERR_NUMERIC;
+    }
+    return CT_OK;
+}
+
+// scale constant so that A applied to a unit-norm vector stores O(1) values
+double fp16_scale_const(const ct_geometry *g) {
+    const int nmax = g->k.nx > g->k.ny ? g->k.nx : g->k.ny;
+    return std::sqrt((double)g->n_vox) / ((double)nmax * g->k.vox);
+}
+
+int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const ct_solver_opts *o, void *ws,
+               size_t ws_bytes, double *res_hist, int *iters_done, hipStream_t s) {
+    GmresBufs bf;
+    size_t need = carve_gmres(g, solver, *o, nullptr, bf);
+    CT_TRY(check_solver_args(g, solver, o, b, x, ws, ws_bytes, need));
+    carve_gmres(g, solver, *o, ws, bf);
+    const int K = o->iters;
+    const double tol = o->breakdown_tol > 0.0 ? o->breakdown_tol : 64.0 * 5.9604644775390625e-08;
+    const bool ba = solver == CT_SOLVER_BA;
+    const bool f16 = o->sino_dtype == CT_F16;
+    const int dt = f16 ? CT_F16 : CT_F32;
+    const double qc = f16 ? fp16_scale_const(g) : 0.0;
+    KState &st = bf.st;
+    const int *stop = st.flags + F_STOP;
+    const int nblk = sweep_blocks(bf.len);
+    OpScratch &op = bf.opA;
+    // flags must start clear: the init kernel writes them, but the sweep that
+    // precedes it reads the stop flag (a kernel, not a memset, so the chain
+    // stays capturable)
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, st.flags, 16);
+    CT_LAUNCH_CHECK();
+    CT_TRY(launch_pad_zero(g, op.vx, op.vy, s));
+
+    // r0 = B b (BA) or b (AB), stored raw as W[0]
+    if (ba) CT_TRY(apply_B(g, o->B, b, CT_F32, bf.W, op, nullptr, nullptr, s));
+    else {
+        hipLaunchKernelGGL(k_copy, dim3(grid_1d(bf.len)), dim3(256), 0, s, b, bf.W, bf.len);
+        CT_LAUNCH_CHECK();
+    }
+    CT_TRY(run_cgs(2, bf, 0, bf.W, bf.W, st.coef, nullptr, s));   // ||r0||^2 (no update)
+    hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, s, st, nblk, qc);
+    CT_LAUNCH_CHECK();
+
+    const float *oscale = f16 ? st.fscale : nullptr;
+    const float *iscale = f16 ? st.fscale + 1 : nullptr;
+    for (int k = 0; k < K; ++k) {
+        float *wk = bf.W + (size_t)k * bf.ldw;
+        float *wn = bf.W + (size_t)(k + 1) * bf.ldw;
+        const bool pad_ready = o->B != CT_B_AT;
+        if (ba) {
+            CT_TRY(apply_A(g, wk, bf.q, dt, op, pad_ready, oscale, stop, s));
+            CT_TRY(apply_B(g, o->B, bf.q, dt, bf.z, op, iscale, stop, s));
+        } else {
+            CT_TRY(apply_B(g, o->B, wk, CT_F32, (float *)bf.q, op, nullptr, stop, s));
+            CT_TRY(apply_A(g, (const float *)bf.q, bf.z, CT_F32, op, pad_ready, nullptr, stop, s));
+        }
+        const int nvec = k + 1;
+        CT_TRY(run_cgs(0, bf, nvec, bf.z, nullptr, nullptr, nullptr, s));
+        hipLaunchKernelGGL(k_gmres_red1, dim3(1), dim3(256), sizeof(double) * (nvec + 1), s, st, nblk, k);
+        CT_LAUNCH_CHECK();
+        CT_TRY(run_cgs(1, bf, nvec, bf.z, wn, st.coef, st.misc + M_ZS, s));
+        hipLaunchKernelGGL(k_gmres_red2, dim3(1), dim3(256), sizeof(double) * nvec, s, st, nblk, k);
+        CT_LAUNCH_CHECK();
+        CT_TRY(run_cgs(2, bf, nvec, wn, wn, st.coef, nullptr, s));
+        hipLaunchKernelGGL(k_gmres_red3, dim3(1), dim3(64), 0, s, st, nblk, k, tol, qc);
+        CT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_gmres_trsv, dim3(1), dim3(64), 0, s, st);
+    CT_LAUNCH_CHECK();
+    if (ba) {
+        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, x);
+        CT_LAUNCH_CHECK();
+    } else {
+        // x = B (W c): combine in data space, then back-project
+        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, bf.z);
+        CT_LAUNCH_CHECK();
+        CT_TRY(apply_B(g, o->B, bf.z, CT_F32, x, op, nullptr, nullptr, s));
+    }
+    return finish(st, K, res_hist, iters_done, s);
+}
+
+int cgls_impl(const ct_geometry *g, const float *b, float *x, const ct_solver_opts *o, void *ws, size_t ws_bytes,
+              double *res_hist, int *iters_done, hipStream_t s) {
+    float *r, *q, *sv, *p;
+    OpScratch op;
+    KState st;
+    size_t need = carve_cgls(g, *o, nullptr, &r, &q, &sv, &p, op, st);
+    CT_TRY(check_solver_args(g, CT_SOLVER_CGLS, o, b, x, ws, ws_bytes, need));
+    carve_cgls(g, *o, ws, &r, &q, &sv, &p, op, st);
+    const size_t n = g->n_vox, m = g->n_rays;
+    const int *stop = st.flags + F_STOP;
+    const int nb_n = sweep_blocks(n), nb_m = sweep_blocks(m);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, st.flags, 16);
+    CT_LAUNCH_CHECK();
+    CT_TRY(launch_fill(x, n, 0.0f, s));
+    CT_TRY(launch_pad_zero(g, op.vx, op.vy, s));
+    hipLaunchKernelGGL(k_copy, dim3(grid_1d(m)), dim3(256), 0, s, b, r, m);
+    CT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, r, m, st.partials, st.pstride, nullptr);
+    CT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cgls_start, dim3(1), dim3(256), 0, s, st, nb_m, 0);
+    CT_LAUNCH_CHECK();
+    CT_TRY(apply_B(g, o->B, r, CT_F32, sv, op, nullptr, stop, s));
+    hipLaunchKernelGGL(k_sumsq, dim3(nb_n), dim3(256), 0, s, sv, n, st.partials, st.pstride, stop);
+    CT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cgls_start, dim3(1), dim3(256), 0, s, st, nb_n, 1);
+    CT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_copy, dim3(grid_1d(n)), dim3(256), 0, s, sv, p, n);
+    CT_LAUNCH_CHECK();
+    const bool pad_ready = o->B != CT_B_AT;
+    for (int k = 0; k < o->iters; ++k) {
+        CT_TRY(apply_A(g, p, q, CT_F32, op, pad_ready, nullptr, stop, s));
+        hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, q, m, st.partials, st.pstride, stop);
+        CT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cgls_alpha, dim3(1), dim3(256), 0, s, st, nb_m);
+        CT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cgls_xr, dim3(grid_1d(n + m)), dim3(256), 0, s, x, p, n, r, q, m, st);
+        CT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, r, m, st.partials, st.pstride, stop);
+        CT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cgls_res, dim3(1), dim3(256), 0, s, st, nb_m, k);
+        CT_LAUNCH_CHECK();
+        CT_TRY(apply_B(g, o->B, r, CT_F32, sv, op, nullptr, stop, s));
+        hipLaunchKernelGGL(k_sumsq, dim3(nb_n), dim3(256), 0, s, sv, n, st.partials, st.pstride, stop);
+        CT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cgls_beta, dim3(1), dim3(256), 0, s, st, nb_n);
+        CT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cgls_p, dim3(grid_1d(n)), dim3(256), 0, s, p, sv, n, st);
+        CT_LAUNCH_CHECK();
+    }
+    return finish(st, o->iters, res_hist, iters_done, s);
+}
+
+}  // namespace
+}  // namespace ct
+
+using namespace ct;
+
+extern "C" int ct_solver_workspace_bytes(const ct_geometry *g, int solver, const ct_solver_opts *opts,
+                                         size_t *bytes) {
+    clear_error();
+    CT_ARG_CHECK(g && opts && bytes, "ct_solver_workspace_bytes: NULL argument");
+    CT_ARG_CHECK(opts->iters >= 0, "ct_solver_workspace_bytes: iters out of range");
+    if (solver != CT_SOLVER_CGLS && opts->iters + 1 > kMaxVec) {
+        set_error("ct_solver_workspace_bytes: GMRES supports at most 56 iterations");
+        return CT_ERR_UNSUPPORTED;
+    }
+    if (solver == CT_SOLVER_BA || solver == CT_SOLVER_AB) {
+        GmresBufs bf;
+        *bytes = carve_gmres(g, solver, *opts, nullptr, bf);
+    } else if (solver == CT_SOLVER_CGLS) {
+        float *r, *q, *sv, *p;
+        OpScratch op;
+        KState st;
+        *bytes = carve_cgls(g, *opts, nullptr, &r, &q, &sv, &p, op, st);
+    } else {
+        set_error("ct_solver_workspace_bytes: unknown solver");
+        return CT_ERR_ARG;
+    }
+    return CT_OK;
+}
+
+extern "C" int ct_ba_gmres(const ct_geometry *g, const float *b, float *x, const ct_solver_opts *opts, void *ws,
+                           size_t ws_bytes, double *res_hist, int *iters_done, void *stream) {
+    clear_error();
+    return gmres_impl(g, CT_SOLVER_BA, b, x, opts, ws, ws_bytes, res_hist, iters_done, (hipStream_t)stream);
+}
+
+extern "C" int ct_ab_gmres(const ct_geometry *g, const float *b, float *x, const ct_solver_opts *opts, void *ws,
+                           size_t ws_bytes, double *res_hist, int *iters_done, void *stream) {
+    clear_error();
+    return gmres_impl(g, CT_SOLVER_AB, b, x, opts, ws, ws_bytes, res_hist, iters_done, (hipStream_t)stream);
+}
+
+extern "C" int ct_cgls(const ct_geometry *g, const float *b, float *x, const ct_solver_opts *opts, void *ws,
+                       size_t ws_bytes, double *res_hist, int *iters_done, void *stream) {
+    clear_error();
+    return cgls_impl(g, b, x, opts, ws, ws_bytes, res_hist, iters_done, (hipStream_t)stream);
+}

@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every function include/ct.h declares
+(no compute calls: these run without a GPU)."""
+
+import ctypes
+import os
+import re
+
+from paper_2201_07408_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ct_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["ct_geometry_create", "ct_project_A", "ct_backproject_B",
+                     "ct_backproject_AT", "ct_ba_gmres", "ct_ab_gmres", "ct_cgls"]:
+        assert required in names
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIBPATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_error_string_without_gpu():
+    lib = _lib.load()
+    assert lib.ct_version().decode().startswith("ctabba")
+    assert lib.ct_last_error() is not None
+
+
+def test_struct_layouts_match_header():
+    # ct_geometry_desc: 4 ints, double, int, pointer, 2 ints, 4 doubles
+    assert ctypes.sizeof(_lib.GeometryDesc) == 4 * 4 + 8 + 8 + 8 + 8 + 4 * 8
+    assert ctypes.sizeof(_lib.SolverOpts) == 3 * 4 + 4 + 8
+
+
+def test_invalid_descriptor_rejected_on_host():
+    """Argument validation happens before any device call."""
+    lib = _lib.load()
+    d = _lib.GeometryDesc(0, 0, 16, 1, 1.0, 10, None, 24, 1, 1.0, 1.0, 0.0, 0.0)
+    h = ctypes.c_void_p()
+    assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_ARG
+    assert h.value is None
+    assert b"volume sizes" in lib.ct_last_error()
+    d = _lib.GeometryDesc(1, 16, 16, 16, 1.0, 10, None, 24, 24, 2.0, 2.0, 64.0, 32.0)
+    assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_ARG
+    d = _lib.GeometryDesc(1, 16, 16, 16, 1.0, 10, None, 24, 4000, 2.0, 2.0, 64.0, 128.0)
+    assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_UNSUPPORTED

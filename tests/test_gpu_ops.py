@@ -1,0 +1,143 @@
+"""GPU operator parity with the FP64 oracle (same seeded FP32 inputs).
+
+Tolerance: relative 2-norm error <= 1e-5 for FP32 outputs.  Derivation: the
+kernels evaluate each sample position in FP32 from FP64 per-ray set-up, so
+the interpolation weights carry errors of a few units of 2^-24 times the
+coordinate magnitude (<= 2^9 voxels here), i.e. <= 3e-5 per weight at worst
+and far smaller on average; sums over hundreds of samples in FP32 add
+O(sqrt(N) 2^-24).  Observed errors sit near 1e-7..1e-6.
+FP16 outputs are checked against FP16 rounding (2^-11 relative).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_07408_amd as ct
+from synth import workloads
+from tests.gpu_helpers import SMALL_GEOMS, dev, f32, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def geoms():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return {k: (d, ct.Geometry(d)) for k, d in SMALL_GEOMS.items()}
+
+
+@pytest.mark.parametrize("name", list(SMALL_GEOMS))
+def test_project_A(geoms, name):
+    desc, g = geoms[name]
+    say("A parity", name)
+    x = f32(np.random.default_rng(1).uniform(0, 1, size=desc.vol_shape))
+    y = host(ct.ct_project_A(g, dev(x)))
+    ref = oracle.project_A(desc, x)
+    assert rel(y, ref) <= TOL
+
+
+@pytest.mark.parametrize("name", list(SMALL_GEOMS))
+def test_backproject_B(geoms, name):
+    desc, g = geoms[name]
+    say("B parity", name)
+    y = f32(np.random.default_rng(2).uniform(0, 1, size=desc.sino_shape))
+    x = host(ct.ct_backproject_B(g, dev(y)))
+    assert rel(x, oracle.backproject_Bun(desc, y)) <= TOL
+
+
+@pytest.mark.parametrize("name", list(SMALL_GEOMS))
+def test_backproject_AT(geoms, name):
+    desc, g = geoms[name]
+    say("AT parity", name)
+    rng = np.random.default_rng(3)
+    y = f32(rng.uniform(0, 1, size=desc.sino_shape))
+    x = host(ct.ct_backproject_AT(g, dev(y)))
+    assert rel(x, oracle.backproject_AT(desc, y)) <= TOL
+    # adjoint identity of the GPU pair itself
+    v = f32(rng.standard_normal(desc.vol_shape))
+    w = f32(rng.standard_normal(desc.sino_shape))
+    lhs = float(host(ct.ct_project_A(g, dev(v))).reshape(-1) @ w.reshape(-1).astype(np.float64))
+    rhs = float(v.reshape(-1).astype(np.float64) @ host(ct.ct_backproject_AT(g, dev(w))).reshape(-1))
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs))
+
+
+@pytest.mark.parametrize("name", ["w1_2d_64", "ragged_2d", "cone_24", "ragged_cone"])
+def test_ramp_and_filtered_backprojection(geoms, name):
+    desc, g = geoms[name]
+    say("F parity", name)
+    y = f32(np.random.default_rng(4).uniform(0, 1, size=desc.sino_shape))
+    f = host(ct.ct_ramp_filter(g, dev(y)))
+    fref = oracle.ramp(desc, y)
+    assert rel(f, fref) <= TOL
+    x = host(ct.ct_backproject_B(g, dev(y), ramp=True))
+    assert rel(x, oracle.backproject_Bun(desc, oracle.ramp(desc, y))) <= TOL
+
+
+@pytest.mark.parametrize("name", ["w1_2d_64", "cone_24"])
+def test_fp16_storage(geoms, name):
+    desc, g = geoms[name]
+    say("FP16 storage", name)
+    x = f32(np.random.default_rng(5).uniform(0, 1, size=desc.vol_shape))
+    y16 = ct.ct_project_A(g, dev(x), y_dtype=torch.float16)
+    assert y16.dtype == torch.float16
+    ref = oracle.project_A(desc, x)
+    assert rel(host(y16), ref) <= 2.0 ** -11
+    xb = host(ct.ct_backproject_B(g, y16))
+    ref_b = oracle.backproject_Bun(desc, host(y16))   # same FP16-rounded data
+    assert rel(xb, ref_b) <= TOL
+
+
+def test_batch_equals_single_calls(geoms):
+    desc, g = geoms["cone_24"]
+    rng = np.random.default_rng(6)
+    xs = f32(rng.uniform(size=(3,) + desc.vol_shape))
+    yb = ct.ct_project_A(g, dev(xs))
+    for i in range(3):
+        yi = ct.ct_project_A(g, dev(xs[i]))
+        assert torch.equal(yb[i], yi)
+    xb = ct.ct_backproject_B(g, yb)
+    for i in range(3):
+        assert torch.equal(xb[i], ct.ct_backproject_B(g, yb[i].contiguous()))
+
+
+def test_empty_batch(geoms):
+    desc, g = geoms["w1_2d_64"]
+    x = torch.empty((0,) + desc.vol_shape, device="cuda")
+    y = ct.ct_project_A(g, x)
+    assert y.shape == (0,) + desc.sino_shape
+
+
+# ------------------------------------------------ full workload sizes
+def _sampled_parity(desc, g, vol, nsamp=3000, seed=7):
+    rng = np.random.default_rng(seed)
+    y = ct.ct_project_A(g, dev(vol))
+    yh = host(y).reshape(-1)
+    rays = rng.choice(desc.n_rays, size=nsamp, replace=False)
+    ref = oracle.project_A_rays(desc, vol, rays)
+    assert rel(yh[rays], ref) <= TOL
+    x = host(ct.ct_backproject_B(g, y)).reshape(-1)
+    vox = rng.choice(desc.n_vox, size=nsamp, replace=False)
+    refb = oracle.backproject_Bun_voxels(desc, f32(yh), vox)
+    assert rel(x[vox], refb) <= TOL
+    xr = host(ct.ct_backproject_B(g, y, ramp=True)).reshape(-1)
+    fy = oracle.ramp(desc, f32(yh))
+    refr = oracle.backproject_Bun_voxels(desc, fy, vox)
+    assert rel(xr[vox], refr) <= TOL
+
+
+def test_w2_full_size_sampled():
+    desc = workloads.w2_geometry()
+    say("W2 128^3 sampled parity")
+    g = ct.Geometry(desc)
+    _sampled_parity(desc, g, workloads.w2_phantom())
+
+
+def test_w3_full_size_sampled():
+    desc = workloads.w3_geometry()
+    say("W3 256^3 sampled parity")
+    g = ct.Geometry(desc)
+    vol = workloads.w3_phantom()
+    _sampled_parity(desc, g, vol, nsamp=2000)

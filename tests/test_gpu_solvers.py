@@ -1,0 +1,131 @@
+"""GPU solver parity with the FP64 oracle.
+
+Tolerance for reconstructions and residual histories at a fixed iteration
+count: relative 1e-4.  Derivation: the operators agree to ~1e-6 (see the
+operator tests); GMRES propagates operator perturbations through the
+Krylov space with a growth set by the conditioning of the small Hessenberg
+problem, which stays below 1e2 for k <= 50 on these workloads (measured);
+the FP32 basis adds orthogonality loss of order 1e-7 per vector.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_07408_amd as ct
+from synth import workloads
+from synth.phantoms import random_ellipsoids, rasterize_ellipsoids
+from synth.geometry import cone3d
+from tests.gpu_helpers import dev, f32, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def w1():
+    desc = workloads.w1_geometry()
+    x_true = workloads.w1_phantom()
+    clean = oracle.project_A(desc, x_true)
+    b = f32(clean + workloads.relative_gaussian_noise(clean, 0.01, 102))
+    return desc, ct.Geometry(desc), b
+
+
+@pytest.fixture(scope="module")
+def cone_small():
+    desc = cone3d(48, 60, 72)
+    ells = random_ellipsoids(211, 8, 48.0)
+    x_true = rasterize_ellipsoids(ells, 48, 1.0)
+    b = f32(oracle.project_A(desc, f32(x_true)))
+    return desc, ct.Geometry(desc), b
+
+
+def _compare(res_gpu, ref, x_tol=TOL):
+    assert res_gpu.iters_done == ref.iters_done
+    assert rel(host(res_gpu.x), ref.x) <= x_tol, rel(host(res_gpu.x), ref.x)
+    assert rel(np.array(res_gpu.res), np.array(ref.res)) <= TOL
+
+
+@pytest.mark.parametrize("B", ["un", "ramp", "AT"])
+def test_ba_gmres_w1(w1, B):
+    desc, g, b = w1
+    say("BA-GMRES W1", B)
+    r = ct.ct_ba_gmres(g, dev(b), 30, B=B)
+    _compare(r, oracle.ba_gmres(desc, b, 30, B=B))
+
+
+@pytest.mark.parametrize("B", ["un", "ramp"])
+def test_ab_gmres_w1(w1, B):
+    desc, g, b = w1
+    say("AB-GMRES W1", B)
+    r = ct.ct_ab_gmres(g, dev(b), 30, B=B)
+    _compare(r, oracle.ab_gmres(desc, b, 30, B=B))
+
+
+def test_cgls_AT_w1(w1):
+    desc, g, b = w1
+    say("CGLS(A^T) W1")
+    r = ct.ct_cgls(g, dev(b), 30, B="AT")
+    _compare(r, oracle.cgls(desc, b, 30, B="AT"))
+
+
+def test_cgls_unmatched_w1_reported(w1):
+    """CGLS with B_un has no convergence theory (parity unpinned in the
+    oracle); GPU-vs-oracle agreement is asserted for the first iterations
+    only, where perturbations have not been amplified."""
+    desc, g, b = w1
+    r = ct.ct_cgls(g, dev(b), 10, B="un")
+    _compare(r, oracle.cgls(desc, b, 10, B="un"))
+
+
+@pytest.mark.parametrize("B", ["un", "ramp"])
+def test_ba_gmres_cone_small(cone_small, B):
+    desc, g, b = cone_small
+    say("BA-GMRES cone 48^3", B)
+    r = ct.ct_ba_gmres(g, dev(b), 20, B=B)
+    _compare(r, oracle.ba_gmres(desc, b, 20, B=B))
+
+
+def test_ab_gmres_and_cgls_cone_small(cone_small):
+    desc, g, b = cone_small
+    say("AB-GMRES / CGLS cone 48^3")
+    _compare(ct.ct_ab_gmres(g, dev(b), 12, B="un"), oracle.ab_gmres(desc, b, 12, B="un"))
+    _compare(ct.ct_cgls(g, dev(b), 12, B="AT"), oracle.cgls(desc, b, 12, B="AT"))
+
+
+def test_ba_gmres_fp16_storage_w1(w1):
+    """FP16 storage of the projections: reported tolerance (FP16 unit
+    roundoff 4.9e-4), not held to the FP32 bound."""
+    desc, g, b = w1
+    r16 = ct.ct_ba_gmres(g, dev(b), 30, B="ramp", sino_dtype=torch.float16)
+    ref = oracle.ba_gmres(desc, b, 30, B="ramp")
+    e = rel(host(r16.x), ref.x)
+    say("FP16-storage BA-GMRES W1 rel err", e)
+    assert r16.iters_done == 30
+    assert e <= 2e-2
+
+
+def test_ba_gmres_full_w3_properties():
+    """Headline workload (256^3 cone beam, ramp-filtered B, K = 30), the
+    launch configuration the benchmark times.  The full FP64 solve is too
+    slow for the oracle, so properties that hold at any size are checked:
+    the residual history is non-increasing, its last entry equals the
+    recomputed ||B b - B A x_K|| (with the GPU operators), and the first
+    residual equals ||B b||."""
+    desc = workloads.w3_geometry()
+    say("W3 BA-GMRES properties")
+    g = ct.Geometry(desc)
+    vol = workloads.w3_phantom()
+    b = ct.ct_project_A(g, dev(vol))
+    r = ct.ct_ba_gmres(g, b.reshape(-1), 30, B="ramp")
+    assert r.iters_done == 30
+    res = np.array(r.res)
+    assert np.all(np.diff(res) <= 1e-6 * res[0])
+    Bb = ct.ct_backproject_B(g, b, ramp=True)
+    assert abs(float(torch.linalg.vector_norm(Bb.double())) - res[0]) <= 1e-5 * res[0]
+    Ax = ct.ct_project_A(g, r.x)
+    rr = Bb - ct.ct_backproject_B(g, Ax, ramp=True)
+    true = float(torch.linalg.vector_norm(rr.double()))
+    assert abs(true - res[-1]) <= 1e-3 * res[0]
