@@ -1,0 +1,208 @@
+"""Benchmark: BA-GMRES iterations/s on the 256^3 cone-beam workload.
+
+One step = one BA-GMRES solve (K = 30 iterations, B = B_un F, the
+ramp-filtered voxel-driven back-projector) from b resident in HBM to x in
+HBM, including the final host copy of the residual history.
+
+Workload (synthetic stand-in for the paper's scanner data): 256^3 volume of
+12 random ellipsoids plus 5 % smoothed Gaussian texture; circular cone beam,
+360 views over 360 deg, 384 x 384 detector at one voxel per pixel at the
+isocentre, SOD = 4 N, SDD = 8 N; data from the projector, scaled so the
+largest line integral is 4, Poisson counts at 1e5 photons per ray, negative
+log.
+
+Prints one JSON line (rank 0) with the throughput, the roofline position of
+the dominant kernel and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--sino-dtype f32|f16] [--no-cpu]
+"""
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+ITERS = 30
+PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak, FLOP/s
+PEAK_HBM = 8.0e12               # bytes/s
+# algorithmic work per unit: Joseph sample = 2 coordinate
+# FMAs + 2 fractions + 3 two-flop lerps + 1 accumulate = 12 FLOP;
+# voxel-driven update = 1 coordinate FMA + 1 fraction + 3 lerps + weighted
+# accumulate = 10 FLOP
+FLOP_PER_A_UPDATE = 12.0
+FLOP_PER_B_UPDATE = 10.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(ct, desc, g, torch):
+    from synth import workloads
+    from synth.phantoms import poisson_log_counts
+    vol = workloads.w3_phantom()
+    x = torch.from_numpy(vol).cuda()
+    ax = ct.ct_project_A(g, x)
+    mu = 4.0 / float(ax.max())
+    clean = (ax * mu).double().cpu().numpy().reshape(-1)
+    b = poisson_log_counts(303, clean, 1e5).astype(np.float32)
+    return torch.from_numpy(b).cuda(), vol * mu
+
+
+def time_op(fn, stream, torch, reps=5):
+    """Average duration of fn() on `stream`, from HIP events on that stream."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(desc, b_host, x_phantom):
+    """FP64 oracle BA-GMRES (ramp) on a bounded sample: the same volume and
+    detector with every 30th view (12 of 360), 2 iterations.  The operator
+    cost is linear in the number of views, so seconds per full iteration are
+    estimated as (sample seconds per iteration) * 30."""
+    import oracle
+    from synth.geometry import GeometryDesc
+    sub = 30
+    angles = [2 * math.pi * p / desc.n_views for p in range(0, desc.n_views, sub)]
+    gs = GeometryDesc(desc.kind, desc.nx, desc.ny, desc.nz, desc.voxel, len(angles), desc.nu,
+                      desc.nv, desc.du, desc.dv, desc.sod, desc.sdd, tuple(angles))
+    bs = b_host.reshape(desc.sino_shape)[::sub].astype(np.float64)
+    t = time.perf_counter()
+    r = oracle.ba_gmres(gs, bs, 2, B="ramp")
+    dt = time.perf_counter() - t
+    # one extra B for the start vector: (iters + 1) back-projections, iters projections
+    per_iter = dt / (r.iters_done + 0.5) * sub
+    out = {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": "FP64 oracle BA-GMRES (B_un F), 2 iterations on the 256^3 volume and "
+                     "384x384 detector with 12 of the 360 views (every 30th); seconds per "
+                     "iteration scaled by 30 (operator cost is linear in views); %.1f s of CPU "
+                     "work" % dt}
+    return out, oracle
+
+
+def sampled_errors(oracle, desc, ct, g, torch, x_phantom):
+    """Relative error of the GPU operators against the FP64 oracle on sampled
+    rays / voxels of the benchmark workload."""
+    rng = np.random.default_rng(11)
+    x = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
+    y = ct.ct_project_A(g, x)
+    yh = y.double().cpu().numpy().reshape(-1)
+    rays = rng.choice(desc.n_rays, size=1500, replace=False)
+    ra = oracle.project_A_rays(desc, x.double().cpu().numpy(), rays)
+    ea = float(np.linalg.norm(yh[rays] - ra) / np.linalg.norm(ra))
+    xb = ct.ct_backproject_B(g, y, ramp=True).double().cpu().numpy().reshape(-1)
+    vox = rng.choice(desc.n_vox, size=1500, replace=False)
+    fy = oracle.ramp(desc, y.float().cpu().numpy())
+    rb = oracle.backproject_Bun_voxels(desc, fy, vox)
+    eb = float(np.linalg.norm(xb[vox] - rb) / np.linalg.norm(rb))
+    return {"A_sampled": ea, "B_FBP_sampled": eb}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sino-dtype", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2201_07408_amd as ct
+    from synth import workloads
+
+    torch.cuda.set_device(0)
+    desc = workloads.w3_geometry()
+    g = ct.Geometry(desc)
+    log("bench: generating inputs")
+    b, x_phantom = make_inputs(ct, desc, g, torch)
+    sdt = torch.float16 if args.sino_dtype == "f16" else torch.float32
+    stream = torch.cuda.current_stream()
+
+    log("bench: warmup")
+    for _ in range(args.warmup):
+        r = ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=sdt)
+    torch.cuda.synchronize()
+    log("bench: timed solves")
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(args.steps):
+        r = ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=sdt)
+        done += r.iters_done
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = done / dt
+
+    # dominant kernels, timed with events on the stream they run on
+    log("bench: operator timing")
+    # exact update counts of this geometry, written by the oracle's counter
+    # (tests/golden/make_update_counts.py); read as data, the oracle is not run
+    counts_path = os.path.join(ROOT, "tests", "golden", "update_counts.json")
+    counts = json.load(open(counts_path))["w3"]
+    a_upd, b_upd = counts["A_updates"], counts["B_updates"]
+    xw = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
+    yw = ct.ct_project_A(g, xw)
+    xo = torch.empty_like(xw)
+    t_a = time_op(lambda: ct.ct_project_A(g, xw, out=yw), stream, torch)
+    t_b = time_op(lambda: ct.ct_backproject_B(g, yw, out=xo), stream, torch)
+    t_f = time_op(lambda: ct.ct_ramp_filter(g, yw), stream, torch)
+    dom = ("A", t_a, a_upd, FLOP_PER_A_UPDATE) if t_a >= t_b else ("B_un", t_b, b_upd, FLOP_PER_B_UPDATE)
+    achieved = dom[2] * dom[3] / dom[1]
+    line = {
+        "metric": "BA-GMRES iters/s at 256^3 cone-beam; A/B voxel-ray updates/s; rel err vs FP64",
+        "value": round(value, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if sdt == torch.float32 else "f32 (f16 data storage)",
+        "data": "synthetic",
+        "config": {"workload": "cone-beam 256^3, 360 views over 360 deg, 384x384 detector, "
+                               "ellipsoids + 5% texture, Poisson 1e5 photons, log; BA-GMRES with "
+                               "B = ramp-filtered voxel-driven B_un, 30 iterations per step",
+                   "iters_per_step": ITERS, "sino_dtype": args.sino_dtype},
+        "A_updates_per_s": a_upd / t_a,
+        "B_updates_per_s": b_upd / t_b,
+        "op_ms": {"A": t_a * 1e3, "B_un": t_b * 1e3, "F": t_f * 1e3},
+        "roofline": {"bound": "alu", "kernel": dom[0], "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": None},
+    }
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        cb, orc = cpu_baseline(desc, b.cpu().numpy(), x_phantom)
+        line["cpu_baseline"] = cb
+        line["rel_err_vs_fp64"] = sampled_errors(orc, desc, ct, g, torch, x_phantom)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

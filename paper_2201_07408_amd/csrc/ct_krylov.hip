@@ -42,7 +42,7 @@ struct KState {
     double *res;       // K+1 residual history
     double *misc;      // [0] scale of the raw z, [1] ||z|| before CGS, [2] CGLS gamma, [3] alpha/beta
     float *fscale;     // [0] A output scale, [1] B input scale (FP16 storage)
-    double *partials;  // kMaxBlk x pstride
+    double *partials;  // [column][block], columns of kMaxBlk doubles
     int pstride;
     int K;
 };
@@ -83,8 +83,17 @@ __global__ __launch_bounds__(kTile) void k_cgs(const float *__restrict__ W, size
     for (size_t t0 = (size_t)blockIdx.x * kTile; t0 < n; t0 += (size_t)gridDim.x * kTile) {
         const size_t i = t0 + tid;
         const bool ok = i < n;
-        for (int j = 0; j < nvec; ++j) wt[j * LD + tid] = ok ? W[(size_t)j * ldw + i] : 0.0f;
+        // eight loads in flight per thread before the LDS stores
         float zv = ok ? zin[i] : 0.0f;
+        int j8 = 0;
+        for (; j8 + 8 <= nvec; j8 += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = ok ? W[(size_t)(j8 + u) * ldw + i] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) wt[(j8 + u) * LD + tid] = v[u];
+        }
+        for (; j8 < nvec; ++j8) wt[j8 * LD + tid] = ok ? W[(size_t)j8 * ldw + i] : 0.0f;
         if (MODE >= 1) {
             double u = zs * (double)zv;
             for (int j = 0; j < nvec; ++j) u -= cf[j] * (double)wt[j * LD + tid];
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(kTile) void k_cgs(const float *__restrict__ W, size
         if (tid == 0) {
             double s = 0.0;
             for (int w = 0; w < kTile / 64; ++w) s += red2[w];
-            partials[(size_t)blockIdx.x * pstride] = s;
+            partials[blockIdx.x] = s;
         }
         return;
     }
@@ -138,24 +147,23 @@ __global__ __launch_bounds__(kTile) void k_cgs(const float *__restrict__ W, size
     for (int j = tid; j < ndot; j += kTile) {
         double s = 0.0;
         for (int w = 0; w < kTile / 64; ++w) s += red[w * 256 + j];
-        partials[(size_t)blockIdx.x * pstride + j] = s;
+        partials[(size_t)j * kMaxBlk + blockIdx.x] = s;
     }
 }
 
-// Sum partials[b][j] over b for j < count into out[j] (one block, fixed order).
+// out[j] = sum over b < nblk of partials[j][b], for j < count.  One wavefront
+// per column, lanes stride the blocks, a fixed shuffle tree finishes: the
+// order never changes, so the result is bitwise reproducible.
 __device__ void reduce_partials(const double *__restrict__ partials, int nblk, int pstride, int count,
                                 double *out) {
-    for (int j = threadIdx.x; j < count; j += blockDim.x) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int b = 0;
-        for (; b + 3 < nblk; b += 4) {
-            s0 += partials[(size_t)b * pstride + j];
-            s1 += partials[(size_t)(b + 1) * pstride + j];
-            s2 += partials[(size_t)(b + 2) * pstride + j];
-            s3 += partials[(size_t)(b + 3) * pstride + j];
-        }
-        for (; b < nblk; ++b) s0 += partials[(size_t)b * pstride + j];
-        out[j] = (s0 + s1) + (s2 + s3);
+    (void)pstride;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wave; j < count; j += nw) {
+        const double *col = partials + (size_t)j * kMaxBlk;
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += col[b];
+        s = wave_sum(s);
+        if (lane == 0) out[j] = s;
     }
 }
 
@@ -311,7 +319,7 @@ __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ v, size
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * pstride] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void k_zero_i32(int *p, int n) {

@@ -37,6 +37,12 @@ __device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(elem * 4u), 0, 0));
 }
 
+// two adjacent floats (4-byte alignment is enough for buffer loads on gfx9)
+__device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(elem * 4u), 0, 0);
+    return make_float2(__builtin_bit_cast(float, (uint32_t)v[0]), __builtin_bit_cast(float, (uint32_t)v[1]));
+}
+
 __device__ __forceinline__ float to_f(float v) { return v; }
 __device__ __forceinline__ float to_f(__half v) { return __half2float(v); }
 template <typename T> __device__ __forceinline__ T from_f(float v);
@@ -201,9 +207,12 @@ __device__ __forceinline__ RaySetup ray_setup(const GeomK &g, const PadLayout &L
     return R;
 }
 
+// `vol` holds Vx at element 0 and Vy at element `offy`; one buffer
+// resource covers both so that the descriptor stays wave-uniform while the
+// copy (and strides) are chosen per ray.
 template <bool CONE, typename OutT>
-__global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const float *__restrict__ vx,
-                                                 const float *__restrict__ vy, OutT *__restrict__ y,
+__global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const float *__restrict__ vol,
+                                                 uint32_t offy, OutT *__restrict__ y,
                                                  const float *__restrict__ out_scale,
                                                  const int *__restrict__ stop) {
     if (stop && *stop) return;
@@ -213,31 +222,73 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
     if (au >= g.nu || av >= g.nv) return;
     const RaySetup R = ray_setup<CONE>(g, L, p, av, au);
     const bool isx = R.ax == 0;
-    const __amdgpu_buffer_rsrc_t rs = isx ? make_rsrc(vx, L.nvx) : make_rsrc(vy, L.nvy);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol, (size_t)offy + L.nvy);
     const uint32_t S = isx ? L.sx : L.sy, Rw = isx ? L.rx : L.ry;
-    float acc = 0.0f;
-    for (int j = R.j0; j <= R.j1; ++j) {
+    const uint32_t base = isx ? 0u : offy;
+    // the plane loop is unrolled by four so that eight (3D) or four (2D)
+    // loads are in flight before the first interpolation; each group of four
+    // samples is summed in FP32 and added to an FP64 accumulator (FP32
+    // accumulation over hundreds of samples costs more accuracy than the
+    // sample positions do)
+    double acc = 0.0;
+    int j = R.j0;
+    for (; j + 3 <= R.j1; j += 4) {
+        uint32_t off[4];
+        float wb[4], wc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float fj = (float)(j + u);
+            const float fb = fmaf(fj, R.gb, R.fb0);
+            const float ibf = floorf(fb);
+            wb[u] = fb - ibf;
+            off[u] = base + __umul24((uint32_t)(j + u), S) + (uint32_t)(int)ibf;
+            if (CONE) {
+                const float fc = fmaf(fj, R.gc, R.fc0);
+                const float icf = floorf(fc);
+                wc[u] = fc - icf;
+                off[u] += __umul24((uint32_t)(int)icf, Rw);
+            }
+        }
+        float2 lo[4], hi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            lo[u] = ld2(rs, off[u]);
+            if (CONE) hi[u] = ld2(rs, off[u] + Rw);
+        }
+        float grp = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float t0 = fmaf(wb[u], lo[u].y - lo[u].x, lo[u].x);
+            if (CONE) {
+                const float t1 = fmaf(wb[u], hi[u].y - hi[u].x, hi[u].x);
+                grp += fmaf(wc[u], t1 - t0, t0);
+            } else {
+                grp += t0;
+            }
+        }
+        acc += (double)grp;
+    }
+    for (; j <= R.j1; ++j) {
         const float fj = (float)j;
         const float fb = fmaf(fj, R.gb, R.fb0);
         const float ibf = floorf(fb);
         const float wb = fb - ibf;
-        uint32_t off = (uint32_t)j * S + (uint32_t)(int)ibf;
+        uint32_t off = base + __umul24((uint32_t)j, S) + (uint32_t)(int)ibf;
         if (CONE) {
             const float fc = fmaf(fj, R.gc, R.fc0);
             const float icf = floorf(fc);
             const float wc = fc - icf;
-            off += (uint32_t)(int)icf * Rw;
-            const float v00 = ldf(rs, off), v01 = ldf(rs, off + 1);
-            const float v10 = ldf(rs, off + Rw), v11 = ldf(rs, off + Rw + 1);
-            const float t0 = fmaf(wb, v01 - v00, v00);
-            const float t1 = fmaf(wb, v11 - v10, v10);
-            acc += fmaf(wc, t1 - t0, t0);
+            off += __umul24((uint32_t)(int)icf, Rw);
+            const float2 a = ld2(rs, off), b = ld2(rs, off + Rw);
+            const float t0 = fmaf(wb, a.y - a.x, a.x);
+            const float t1 = fmaf(wb, b.y - b.x, b.x);
+            acc += (double)fmaf(wc, t1 - t0, t0);
         } else {
-            const float v0 = ldf(rs, off), v1 = ldf(rs, off + 1);
-            acc += fmaf(wb, v1 - v0, v0);
+            const float2 a = ld2(rs, off);
+            acc += (double)fmaf(wb, a.y - a.x, a.x);
         }
     }
-    float val = acc * R.step;
+    float val = (float)(acc * (double)R.step);
     if (out_scale) val *= *out_scale;
     y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(val);
 }
@@ -305,9 +356,11 @@ __global__ __launch_bounds__(256) void k_bp_cone(GeomK g, const InT *__restrict_
     const double wconst = g.vox * g.vox * g.vox * inv_du * inv_dv;
     const double cu = 0.5 * (g.nu - 1), cv = 0.5 * (g.nv - 1);
     const int nu = g.nu, nv = g.nv;
-    float acc[kZC];
+    // views are summed in FP32 in groups of four, groups in FP64
+    double acc[kZC];
+    float grp[kZC];
 #pragma unroll
-    for (int z = 0; z < kZC; ++z) acc[z] = 0.0f;
+    for (int z = 0; z < kZC; ++z) { acc[z] = 0.0; grp[z] = 0.0f; }
     const size_t view = (size_t)nv * nu;
     for (int p = 0; p < g.P; ++p) {
         const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
@@ -336,14 +389,18 @@ __global__ __launch_bounds__(256) void k_bp_cone(GeomK g, const InT *__restrict_
             const size_t r0 = (size_t)(v0 ? iv : 0) * nu, r1 = (size_t)(v1 ? iv + 1 : 0) * nu;
             const float a = wu0 * to_f(yp[r0 + c0]) + wu1 * to_f(yp[r0 + c1]);
             const float b = wu0 * to_f(yp[r1 + c0]) + wu1 * to_f(yp[r1 + c1]);
-            acc[z] += (v0 ? 1.0f - wv : 0.0f) * a + (v1 ? wv : 0.0f) * b;
+            grp[z] += (v0 ? 1.0f - wv : 0.0f) * a + (v1 ? wv : 0.0f) * b;
+        }
+        if ((p & 3) == 3 || p == g.P - 1) {
+#pragma unroll
+            for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
         }
     }
-    const float sc = in_scale ? *in_scale : 1.0f;
+    const double sc = in_scale ? (double)*in_scale : 1.0;
 #pragma unroll
     for (int z = 0; z < kZC; ++z) {
         const int iz = iz0 + z;
-        if (iz < g.nz) x[((size_t)iz * g.ny + iy) * g.nx + ix] = acc[z] * sc;
+        if (iz < g.nz) x[((size_t)iz * g.ny + iy) * g.nx + ix] = (float)(acc[z] * sc);
     }
 }
 
@@ -359,7 +416,9 @@ __global__ __launch_bounds__(256) void k_bp_par(GeomK g, const InT *__restrict__
     const double py = (iy - 0.5 * (g.ny - 1)) * g.vox * inv_du;
     const double cu = 0.5 * (g.nu - 1);
     const int nu = g.nu;
-    float acc = 0.0f;
+    // views summed in FP32 in groups of four, groups in FP64
+    double acc = 0.0;
+    float grp = 0.0f;
     for (int p = 0; p < g.P; ++p) {
         const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
         const float fu = (float)(px * c + py * s + cu);
@@ -370,10 +429,11 @@ __global__ __launch_bounds__(256) void k_bp_par(GeomK g, const InT *__restrict__
         const InT *yp = y + (size_t)p * nu;
         const float a = u0 ? to_f(yp[u0 ? iu : 0]) : 0.0f;
         const float b = u1 ? to_f(yp[u1 ? iu + 1 : 0]) : 0.0f;
-        acc += fmaf(wu, b - a, a);
+        grp += fmaf(wu, b - a, a);
+        if ((p & 3) == 3 || p == g.P - 1) { acc += (double)grp; grp = 0.0f; }
     }
-    const float sc = in_scale ? *in_scale : 1.0f;
-    x[(size_t)iy * g.nx + ix] = acc * (float)(g.vox * g.vox * inv_du) * sc;
+    const double sc = in_scale ? (double)*in_scale : 1.0;
+    x[(size_t)iy * g.nx + ix] = (float)(acc * (g.vox * g.vox * inv_du) * sc);
 }
 
 // ----------------------------------------------------------------- F
@@ -445,12 +505,19 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
     dim3 grid, block;
     ray_grid(g, grid, block);
     const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
+    // the two copies must be carved back to back (one buffer resource)
+    const ptrdiff_t dy = vy - vx;
+    if (dy < (ptrdiff_t)g->pad.nvx || (double)(dy + g->pad.nvy) * 4.0 >= 4294967296.0) {
+        set_error("launch_project: padded volume copies are not contiguous or exceed 4 GiB");
+        return CT_ERR_UNSUPPORTED;
+    }
+    const uint32_t offy = (uint32_t)dy;
     if (y_dtype == CT_F32) {
-        if (cone) hipLaunchKernelGGL((k_project<true, float>), grid, block, 0, s, g->k, g->pad, vx, vy, (float *)y, out_scale, stop);
-        else hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, vy, (float *)y, out_scale, stop);
+        if (cone) hipLaunchKernelGGL((k_project<true, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
+        else hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
     } else {
-        if (cone) hipLaunchKernelGGL((k_project<true, __half>), grid, block, 0, s, g->k, g->pad, vx, vy, (__half *)y, out_scale, stop);
-        else hipLaunchKernelGGL((k_project<false, __half>), grid, block, 0, s, g->k, g->pad, vx, vy, (__half *)y, out_scale, stop);
+        if (cone) hipLaunchKernelGGL((k_project<true, __half>), grid, block, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
+        else hipLaunchKernelGGL((k_project<false, __half>), grid, block, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
     }
     CT_LAUNCH_CHECK();
     return CT_OK;
