@@ -67,8 +67,9 @@ struct GeomK {
 
 // Padded, axis-permuted volume copies read by the forward projector and
 // accumulated into by the scatter transpose.
-//   Vx[ix][iz+pz][iy+kPad], rows of ny+2*kPad, (nz+2*pz) rows per plane
-//   Vy[iy][iz+pz][ix+kPad], rows of nx+2*kPad
+//   Vx[ix][iz+pz][iy+kPad], rows of ny+2*kPad rounded up to a multiple of 4,
+//   (nz+2*pz) rows per plane
+//   Vy[iy][iz+pz][ix+kPad], rows of nx+2*kPad rounded likewise
 // with pz = kPad in 3D and 0 in 2D.
 struct PadLayout {
     int pz;
@@ -80,9 +81,10 @@ struct PadLayout {
 inline PadLayout pad_layout(const GeomK &g) {
     PadLayout L;
     L.pz = (g.kind == 1) ? kPad : 0;
-    L.rx = (uint32_t)(g.ny + 2 * kPad);
+    // rows are a multiple of four floats so that staged 16-byte loads align
+    L.rx = (uint32_t)((g.ny + 2 * kPad + 3) & ~3);
     L.sx = L.rx * (uint32_t)(g.nz + 2 * L.pz);
-    L.ry = (uint32_t)(g.nx + 2 * kPad);
+    L.ry = (uint32_t)((g.nx + 2 * kPad + 3) & ~3);
     L.sy = L.ry * (uint32_t)(g.nz + 2 * L.pz);
     L.nvx = (size_t)L.sx * g.nx;
     L.nvy = (size_t)L.sy * g.ny;

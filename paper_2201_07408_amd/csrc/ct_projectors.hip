@@ -53,9 +53,9 @@ template <> __device__ __forceinline__ __half from_f<__half>(float v) { return _
 // Zero only the border cells of both padded copies.
 __global__ void k_pad_zero(float *__restrict__ vx, float *__restrict__ vy, int nx, int ny,
                            int nz, PadLayout L) {
-    // cells per plane: full border rows + two side strips of kPad per interior row
-    const size_t per_x = (size_t)2 * L.pz * L.rx + (size_t)nz * 2 * kPad;
-    const size_t per_y = (size_t)2 * L.pz * L.ry + (size_t)nz * 2 * kPad;
+    // cells per plane: full border rows + the side strips of each interior row
+    const size_t per_x = (size_t)2 * L.pz * L.rx + (size_t)nz * (L.rx - ny);
+    const size_t per_y = (size_t)2 * L.pz * L.ry + (size_t)nz * (L.ry - nx);
     const size_t tot_x = per_x * nx, tot = tot_x + per_y * ny;
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -74,9 +74,11 @@ __global__ void k_pad_zero(float *__restrict__ vx, float *__restrict__ vy, int n
             col = (uint32_t)(q % R);
             if (row >= (uint32_t)L.pz) row += nz;
         } else {
+            // kPad cells on the left, R - nb - kPad on the right of each interior row
+            const uint32_t side = R - (uint32_t)nb;
             const size_t q2 = q - full;
-            row = (uint32_t)(L.pz + q2 / (2 * kPad));
-            const uint32_t c = (uint32_t)(q2 % (2 * kPad));
+            row = (uint32_t)(L.pz + q2 / side);
+            const uint32_t c = (uint32_t)(q2 % side);
             col = c < (uint32_t)kPad ? c : (uint32_t)nb + c;
         }
         float *dst = isx ? vx : vy;
@@ -207,32 +209,21 @@ __device__ __forceinline__ RaySetup ray_setup(const GeomK &g, const PadLayout &L
     return R;
 }
 
-// `vol` holds Vx at element 0 and Vy at element `offy`; one buffer
-// resource covers both so that the descriptor stays wave-uniform while the
-// copy (and strides) are chosen per ray.
-template <bool CONE, typename OutT>
-__global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const float *__restrict__ vol,
-                                                 uint32_t offy, OutT *__restrict__ y,
-                                                 const float *__restrict__ out_scale,
-                                                 const int *__restrict__ stop) {
-    if (stop && *stop) return;
-    const int au = blockIdx.x * blockDim.x + threadIdx.x;
-    const int av = blockIdx.y * blockDim.y + threadIdx.y;
-    const int p = blockIdx.z;
-    if (au >= g.nu || av >= g.nv) return;
-    const RaySetup R = ray_setup<CONE>(g, L, p, av, au);
-    const bool isx = R.ax == 0;
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol, (size_t)offy + L.nvy);
-    const uint32_t S = isx ? L.sx : L.sy, Rw = isx ? L.rx : L.ry;
-    const uint32_t base = isx ? 0u : offy;
-    // the plane loop is unrolled by four so that eight (3D) or four (2D)
-    // loads are in flight before the first interpolation; each group of four
-    // samples is summed in FP32 and added to an FP64 accumulator (FP32
-    // accumulation over hundreds of samples costs more accuracy than the
-    // sample positions do)
+// Direct (cache-gather) evaluation of the samples of one ray on planes
+// [ja, jb], read straight from the padded copy.  `vol` holds Vx at element 0
+// and Vy at element `offy`; one buffer resource covers both so that the
+// descriptor stays wave-uniform while the copy (and strides) are chosen per
+// ray.  The plane loop is unrolled by four so that eight (3D) or four (2D)
+// loads are in flight before the first interpolation; each group of four
+// samples is summed in FP32 and added to an FP64 accumulator (FP32
+// accumulation over hundreds of samples costs more accuracy than the sample
+// positions do).
+template <bool CONE>
+__device__ __forceinline__ double direct_samples(const RaySetup &R, __amdgpu_buffer_rsrc_t rs, uint32_t base,
+                                                 uint32_t S, uint32_t Rw, int ja, int jb) {
     double acc = 0.0;
-    int j = R.j0;
-    for (; j + 3 <= R.j1; j += 4) {
+    int j = ja;
+    for (; j + 3 <= jb; j += 4) {
         uint32_t off[4];
         float wb[4], wc[4];
 #pragma unroll
@@ -268,7 +259,7 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
         }
         acc += (double)grp;
     }
-    for (; j <= R.j1; ++j) {
+    for (; j <= jb; ++j) {
         const float fj = (float)j;
         const float fb = fmaf(fj, R.gb, R.fb0);
         const float ibf = floorf(fb);
@@ -288,9 +279,204 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
             acc += (double)fmaf(wb, a.y - a.x, a.x);
         }
     }
-    float val = (float)(acc * (double)R.step);
+    return acc;
+}
+
+template <typename OutT>
+__device__ __forceinline__ void store_ray(const GeomK &g, OutT *y, int p, int av, int au, double acc,
+                                          float step, const float *out_scale) {
+    float val = (float)(acc * (double)step);
     if (out_scale) val *= *out_scale;
     y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(val);
+}
+
+// Direct projector: one work-item per ray (2D, and 3D fallback).
+template <bool CONE, typename OutT>
+__global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const float *__restrict__ vol,
+                                                 uint32_t offy, OutT *__restrict__ y,
+                                                 const float *__restrict__ out_scale,
+                                                 const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int au = blockIdx.x * blockDim.x + threadIdx.x;
+    const int av = blockIdx.y * blockDim.y + threadIdx.y;
+    const int p = blockIdx.z;
+    if (au >= g.nu || av >= g.nv) return;
+    const RaySetup R = ray_setup<CONE>(g, L, p, av, au);
+    const bool isx = R.ax == 0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol, (size_t)offy + L.nvy);
+    const double acc = direct_samples<CONE>(R, rs, isx ? 0u : offy, isx ? L.sx : L.sy, isx ? L.rx : L.ry,
+                                            R.j0, R.j1);
+    store_ray(g, y, p, av, au, acc, R.step, out_scale);
+}
+
+// ---------------------------------------------------- staged 3D projector
+// A workgroup is a 16 (u) x 16 (v) tile of one view's detector.  At a given
+// plane its 256 rays sample a compact patch of about 18 x 18 voxels, and
+// each voxel feeds about three of the tile's samples, so the patch is staged
+// in LDS once and the taps are read from there.  For each chunk of kPC
+// planes the patch (the union box of the chunk's planes) is copied with
+// 16-byte loads of the rows and columns the box needs, then every ray reads
+// its four taps per plane from LDS.  The box comes from the tile's four
+// corner rays: at a fixed plane the in-plane position is monotone in u and
+// in v, and it is linear in the plane index, so the corners at the chunk's
+// first and last planes bound every ray of the tile.  The next chunk's loads
+// are issued into registers before the current chunk is interpolated.
+// Tiles whose rays do not share a dominant axis, and chunks whose box does
+// not fit, take the direct path.
+constexpr int kTU = 16, kTV = 16;     // rays per workgroup
+constexpr int kPC = 4;                // planes per staged chunk
+constexpr int kSR = 24, kSC = 36;     // staged rows / columns per plane (kSC % 4 == 0)
+constexpr int kMaxChunks = 512;       // planes up to 2048
+constexpr int kQPT = 4;               // 16-byte cells per thread per chunk (upper bound)
+
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
+                                                        uint32_t offy, OutT *__restrict__ y,
+                                                        const float *__restrict__ out_scale,
+                                                        const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    __shared__ float4 tile4[kPC * kSR * kSC / 4];
+    __shared__ short s_box[kMaxChunks][4];   // b0 (aligned to 4, -1: direct), c0, rows, 16-byte columns
+    __shared__ float s_corner[4][4];
+    __shared__ int s_axes, s_jlo, s_jhi;
+    const float *tile = (const float *)tile4;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx;
+    const int au0 = blockIdx.x * kTU, av0 = blockIdx.y * kTV, p = blockIdx.z;
+    const int au = au0 + tx, av = av0 + ty;
+    const bool active = au < g.nu && av < g.nv;
+    if (tid == 0) { s_axes = 0; s_jlo = 0x7fffffff; s_jhi = -1; }
+    __syncthreads();
+    RaySetup R;
+    R.j0 = 1; R.j1 = 0; R.ax = 0; R.fb0 = R.gb = R.fc0 = R.gc = R.step = 0.0f;
+    if (active) {
+        R = ray_setup<true>(g, L, p, av, au);
+        atomicOr(&s_axes, 1 << R.ax);
+        if (R.j0 <= R.j1) { atomicMin(&s_jlo, R.j0); atomicMax(&s_jhi, R.j1); }
+        // corner rays of the (possibly partial) tile
+        const int ulast = min(au0 + kTU, g.nu) - 1 - au0, vlast = min(av0 + kTV, g.nv) - 1 - av0;
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx)
+                if ((cx ? tx == ulast : tx == 0) && (cy ? ty == vlast : ty == 0)) {
+                    s_corner[cy * 2 + cx][0] = R.fb0;
+                    s_corner[cy * 2 + cx][1] = R.gb;
+                    s_corner[cy * 2 + cx][2] = R.fc0;
+                    s_corner[cy * 2 + cx][3] = R.gc;
+                }
+    }
+    __syncthreads();
+    const int axes = s_axes, jlo = s_jlo, jhi = s_jhi;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol, (size_t)offy + L.nvy);
+    const int nch = jhi >= jlo ? (jhi - jlo) / kPC + 1 : 0;
+    if (axes == 3 || nch > kMaxChunks) {   // mixed dominant axes: direct path
+        if (active) {
+            const bool isx = R.ax == 0;
+            const double acc = direct_samples<true>(R, rs, isx ? 0u : offy, isx ? L.sx : L.sy,
+                                                    isx ? L.rx : L.ry, R.j0, R.j1);
+            store_ray(g, y, p, av, au, acc, R.step, out_scale);
+        }
+        return;
+    }
+    const bool isx = axes != 2;
+    const uint32_t S = isx ? L.sx : L.sy, Rw = isx ? L.rx : L.ry, base = isx ? 0u : offy;
+    const int Na = isx ? g.nx : g.ny;
+    const int nrows = g.nz + 2 * L.pz;
+    // box of every chunk
+    for (int c = tid; c < nch; c += kTU * kTV) {
+        const int ja = jlo + c * kPC, jb = min(ja + kPC - 1, jhi);
+        float bmin = 3.0e38f, bmax = -3.0e38f, cmin = 3.0e38f, cmax = -3.0e38f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const float fj = (float)(e ? jb : ja);
+                const float fb = fmaf(fj, s_corner[k][1], s_corner[k][0]);
+                const float fc = fmaf(fj, s_corner[k][3], s_corner[k][2]);
+                bmin = fminf(bmin, fb); bmax = fmaxf(bmax, fb);
+                cmin = fminf(cmin, fc); cmax = fmaxf(cmax, fc);
+            }
+        }
+        // one cell of margin on each side absorbs rounding; clamp to the copy
+        const int b0 = max((int)floorf(bmin) - 1, 0) & ~3;
+        const int b1 = min((int)floorf(bmax) + 2, (int)Rw - 1);
+        const int c0 = max((int)floorf(cmin) - 1, 0);
+        const int c1 = min((int)floorf(cmax) + 2, nrows - 1);
+        const int nr = c1 - c0 + 1, nq = (b1 - b0) / 4 + 1;
+        const bool fits = nr <= kSR && 4 * nq <= kSC && kPC * nr * nq <= kQPT * kTU * kTV;
+        s_box[c][0] = (short)(fits ? b0 : -1);
+        s_box[c][1] = (short)c0;
+        s_box[c][2] = (short)nr;
+        s_box[c][3] = (short)nq;
+    }
+    float4 pre[kQPT];
+    auto fetch = [&](int c) {
+        const int ja = jlo + c * kPC;
+        const int b0 = s_box[c][0], c0 = s_box[c][1], nr = s_box[c][2], nq = s_box[c][3];
+        const int cells = kPC * nr * nq;
+#pragma unroll
+        for (int k = 0; k < kQPT; ++k) {
+            const int q = tid + k * kTU * kTV;
+            pre[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (b0 >= 0 && q < cells) {
+                const int pl = q / (nr * nq);
+                const int rem = q - pl * nr * nq;
+                const int r = rem / nq, c4 = rem - r * nq;
+                const int j = ja + pl;
+                if (j < Na) {
+                    const uint32_t off = base + __umul24((uint32_t)j, S) + __umul24((uint32_t)(c0 + r), Rw) +
+                                         (uint32_t)(b0 + 4 * c4);
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off * 4u), 0, 0);
+                    pre[k] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]),
+                                         __builtin_bit_cast(float, (uint32_t)w[1]),
+                                         __builtin_bit_cast(float, (uint32_t)w[2]),
+                                         __builtin_bit_cast(float, (uint32_t)w[3]));
+                }
+            }
+        }
+    };
+    __syncthreads();   // boxes visible
+    if (nch > 0) fetch(0);
+    double acc = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        const int ja = jlo + c * kPC;
+        const int b0 = s_box[c][0], c0 = s_box[c][1], nr = s_box[c][2], nq = s_box[c][3];
+        const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
+        if (b0 >= 0) {
+            __syncthreads();   // previous chunk's readers are done with the tile
+            const int cells = kPC * nr * nq;
+#pragma unroll
+            for (int k = 0; k < kQPT; ++k) {
+                const int q = tid + k * kTU * kTV;
+                if (q < cells) {
+                    const int pl = q / (nr * nq);
+                    const int rem = q - pl * nr * nq;
+                    const int r = rem / nq, c4 = rem - r * nq;
+                    tile4[((pl * kSR + r) * kSC) / 4 + c4] = pre[k];
+                }
+            }
+            __syncthreads();
+        }
+        if (c + 1 < nch) fetch(c + 1);
+        if (b0 < 0) {      // box too large: direct loads for this chunk
+            if (jf <= jb) acc += direct_samples<true>(R, rs, base, S, Rw, jf, jb);
+            continue;
+        }
+        float grp = 0.0f;
+        for (int j = jf; j <= jb; ++j) {
+            const float fj = (float)j;
+            const float fb = fmaf(fj, R.gb, R.fb0);
+            const float fc = fmaf(fj, R.gc, R.fc0);
+            const float ibf = floorf(fb), icf = floorf(fc);
+            const float wb = fb - ibf, wc = fc - icf;
+            const int o = ((j - ja) * kSR + ((int)icf - c0)) * kSC + ((int)ibf - b0);
+            const float t00 = tile[o], t01 = tile[o + 1];
+            const float t10 = tile[o + kSC], t11 = tile[o + kSC + 1];
+            const float a0 = fmaf(wb, t01 - t00, t00);
+            const float a1 = fmaf(wb, t11 - t10, t10);
+            grp += fmaf(wc, a1 - a0, a0);
+        }
+        acc += (double)grp;
+    }
+    if (active) store_ray(g, y, p, av, au, acc, R.step, out_scale);
 }
 
 __device__ __forceinline__ uint32_t clampu(int v, int hi) { return (uint32_t)min(max(v, 0), hi); }
@@ -341,61 +527,166 @@ __global__ __launch_bounds__(256) void k_project_T(GeomK g, PadLayout L, const I
 // --------------------------------------------------------------- B_un
 constexpr int kZC = 16;   // z voxels per work-item in the cone back-projector
 
+// ---------------------------------------------- staged 3D back-projector
+// A workgroup is 16 x 16 columns (x, y) times kZC voxels in z.  For groups of
+// kVG views it copies each view's footprint (kSV rows x kSU columns of the
+// detector, zero outside it) into LDS with 16-byte loads, then every column
+// reads its bilinear taps for all kZC voxels from LDS.  The footprint of a
+// view comes from the workgroup's four corner columns: u is monotone along
+// x and y at fixed view, v is monotone in z and along the view direction.
+// Workgroups with any footprint larger than the tile take the direct path.
+constexpr int kVG = 4;               // views per staged group
+constexpr int kSU = 36, kSV = 32;    // staged detector columns / rows per view
+constexpr int kMaxViewsStaged = 2048;
+
+__device__ __forceinline__ void project_point(const GeomK &g, double px, double py, double c, double s,
+                                              double &fu, double &M) {
+    const double U = g.sod - (px * c + py * s);
+    M = g.sdd / U;
+    fu = M * (py * c - px * s) / g.du + 0.5 * (g.nu - 1);
+}
+
 template <typename InT>
-__global__ __launch_bounds__(256) void k_bp_cone(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
-                                                 const float *__restrict__ in_scale,
-                                                 const int *__restrict__ stop) {
+__global__ __launch_bounds__(256) void k_bp_cone_staged(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
+                                                        const float *__restrict__ in_scale,
+                                                        const int *__restrict__ stop) {
     if (stop && *stop) return;
-    const int ix = blockIdx.x * 16 + threadIdx.x, iy = blockIdx.y * 16 + threadIdx.y;
-    const int iz0 = blockIdx.z * kZC;
-    if (ix >= g.nx || iy >= g.ny) return;
+    __shared__ float4 tile4[kVG * kSV * kSU / 4];
+    __shared__ short s_box[kMaxViewsStaged][2];
+    __shared__ int s_bad;
+    const float *tile = (const float *)tile4;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 16 + tx;
+    const int ix0 = blockIdx.x * 16, iy0 = blockIdx.y * 16, iz0 = blockIdx.z * kZC;
+    const int ix = ix0 + tx, iy = iy0 + ty;
+    const bool active = ix < g.nx && iy < g.ny;
+    const int nu = g.nu, nv = g.nv, P = g.P;
+    if (tid == 0) s_bad = P > kMaxViewsStaged;
+    __syncthreads();
+    const double inv_dv = 1.0 / g.dv;
+    const double cv = 0.5 * (nv - 1);
+    // footprint of each view from the corner columns and the chunk's z range
+    if (!s_bad) {
+        const int ix1 = min(ix0 + 15, g.nx - 1), iy1 = min(iy0 + 15, g.ny - 1), iz1 = min(iz0 + kZC - 1, g.nz - 1);
+        const double pza = (iz0 - 0.5 * (g.nz - 1)) * g.vox, pzb = (iz1 - 0.5 * (g.nz - 1)) * g.vox;
+        for (int p = tid; p < P; p += 256) {
+            const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+            for (int k = 0; k < 4; ++k) {
+                const double px = ((k & 1 ? ix1 : ix0) - 0.5 * (g.nx - 1)) * g.vox;
+                const double py = ((k & 2 ? iy1 : iy0) - 0.5 * (g.ny - 1)) * g.vox;
+                double fu, M;
+                project_point(g, px, py, c, s, fu, M);
+                umin = fmin(umin, fu); umax = fmax(umax, fu);
+                const double va = M * pza * inv_dv + cv, vb = M * pzb * inv_dv + cv;
+                vmin = fmin(vmin, fmin(va, vb)); vmax = fmax(vmax, fmax(va, vb));
+            }
+            // one cell of margin each side; u start aligned to 4 for 16-byte loads
+            const int u0 = ((int)floor(umin) - 1) & ~3, u1 = (int)floor(umax) + 2;
+            const int v0 = (int)floor(vmin) - 1, v1 = (int)floor(vmax) + 2;
+            if (u1 - u0 >= kSU || v1 - v0 >= kSV || u0 < -32000 || v0 < -32000 || u0 > 32000 || v0 > 32000)
+                s_bad = 1;
+            s_box[p][0] = (short)u0;
+            s_box[p][1] = (short)v0;
+        }
+    }
+    __syncthreads();
     const double px = (ix - 0.5 * (g.nx - 1)) * g.vox;
     const double py = (iy - 0.5 * (g.ny - 1)) * g.vox;
     const double pz0 = (iz0 - 0.5 * (g.nz - 1)) * g.vox;
-    const double inv_du = 1.0 / g.du, inv_dv = 1.0 / g.dv;
-    const double wconst = g.vox * g.vox * g.vox * inv_du * inv_dv;
-    const double cu = 0.5 * (g.nu - 1), cv = 0.5 * (g.nv - 1);
-    const int nu = g.nu, nv = g.nv;
-    // views are summed in FP32 in groups of four, groups in FP64
+    const double wconst = g.vox * g.vox * g.vox / (g.du * g.dv);
     double acc[kZC];
     float grp[kZC];
 #pragma unroll
     for (int z = 0; z < kZC; ++z) { acc[z] = 0.0; grp[z] = 0.0f; }
-    const size_t view = (size_t)nv * nu;
-    for (int p = 0; p < g.P; ++p) {
-        const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
-        const double U = g.sod - (px * c + py * s);
-        const double M = g.sdd / U;
-        const double fu = M * (py * c - px * s) * inv_du + cu;
-        const double fv0 = M * pz0 * inv_dv + cv;
-        const float dfv = (float)(M * g.vox * inv_dv);
-        const float w = (float)(M * M * wconst);
-        const float fuf = (float)fu;
-        const float iuf = floorf(fuf);
-        const float wu = fuf - iuf;
-        const int iu = (int)iuf;
-        const bool u0 = iu >= 0 && iu < nu, u1 = iu + 1 >= 0 && iu + 1 < nu;
-        const float wu0 = u0 ? (1.0f - wu) * w : 0.0f, wu1 = u1 ? wu * w : 0.0f;
-        const int c0 = u0 ? iu : 0, c1 = u1 ? iu + 1 : 0;
-        const InT *yp = y + (size_t)p * view;
-        const float fv0f = (float)fv0;
+    if (s_bad) {
+        // direct path: masked gathers from global memory
+        if (active) {
+            for (int p = 0; p < P; ++p) {
+                const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+                double fu, M;
+                project_point(g, px, py, c, s, fu, M);
+                const float dfv = (float)(M * g.vox * inv_dv);
+                const float w = (float)(M * M * wconst);
+                const float fuf = (float)fu;
+                const float iuf = floorf(fuf);
+                const float wu = fuf - iuf;
+                const int iu = (int)iuf;
+                const bool u0 = iu >= 0 && iu < nu, u1 = iu + 1 >= 0 && iu + 1 < nu;
+                const float wu0 = u0 ? (1.0f - wu) * w : 0.0f, wu1 = u1 ? wu * w : 0.0f;
+                const int c0 = u0 ? iu : 0, c1 = u1 ? iu + 1 : 0;
+                const InT *yp = y + (size_t)p * nv * nu;
+                const float fv0f = (float)(M * pz0 * inv_dv + cv);
 #pragma unroll
-        for (int z = 0; z < kZC; ++z) {
-            const float fv = fmaf((float)z, dfv, fv0f);
-            const float ivf = floorf(fv);
-            const float wv = fv - ivf;
-            const int iv = (int)ivf;
-            const bool v0 = iv >= 0 && iv < nv, v1 = iv + 1 >= 0 && iv + 1 < nv;
-            const size_t r0 = (size_t)(v0 ? iv : 0) * nu, r1 = (size_t)(v1 ? iv + 1 : 0) * nu;
-            const float a = wu0 * to_f(yp[r0 + c0]) + wu1 * to_f(yp[r0 + c1]);
-            const float b = wu0 * to_f(yp[r1 + c0]) + wu1 * to_f(yp[r1 + c1]);
-            grp[z] += (v0 ? 1.0f - wv : 0.0f) * a + (v1 ? wv : 0.0f) * b;
+                for (int z = 0; z < kZC; ++z) {
+                    const float fv = fmaf((float)z, dfv, fv0f);
+                    const float ivf = floorf(fv);
+                    const float wv = fv - ivf;
+                    const int iv = (int)ivf;
+                    const bool v0 = iv >= 0 && iv < nv, v1 = iv + 1 >= 0 && iv + 1 < nv;
+                    const size_t r0 = (size_t)(v0 ? iv : 0) * nu, r1 = (size_t)(v1 ? iv + 1 : 0) * nu;
+                    const float a = wu0 * to_f(yp[r0 + c0]) + wu1 * to_f(yp[r0 + c1]);
+                    const float b = wu0 * to_f(yp[r1 + c0]) + wu1 * to_f(yp[r1 + c1]);
+                    grp[z] += (v0 ? 1.0f - wv : 0.0f) * a + (v1 ? wv : 0.0f) * b;
+                }
+                if ((p & 3) == 3 || p == P - 1) {
+#pragma unroll
+                    for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
+                }
+            }
         }
-        if ((p & 3) == 3 || p == g.P - 1) {
+    } else {
+        constexpr int Q = kSU / 4;   // 16-byte chunks per staged row
+        for (int p0 = 0; p0 < P; p0 += kVG) {
+            __syncthreads();
+            for (int q = tid; q < kVG * kSV * Q; q += 256) {
+                const int vv = q / (kSV * Q), r = (q / Q) % kSV, c4 = q % Q;
+                const int p = p0 + vv;
+                float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (p < P) {
+                    const int v = s_box[p][1] + r, u = s_box[p][0] + 4 * c4;
+                    if (v >= 0 && v < nv) {
+                        const InT *row = y + ((size_t)p * nv + v) * nu;
 #pragma unroll
-            for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
+                        for (int k = 0; k < 4; ++k)
+                            if (u + k >= 0 && u + k < nu) e[k] = to_f(row[u + k]);
+                    }
+                }
+                tile4[q] = make_float4(e[0], e[1], e[2], e[3]);
+            }
+            __syncthreads();
+            if (active) {
+                for (int vv = 0; vv < kVG && p0 + vv < P; ++vv) {
+                    const int p = p0 + vv;
+                    const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+                    double fu, M;
+                    project_point(g, px, py, c, s, fu, M);
+                    const float dfv = (float)(M * g.vox * inv_dv);
+                    const float w = (float)(M * M * wconst);
+                    const float fuf = (float)fu;
+                    const float iuf = floorf(fuf);
+                    const float wu = fuf - iuf;
+                    const int lu = min(max((int)iuf - s_box[p][0], 0), kSU - 2);
+                    const int v0 = s_box[p][1];
+                    const float fv0f = (float)(M * pz0 * inv_dv + cv);
+                    const float *tv = tile + vv * kSV * kSU + lu;
+#pragma unroll
+                    for (int z = 0; z < kZC; ++z) {
+                        const float fv = fmaf((float)z, dfv, fv0f);
+                        const float ivf = floorf(fv);
+                        const float wv = fv - ivf;
+                        const int lv = min(max((int)ivf - v0, 0), kSV - 2);
+                        const float *t = tv + lv * kSU;
+                        const float a = fmaf(wu, t[1] - t[0], t[0]);
+                        const float b = fmaf(wu, t[kSU + 1] - t[kSU], t[kSU]);
+                        grp[z] = fmaf(w, fmaf(wv, b - a, a), grp[z]);
+                    }
+                }
+#pragma unroll
+                for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
+            }
         }
     }
+    if (!active) return;
     const double sc = in_scale ? (double)*in_scale : 1.0;
 #pragma unroll
     for (int z = 0; z < kZC; ++z) {
@@ -437,6 +728,8 @@ __global__ __launch_bounds__(256) void k_bp_par(GeomK g, const InT *__restrict__
 }
 
 // ----------------------------------------------------------------- F
+// Generic row filter: one workgroup per row, one output per lane (rows of
+// any length up to 4096).
 template <typename InT, typename OutT>
 __global__ __launch_bounds__(256) void k_ramp(const InT *__restrict__ q, OutT *__restrict__ out,
                                               const float *__restrict__ taps, int nu,
@@ -462,13 +755,66 @@ __global__ __launch_bounds__(256) void k_ramp(const InT *__restrict__ q, OutT *_
     }
 }
 
+// Register-blocked row filter: one wavefront per row, RB consecutive outputs
+// per lane (nu <= 64 RB).  For odd tap j the lane needs q[a-j] and q[a+j] for
+// its RB outputs; stepping j by two shifts both windows by two, so each step
+// reads four new values from LDS and does RB adds and RB FMAs.  The
+// symmetric, odd-only Ram-Lak taps (h[even] = 0) halve the work of a dense
+// convolution.  Four rows per workgroup.
+template <int RB, typename InT, typename OutT>
+__global__ __launch_bounds__(256) void k_ramp_rb(const InT *__restrict__ q, OutT *__restrict__ out,
+                                                 const float *__restrict__ taps, int nu, size_t rows,
+                                                 const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    constexpr int W = 64 * RB;                 // padded row length handled
+    constexpr int E = 4;                       // guard cells: the last window shift reads past +-W
+    __shared__ float qs[4][3 * W + 2 * E];     // [E + W zeros][row][W + E zeros]
+    __shared__ float hs[W];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const size_t row = (size_t)blockIdx.x * 4 + wv;
+    for (int i = threadIdx.x; i < W; i += 256) hs[i] = i < nu ? taps[i] : 0.0f;
+    float *qw = qs[wv];
+    for (int i = lane; i < 3 * W + 2 * E; i += 64) {
+        const int a = i - W - E;
+        qw[i] = (row < rows && a >= 0 && a < nu) ? to_f(q[row * nu + a]) : 0.0f;
+    }
+    __syncthreads();
+    if (row >= rows) return;
+    const int a0 = lane * RB;
+    const float *qc = qw + E + W + a0;         // q[a0 + r] = qc[r]
+    float acc[RB], L[RB], U[RB];
+    const float h0 = hs[0];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = h0 * qc[r];
+    // window for j = 1: L[r] = q[a0 + r - 1], U[r] = q[a0 + r + 1]
+#pragma unroll
+    for (int r = 0; r < RB; ++r) { L[r] = qc[r - 1]; U[r] = qc[r + 1]; }
+    for (int j = 1; j < nu; j += 2) {
+        const float h = hs[j];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = fmaf(h, L[r] + U[r], acc[r]);
+        // shift to j + 2
+#pragma unroll
+        for (int r = RB - 1; r >= 2; --r) L[r] = L[r - 2];
+        L[1] = qc[-j - 1];
+        L[0] = qc[-j - 2];
+#pragma unroll
+        for (int r = 0; r < RB - 2; ++r) U[r] = U[r + 2];
+        U[RB - 2] = qc[RB - 2 + j + 2];
+        U[RB - 1] = qc[RB - 1 + j + 2];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (a0 + r < nu) out[row * nu + a0 + r] = from_f<OutT>(acc[r]);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
 int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s) {
     const PadLayout &L = g->pad;
-    const size_t per_x = (size_t)2 * L.pz * L.rx + (size_t)g->k.nz * 2 * kPad;
-    const size_t per_y = (size_t)2 * L.pz * L.ry + (size_t)g->k.nz * 2 * kPad;
+    const size_t per_x = (size_t)2 * L.pz * L.rx + (size_t)g->k.nz * (L.rx - g->k.ny);
+    const size_t per_y = (size_t)2 * L.pz * L.ry + (size_t)g->k.nz * (L.ry - g->k.nx);
     const size_t tot = per_x * g->k.nx + per_y * g->k.ny;
     size_t blocks = (tot + 255) / 256;
     if (blocks > 8192) blocks = 8192;
@@ -512,11 +858,13 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
         return CT_ERR_UNSUPPORTED;
     }
     const uint32_t offy = (uint32_t)dy;
-    if (y_dtype == CT_F32) {
-        if (cone) hipLaunchKernelGGL((k_project<true, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
-        else hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
+    if (cone) {
+        // 64 x 4 ray tiles (block shape fixed by the staged kernel)
+        dim3 sgrid((g->k.nu + kTU - 1) / kTU, (g->k.nv + kTV - 1) / kTV, g->k.P), sblock(kTU, kTV);
+        if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
+        else hipLaunchKernelGGL((k_project_staged<__half>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
     } else {
-        if (cone) hipLaunchKernelGGL((k_project<true, __half>), grid, block, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
+        if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
         else hipLaunchKernelGGL((k_project<false, __half>), grid, block, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
     }
     CT_LAUNCH_CHECK();
@@ -545,8 +893,8 @@ int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *
     dim3 block(16, 16);
     if (cone) {
         dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC);
-        if (y_dtype == CT_F32) hipLaunchKernelGGL((k_bp_cone<float>), grid, block, 0, s, g->k, (const float *)y, x, in_scale, stop);
-        else hipLaunchKernelGGL((k_bp_cone<__half>), grid, block, 0, s, g->k, (const __half *)y, x, in_scale, stop);
+        if (y_dtype == CT_F32) hipLaunchKernelGGL((k_bp_cone_staged<float>), grid, block, 0, s, g->k, (const float *)y, x, in_scale, stop);
+        else hipLaunchKernelGGL((k_bp_cone_staged<__half>), grid, block, 0, s, g->k, (const __half *)y, x, in_scale, stop);
     } else {
         dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, 1);
         if (y_dtype == CT_F32) hipLaunchKernelGGL((k_bp_par<float>), grid, block, 0, s, g->k, (const float *)y, x, in_scale, stop);
@@ -563,6 +911,21 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
     if (shm > 64 * 1024) {
         set_error("ramp filter: detector rows longer than 4096 are not supported");
         return CT_ERR_UNSUPPORTED;
+    }
+    if (nu <= 64 * 8) {
+        // register-blocked path: RB outputs per lane, four rows per workgroup
+        const int rb = nu <= 128 ? 2 : nu <= 256 ? 4 : nu <= 384 ? 6 : 8;
+        dim3 rgrid((unsigned)((rows + 3) / 4)), rblock(256);
+#define CT_RAMP_RB(RBV)                                                                                           do {                                                                                                              if (q_dtype == CT_F32 && out_dtype == CT_F32)                                                                     hipLaunchKernelGGL((k_ramp_rb<RBV, float, float>), rgrid, rblock, 0, s, (const float *)q, (float *)out, g->d_ramp, nu, rows, stop);         else if (q_dtype == CT_F16 && out_dtype == CT_F16)                                                                hipLaunchKernelGGL((k_ramp_rb<RBV, __half, __half>), rgrid, rblock, 0, s, (const __half *)q, (__half *)out, g->d_ramp, nu, rows, stop);         else if (q_dtype == CT_F16 && out_dtype == CT_F32)                                                                hipLaunchKernelGGL((k_ramp_rb<RBV, __half, float>), rgrid, rblock, 0, s, (const __half *)q, (float *)out, g->d_ramp, nu, rows, stop);         else                                                                                                              hipLaunchKernelGGL((k_ramp_rb<RBV, float, __half>), rgrid, rblock, 0, s, (const float *)q, (__half *)out, g->d_ramp, nu, rows, stop);     } while (0)
+        switch (rb) {
+        case 2: CT_RAMP_RB(2); break;
+        case 4: CT_RAMP_RB(4); break;
+        case 6: CT_RAMP_RB(6); break;
+        default: CT_RAMP_RB(8); break;
+        }
+#undef CT_RAMP_RB
+        CT_LAUNCH_CHECK();
+        return CT_OK;
     }
     dim3 grid((unsigned)rows), block(256);
     if (q_dtype == CT_F32 && out_dtype == CT_F32)
