@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kTile = 256;       // elements per LDS tile (= block size)
 constexpr int kMaxBlk = 1024;    // upper bound on blocks of a sweep kernel
-constexpr int kMaxVec = 57;      // basis vectors staged in LDS per sweep (K+1); tile <= 60 KB
+constexpr int kMaxVec = 57;      // basis vectors per sweep (K+1), bounded by the 64-vector kernel
 
 // Device scalar state carved from the workspace.
 struct KState {
@@ -56,99 +56,112 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // -------------------------------------------------------- sweep kernels
-// MODE 0: partial d[j] = sum_i W[j][i] z[i] for j < nvec, and d[nvec] = sum z^2
-// MODE 1: z1 = zs*z - sum_j coef[j] W[j]  (stored to zout), partial d[j] = W[j].z1
-// MODE 2: z2 = z - sum_j coef[j] W[j]     (stored to zout), partial sum z2^2
-template <int MODE>
-__global__ __launch_bounds__(kTile) void k_cgs(const float *__restrict__ W, size_t ldw, int nvec,
-                                               const float *zin, float *zout,   // may alias (pass 3)
-                                               size_t n, const double *__restrict__ coef,
-                                               const double *__restrict__ zscale,
-                                               double *__restrict__ partials, int pstride,
+// CGS2 runs as streaming passes over chunks of at most NV basis vectors:
+//   k_mdot:  partial d[j] = W[j] . z for the chunk (columns vlo + j), and
+//            optionally ||z||^2 (column ncol);
+//   k_maxpy: z' = zs z - sum_j coef[j] W[j] for the chunk, in place or to a
+//            new array, optionally with ||z'||^2 (column ncol).
+// Work-items stride over 16-byte groups of four elements (the last partial
+// group goes element by element), every basis vector of the chunk is read
+// once per pass with 16-byte loads, and all sums accumulate in FP64.  Block
+// partials are reduced with a fixed shuffle tree and a fixed-order sum over
+// the four wavefronts, so results are reproducible run to run.
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&acc)[NV], int cnt, double nacc, bool nrm, int vlo, int ncol,
+                                               double *__restrict__ partials) {
+    __shared__ double red[4][NV + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        if (j < cnt) {
+            const double v = wave_sum(acc[j]);
+            if (lane == 0) red[wave][j] = v;
+        }
+    if (nrm) {
+        const double v = wave_sum(nacc);
+        if (lane == 0) red[wave][NV] = v;
+    }
+    __syncthreads();
+    for (int j = tid; j < cnt; j += 256)
+        partials[(size_t)(vlo + j) * kMaxBlk + blockIdx.x] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+    if (nrm && tid == 0)
+        partials[(size_t)ncol * kMaxBlk + blockIdx.x] = (red[0][NV] + red[1][NV]) + (red[2][NV] + red[3][NV]);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_mdot(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
+                                              const float *__restrict__ z, size_t n, int nrm, int ncol,
+                                              double *__restrict__ partials, const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    double acc[NV], nacc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    const float *Wc = W + (size_t)vlo * ldw;
+    const size_t n4 = n / 4;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
+        const float4 zv = reinterpret_cast<const float4 *>(z)[q];
+        const double z0 = zv.x, z1 = zv.y, z2 = zv.z, z3 = zv.w;
+        nacc += z0 * z0 + z1 * z1 + z2 * z2 + z3 * z3;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) {
+                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                acc[j] += (double)w.x * z0 + (double)w.y * z1 + (double)w.z * z2 + (double)w.w * z3;
+            }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)   // tail of fewer than four elements
+        for (size_t i = n4 * 4; i < n; ++i) {
+            const double zd = z[i];
+            nacc += zd * zd;
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                if (j < cnt) acc[j] += (double)Wc[(size_t)j * ldw + i] * zd;
+        }
+    block_partials<NV>(acc, cnt, nacc, nrm != 0, vlo, ncol, partials);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_maxpy(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
+                                               const float *zin, float *zout, size_t n,
+                                               const double *__restrict__ coef, const double *__restrict__ zscale,
+                                               int nrm, int ncol, double *__restrict__ partials,
                                                const int *__restrict__ stop) {
     if (stop && *stop) return;
-    extern __shared__ float sm[];
-    constexpr int LD = kTile + 1;
-    float *wt = sm;                                    // nvec x LD
-    float *zt = sm + (size_t)nvec * LD;                // kTile
-    double *cf = (double *)(sm + (((size_t)nvec * LD + kTile + 1) & ~(size_t)1));  // nvec
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (MODE >= 1)
-        for (int j = tid; j < nvec; j += kTile) cf[j] = coef[j];
-    const double zs = (MODE == 1 && zscale) ? *zscale : 1.0;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ double cf[NV];
+    for (int j = threadIdx.x; j < cnt; j += 256) cf[j] = coef[vlo + j];
+    __syncthreads();
+    const double zs = zscale ? *zscale : 1.0;
+    double acc[NV];
     double nacc = 0.0;
-    const int ndot = MODE == 0 ? nvec + 1 : nvec;      // MODE 0 adds ||z||^2
-    __syncthreads();
-    for (size_t t0 = (size_t)blockIdx.x * kTile; t0 < n; t0 += (size_t)gridDim.x * kTile) {
-        const size_t i = t0 + tid;
-        const bool ok = i < n;
-        // eight loads in flight per thread before the LDS stores
-        float zv = ok ? zin[i] : 0.0f;
-        int j8 = 0;
-        for (; j8 + 8 <= nvec; j8 += 8) {
-            float v[8];
+    const float *Wc = W + (size_t)vlo * ldw;
+    const size_t n4 = n / 4;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
+        const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
+        double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = ok ? W[(size_t)(j8 + u) * ldw + i] : 0.0f;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) wt[(j8 + u) * LD + tid] = v[u];
-        }
-        for (; j8 < nvec; ++j8) wt[j8 * LD + tid] = ok ? W[(size_t)j8 * ldw + i] : 0.0f;
-        if (MODE >= 1) {
-            double u = zs * (double)zv;
-            for (int j = 0; j < nvec; ++j) u -= cf[j] * (double)wt[j * LD + tid];
-            zv = ok ? (float)u : 0.0f;
-            if (ok) zout[i] = zv;
-        }
-        if (MODE == 2) {
-            nacc += (double)zv * (double)zv;
-            continue;
-        }
-        zt[tid] = zv;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = lane + 64 * q;
-            if (j < ndot) {
-                double a = 0.0;
-                const int tb = wave * 64;
-                if (j < nvec) {
-                    const float *wr = wt + j * LD + tb;
-                    for (int t = 0; t < 64; ++t) a += (double)wr[t] * (double)zt[tb + t];
-                } else {
-                    for (int t = 0; t < 64; ++t) a += (double)zt[tb + t] * (double)zt[tb + t];
-                }
-                acc[q] += a;
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) {
+                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                const double c = cf[j];
+                u0 -= c * (double)w.x; u1 -= c * (double)w.y; u2 -= c * (double)w.z; u3 -= c * (double)w.w;
             }
-        }
-        __syncthreads();
+        const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
+        reinterpret_cast<float4 *>(zout)[q] = o;
+        nacc += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
     }
-    if (MODE == 2) {
-        double v = wave_sum(nacc);
-        __shared__ double red2[kTile / 64];
-        if (lane == 0) red2[wave] = v;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < kTile / 64; ++w) s += red2[w];
-            partials[blockIdx.x] = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (size_t i = n4 * 4; i < n; ++i) {
+            double u = zs * (double)zin[i];
+            for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)Wc[(size_t)j * ldw + i];
+            const float o = (float)u;
+            zout[i] = o;
+            nacc += (double)o * o;
         }
-        return;
-    }
-    // combine the four waves' partial dots in a fixed order
-    __syncthreads();
-    double *red = (double *)sm;   // 4 x 256 doubles fits in the wt region
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int j = lane + 64 * q;
-        if (j < ndot) red[wave * 256 + j] = acc[q];
-    }
-    __syncthreads();
-    for (int j = tid; j < ndot; j += kTile) {
-        double s = 0.0;
-        for (int w = 0; w < kTile / 64; ++w) s += red[w * 256 + j];
-        partials[(size_t)j * kMaxBlk + blockIdx.x] = s;
-    }
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    block_partials<NV>(acc, 0, nacc, nrm != 0, vlo, ncol, partials);
 }
 
 // out[j] = sum over b < nblk of partials[j][b], for j < count.  One wavefront
@@ -443,13 +456,6 @@ int grid_1d(size_t n) {
     return (int)b;
 }
 
-size_t cgs_lds_bytes(int nvec) {
-    const size_t f = (size_t)nvec * (kTile + 1) + kTile + 2;
-    size_t bytes = f * 4 + (size_t)nvec * 8 + 16;
-    const size_t red = 4 * 256 * 8;   // wave-combine buffer reuses the front
-    return bytes > red ? bytes : red;
-}
-
 struct Carver {
     char *base;
     size_t off = 0;
@@ -512,21 +518,66 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
     return c.off;
 }
 
+constexpr int kCgsChunk = 16;   // basis vectors per streaming pass (register budget)
+
+static int launch_mdot(const GmresBufs &b, int vlo, int cnt, const float *z, bool nrm, int ncol, hipStream_t s) {
+    const int nblk = sweep_blocks(b.len / 4 + 1);
+    const int *stop = b.st.flags + F_STOP;
+#define CT_MDOT(NVV) \
+    hipLaunchKernelGGL(k_mdot<NVV>, dim3(nblk), dim3(256), 0, s, b.W, b.ldw, vlo, cnt, z, b.len, (int)nrm, ncol, b.st.partials, stop)
+    if (cnt <= 1) CT_MDOT(1);
+    else if (cnt <= 4) CT_MDOT(4);
+    else if (cnt <= 8) CT_MDOT(8);
+    else CT_MDOT(16);
+#undef CT_MDOT
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+static int launch_maxpy(const GmresBufs &b, int vlo, int cnt, const float *zin, float *zout, const double *coef,
+                        const double *zscale, bool nrm, int ncol, hipStream_t s) {
+    const int nblk = sweep_blocks(b.len / 4 + 1);
+    const int *stop = b.st.flags + F_STOP;
+#define CT_MAXPY(NVV) \
+    hipLaunchKernelGGL(k_maxpy<NVV>, dim3(nblk), dim3(256), 0, s, b.W, b.ldw, vlo, cnt, zin, zout, b.len, coef, zscale, \
+                       (int)nrm, ncol, b.st.partials, stop)
+    if (cnt <= 1) CT_MAXPY(1);
+    else if (cnt <= 4) CT_MAXPY(4);
+    else if (cnt <= 8) CT_MAXPY(8);
+    else CT_MAXPY(16);
+#undef CT_MAXPY
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+// Partial sums for every block of a pass land in the same columns, so every
+// pass over a vector range uses the same number of blocks (sweep_blocks of
+// len/4 + 1) and the reduction kernels read that many.
+//   mode 0: d[j] = W[j].z (j < nvec) and ||z||^2 in column nvec
+//   mode 1: z1 = zs z - sum coef W (to zout), then d[j] = W[j].z1
+//   mode 2: z2 = z - sum coef W (to zout) and ||z2||^2 in column 0
 int run_cgs(int mode, const GmresBufs &b, int nvec, const float *zin, float *zout, const double *coef,
             const double *zscale, hipStream_t s) {
-    const int nblk = sweep_blocks(b.len);
-    const size_t shm = cgs_lds_bytes(nvec);
-    const int *stop = b.st.flags + F_STOP;
-    if (mode == 0)
-        hipLaunchKernelGGL(k_cgs<0>, dim3(nblk), dim3(kTile), shm, s, b.W, b.ldw, nvec, zin, zout, b.len, coef, zscale,
-                           b.st.partials, b.st.pstride, stop);
-    else if (mode == 1)
-        hipLaunchKernelGGL(k_cgs<1>, dim3(nblk), dim3(kTile), shm, s, b.W, b.ldw, nvec, zin, zout, b.len, coef, zscale,
-                           b.st.partials, b.st.pstride, stop);
-    else
-        hipLaunchKernelGGL(k_cgs<2>, dim3(nblk), dim3(kTile), shm, s, b.W, b.ldw, nvec, zin, zout, b.len, coef, zscale,
-                           b.st.partials, b.st.pstride, stop);
-    CT_LAUNCH_CHECK();
+    if (mode == 0) {
+        if (nvec == 0) return launch_mdot(b, 0, 0, zin, true, 0, s);
+        for (int lo = 0; lo < nvec; lo += kCgsChunk) {
+            const int cnt = nvec - lo < kCgsChunk ? nvec - lo : kCgsChunk;
+            CT_TRY(launch_mdot(b, lo, cnt, zin, lo == 0, nvec, s));
+        }
+        return CT_OK;
+    }
+    if (nvec == 0) return launch_maxpy(b, 0, 0, zin, zout, coef, nullptr, true, 0, s);
+    for (int lo = 0; lo < nvec; lo += kCgsChunk) {
+        const int cnt = nvec - lo < kCgsChunk ? nvec - lo : kCgsChunk;
+        const bool last = lo + cnt >= nvec;
+        CT_TRY(launch_maxpy(b, lo, cnt, lo == 0 ? zin : zout, zout, coef, lo == 0 ? zscale : nullptr,
+                            mode == 2 && last, 0, s));
+    }
+    if (mode == 1)
+        for (int lo = 0; lo < nvec; lo += kCgsChunk) {
+            const int cnt = nvec - lo < kCgsChunk ? nvec - lo : kCgsChunk;
+            CT_TRY(launch_mdot(b, lo, cnt, zout, false, 0, s));
+        }
     return CT_OK;
 }
 
@@ -617,7 +668,7 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
     const double qc = f16 ? fp16_scale_const(g) : 0.0;
     KState &st = bf.st;
     const int *stop = st.flags + F_STOP;
-    const int nblk = sweep_blocks(bf.len);
+    const int nblk = sweep_blocks(bf.len / 4 + 1);
     OpScratch &op = bf.opA;
     // flags must start clear: the init kernel writes them, but the sweep that
     // precedes it reads the stop flag (a kernel, not a memset, so the chain

@@ -325,9 +325,35 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
 // not fit, take the direct path.
 constexpr int kTU = 16, kTV = 16;     // rays per workgroup
 constexpr int kPC = 4;                // planes per staged chunk
-constexpr int kSR = 24, kSC = 36;     // staged rows / columns per plane (kSC % 4 == 0)
+constexpr int kSR = 32, kSC = 48;     // staged row slots / row stride per plane; 48 = 16 (mod 32 banks)
+constexpr int kNQ = 10;               // staged 16-byte columns per row (40 floats)
+constexpr int kSlots = (kPC * kSR * kNQ + 255) / 256;   // staging cells per thread
+static_assert(kSR == 32, "row slots are decoded with shifts");
 constexpr int kMaxChunks = 512;       // planes up to 2048
-constexpr int kQPT = 4;               // 16-byte cells per thread per chunk (upper bound)
+constexpr int kVGrp = 8;              // consecutive views kept on one XCD
+
+// Workgroup order: the hardware deals workgroups to the eight XCDs in turn,
+// so the flat index is remapped such that each XCD receives a contiguous
+// range of logical work, ordered [view group][tile][view in group].  The
+// workgroups resident on one XCD then project the same tiles for
+// neighbouring views, whose footprints overlap, and the XCD's L2 serves the
+// overlap.  Returns false for the padding workgroups of the last XCD.
+__device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int &tu, int &tv, int &p) {
+    const int ntiles = ntu * ntv;
+    const int ngrp = (P + kVGrp - 1) / kVGrp;
+    const int nlog = ngrp * ntiles * kVGrp;
+    const int per = (nlog + 7) / 8;
+    const int b = blockIdx.x;
+    const int lg = (b & 7) * per + (b >> 3);
+    if ((b >> 3) >= per || lg >= nlog) return false;
+    const int vv = lg % kVGrp;
+    const int t = (lg / kVGrp) % ntiles;
+    const int grp = lg / (kVGrp * ntiles);
+    p = grp * kVGrp + vv;
+    tu = t % ntu;
+    tv = t / ntu;
+    return p < P;
+}
 
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
@@ -335,13 +361,15 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
                                                         const float *__restrict__ out_scale,
                                                         const int *__restrict__ stop) {
     if (stop && *stop) return;
+    int tu, tv, p;
+    if (!xcd_tile((g.nu + kTU - 1) / kTU, (g.nv + kTV - 1) / kTV, g.P, tu, tv, p)) return;
     __shared__ float4 tile4[kPC * kSR * kSC / 4];
-    __shared__ short s_box[kMaxChunks][4];   // b0 (aligned to 4, -1: direct), c0, rows, 16-byte columns
+    __shared__ short s_box[kMaxChunks][3];   // b0 (aligned to 4, -1: direct), c0, rows
     __shared__ float s_corner[4][4];
     __shared__ int s_axes, s_jlo, s_jhi;
     const float *tile = (const float *)tile4;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx;
-    const int au0 = blockIdx.x * kTU, av0 = blockIdx.y * kTV, p = blockIdx.z;
+    const int au0 = tu * kTU, av0 = tv * kTV;
     const int au = au0 + tx, av = av0 + ty;
     const bool active = au < g.nu && av < g.nv;
     if (tid == 0) { s_axes = 0; s_jlo = 0x7fffffff; s_jhi = -1; }
@@ -400,37 +428,45 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
         const int b1 = min((int)floorf(bmax) + 2, (int)Rw - 1);
         const int c0 = max((int)floorf(cmin) - 1, 0);
         const int c1 = min((int)floorf(cmax) + 2, nrows - 1);
-        const int nr = c1 - c0 + 1, nq = (b1 - b0) / 4 + 1;
-        const bool fits = nr <= kSR && 4 * nq <= kSC && kPC * nr * nq <= kQPT * kTU * kTV;
+        const int nr = c1 - c0 + 1;
+        const bool fits = nr <= kSR && b1 - b0 < 4 * kNQ;
         s_box[c][0] = (short)(fits ? b0 : -1);
         s_box[c][1] = (short)c0;
         s_box[c][2] = (short)nr;
-        s_box[c][3] = (short)nq;
     }
-    float4 pre[kQPT];
+    // staging cells of this thread, fixed for the whole block: cell q covers
+    // 16-byte column q % kNQ of row slot q / kNQ (= plane * kSR + row)
+    uint32_t goff[kSlots];     // element offset within the chunk's box
+    int lrow[kSlots];          // row within the plane (skip when >= rows)
+    int loff[kSlots];          // float4 index in the tile (-1: none)
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        const int q = tid + 256 * k;
+        const int rg = q / kNQ, c4 = q - rg * kNQ;
+        const int pl = rg / kSR, r = rg - pl * kSR;
+        const bool ok = q < kPC * kSR * kNQ;
+        goff[k] = __umul24((uint32_t)pl, S) + __umul24((uint32_t)r, Rw) + 4u * (uint32_t)c4;
+        lrow[k] = ok ? r + kSR * pl : (kPC * kSR) | (kSR - 1);   // invalid: plane kPC, never < nplanes
+        loff[k] = ok ? (rg * kSC) / 4 + c4 : -1;
+    }
+    // cells a chunk does not need are pointed past the end of the buffer:
+    // the range check returns zeros, so the loads need neither branches nor
+    // zero fill
+    float4 pre[kSlots];
     auto fetch = [&](int c) {
         const int ja = jlo + c * kPC;
-        const int b0 = s_box[c][0], c0 = s_box[c][1], nr = s_box[c][2], nq = s_box[c][3];
-        const int cells = kPC * nr * nq;
+        const int b0 = s_box[c][0], c0 = s_box[c][1], nr = s_box[c][2];
+        const uint32_t cbase = (base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0) * 4u;
+        const int nplanes = min(kPC, Na - ja);
+        // valid iff row < rows and plane < nplanes: lrow = row + kSR * plane
 #pragma unroll
-        for (int k = 0; k < kQPT; ++k) {
-            const int q = tid + k * kTU * kTV;
-            pre[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (b0 >= 0 && q < cells) {
-                const int pl = q / (nr * nq);
-                const int rem = q - pl * nr * nq;
-                const int r = rem / nq, c4 = rem - r * nq;
-                const int j = ja + pl;
-                if (j < Na) {
-                    const uint32_t off = base + __umul24((uint32_t)j, S) + __umul24((uint32_t)(c0 + r), Rw) +
-                                         (uint32_t)(b0 + 4 * c4);
-                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off * 4u), 0, 0);
-                    pre[k] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]),
-                                         __builtin_bit_cast(float, (uint32_t)w[1]),
-                                         __builtin_bit_cast(float, (uint32_t)w[2]),
-                                         __builtin_bit_cast(float, (uint32_t)w[3]));
-                }
-            }
+        for (int k = 0; k < kSlots; ++k) {
+            const int pl = lrow[k] >> 5, r = lrow[k] & (kSR - 1);
+            const bool ok = b0 >= 0 && r < nr && pl < nplanes;
+            const uint32_t boff = ok ? cbase + goff[k] * 4u : 0xFFFFFFF0u;
+            const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff, 0, 0);
+            pre[k] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]), __builtin_bit_cast(float, (uint32_t)w[1]),
+                                 __builtin_bit_cast(float, (uint32_t)w[2]), __builtin_bit_cast(float, (uint32_t)w[3]));
         }
     };
     __syncthreads();   // boxes visible
@@ -438,41 +474,41 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     double acc = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int ja = jlo + c * kPC;
-        const int b0 = s_box[c][0], c0 = s_box[c][1], nr = s_box[c][2], nq = s_box[c][3];
-        const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
+        const int b0 = s_box[c][0], c0 = s_box[c][1];
         if (b0 >= 0) {
             __syncthreads();   // previous chunk's readers are done with the tile
-            const int cells = kPC * nr * nq;
 #pragma unroll
-            for (int k = 0; k < kQPT; ++k) {
-                const int q = tid + k * kTU * kTV;
-                if (q < cells) {
-                    const int pl = q / (nr * nq);
-                    const int rem = q - pl * nr * nq;
-                    const int r = rem / nq, c4 = rem - r * nq;
-                    tile4[((pl * kSR + r) * kSC) / 4 + c4] = pre[k];
-                }
-            }
+            for (int k = 0; k < kSlots; ++k)
+                if (loff[k] >= 0) tile4[loff[k]] = pre[k];
             __syncthreads();
         }
         if (c + 1 < nch) fetch(c + 1);
+        const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
         if (b0 < 0) {      // box too large: direct loads for this chunk
             if (jf <= jb) acc += direct_samples<true>(R, rs, base, S, Rw, jf, jb);
             continue;
         }
+        // the four planes of the chunk, unrolled; each lane masks the planes
+        // outside its own range
+        const int rb = -(c0 * kSC + b0);
         float grp = 0.0f;
-        for (int j = jf; j <= jb; ++j) {
-            const float fj = (float)j;
-            const float fb = fmaf(fj, R.gb, R.fb0);
-            const float fc = fmaf(fj, R.gc, R.fc0);
-            const float ibf = floorf(fb), icf = floorf(fc);
-            const float wb = fb - ibf, wc = fc - icf;
-            const int o = ((j - ja) * kSR + ((int)icf - c0)) * kSC + ((int)ibf - b0);
-            const float t00 = tile[o], t01 = tile[o + 1];
-            const float t10 = tile[o + kSC], t11 = tile[o + kSC + 1];
-            const float a0 = fmaf(wb, t01 - t00, t00);
-            const float a1 = fmaf(wb, t11 - t10, t10);
-            grp += fmaf(wc, a1 - a0, a0);
+#pragma unroll
+        for (int pl = 0; pl < kPC; ++pl) {
+            const int j = ja + pl;
+            if (j >= jf && j <= jb) {
+                // padded coordinates are positive here (>= kPad - 1 at the
+                // first and last sampled planes), so truncation is floor
+                const float fj = (float)j;
+                const float fb = fmaf(fj, R.gb, R.fb0);
+                const float fc = fmaf(fj, R.gc, R.fc0);
+                const float wb = __builtin_amdgcn_fractf(fb), wc = __builtin_amdgcn_fractf(fc);
+                const int o = pl * kSR * kSC + rb + (int)__umul24((uint32_t)(int)fc, (uint32_t)kSC) + (int)fb;
+                const float t00 = tile[o], t01 = tile[o + 1];
+                const float t10 = tile[o + kSC], t11 = tile[o + kSC + 1];
+                const float a0 = fmaf(wb, t01 - t00, t00);
+                const float a1 = fmaf(wb, t11 - t10, t10);
+                grp += fmaf(wc, a1 - a0, a0);
+            }
         }
         acc += (double)grp;
     }
@@ -662,19 +698,19 @@ __global__ __launch_bounds__(256) void k_bp_cone_staged(GeomK g, const InT *__re
                     project_point(g, px, py, c, s, fu, M);
                     const float dfv = (float)(M * g.vox * inv_dv);
                     const float w = (float)(M * M * wconst);
-                    const float fuf = (float)fu;
-                    const float iuf = floorf(fuf);
-                    const float wu = fuf - iuf;
-                    const int lu = min(max((int)iuf - s_box[p][0], 0), kSU - 2);
-                    const int v0 = s_box[p][1];
-                    const float fv0f = (float)(M * pz0 * inv_dv + cv);
+                    // coordinates relative to the staged box are >= 1 (one
+                    // cell of margin), so truncation is floor; the clamps only
+                    // guard the tile against rounding
+                    const float fur = (float)(fu - (double)s_box[p][0]);
+                    const float wu = __builtin_amdgcn_fractf(fur);
+                    const int lu = min(max((int)fur, 0), kSU - 2);
+                    const float fv0r = (float)(M * pz0 * inv_dv + cv - (double)s_box[p][1]);
                     const float *tv = tile + vv * kSV * kSU + lu;
 #pragma unroll
                     for (int z = 0; z < kZC; ++z) {
-                        const float fv = fmaf((float)z, dfv, fv0f);
-                        const float ivf = floorf(fv);
-                        const float wv = fv - ivf;
-                        const int lv = min(max((int)ivf - v0, 0), kSV - 2);
+                        const float fv = fmaf((float)z, dfv, fv0r);
+                        const float wv = __builtin_amdgcn_fractf(fv);
+                        const int lv = min(max((int)fv, 0), kSV - 2);
                         const float *t = tv + lv * kSU;
                         const float a = fmaf(wu, t[1] - t[0], t[0]);
                         const float b = fmaf(wu, t[kSU + 1] - t[kSU], t[kSU]);
@@ -859,8 +895,15 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
     }
     const uint32_t offy = (uint32_t)dy;
     if (cone) {
-        // 64 x 4 ray tiles (block shape fixed by the staged kernel)
-        dim3 sgrid((g->k.nu + kTU - 1) / kTU, (g->k.nv + kTV - 1) / kTV, g->k.P), sblock(kTU, kTV);
+        // 16 x 16 ray tiles, flat grid remapped per XCD inside the kernel
+        const long ntiles = (long)((g->k.nu + kTU - 1) / kTU) * ((g->k.nv + kTV - 1) / kTV);
+        const long nlog = (long)((g->k.P + kVGrp - 1) / kVGrp) * ntiles * kVGrp;
+        const long per = (nlog + 7) / 8;
+        if (8 * per > 2147483647L) {
+            set_error("launch_project: too many ray tiles");
+            return CT_ERR_UNSUPPORTED;
+        }
+        dim3 sgrid((unsigned)(8 * per)), sblock(kTU, kTV);
         if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
         else hipLaunchKernelGGL((k_project_staged<__half>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
     } else {
