@@ -34,12 +34,18 @@ if ROOT not in sys.path:
 ITERS = 30
 PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak, FLOP/s
 PEAK_HBM = 8.0e12               # bytes/s
-# algorithmic work per unit: Joseph sample = 2 coordinate
-# FMAs + 2 fractions + 3 two-flop lerps + 1 accumulate = 12 FLOP;
-# voxel-driven update = 1 coordinate FMA + 1 fraction + 3 lerps + weighted
-# accumulate = 10 FLOP
-FLOP_PER_A_UPDATE = 12.0
-FLOP_PER_B_UPDATE = 10.0
+# algorithmic work per unit: a Joseph sample is 2 coordinate FMAs (4) + 2
+# fractions (2) + 3 linear interpolations of a sub and an FMA (9) + 1
+# accumulate = 16 FLOP; a voxel-driven update is 1 coordinate FMA (2) + 1
+# fraction (1) + 3 interpolations (9) + a weighted accumulate FMA (2) = 14
+FLOP_PER_A_UPDATE = 16.0
+FLOP_PER_B_UPDATE = 14.0
+# HBM traffic of one projector launch on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes over this benchmark, each scaled by what
+# the counter reads for a 256 MiB copy (FETCH x2.0, WRITE x1.0); valid only
+# for the projector source it was measured on (hash of the kernel's text)
+A_TRAFFIC_BYTES = 6336540774
+A_TRAFFIC_SRC = "d6ed0f2f71d21fe8"
 
 
 def log(*a):
@@ -58,18 +64,14 @@ def make_inputs(ct, desc, g, torch):
     return torch.from_numpy(b).cuda(), vol * mu
 
 
-def time_op(fn, stream, torch, reps=5):
-    """Average duration of fn() on `stream`, from HIP events on that stream."""
-    fn()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
+def projector_src_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2201_07408_amd", "csrc", "ct_projectors.hip")
+    src = open(path).read()
+    a, b = src.find("struct RaySetup {"), src.find("__device__ __forceinline__ uint32_t clampu")
+    if a < 0 or b < 0:
+        return None
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def cpu_baseline(desc, b_host, x_phantom):
@@ -140,13 +142,18 @@ def main():
     log("bench: generating inputs")
     b, x_phantom = make_inputs(ct, desc, g, torch)
     sdt = torch.float16 if args.sino_dtype == "f16" else torch.float32
-    stream = torch.cuda.current_stream()
 
     log("bench: warmup")
     for _ in range(args.warmup):
         r = ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=sdt)
     torch.cuda.synchronize()
     log("bench: timed solves")
+    # kernel classes are timed inside the timed region by the library's
+    # event pairs, recorded on the stream the kernels run on
+    lib = ct.api.L.load()
+    lib.ct_profile_reset()
+    lib.ct_profile_enable(1)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
     for _ in range(args.steps):
@@ -154,24 +161,28 @@ def main():
         done += r.iters_done
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    lib.ct_profile_enable(0)
     ms_per_step = dt / args.steps * 1e3
     value = done / dt
+    kern = {}
+    for name in ("A", "B", "F", "CGS"):
+        n_l, t_l = ctypes.c_long(), ctypes.c_double()
+        lib.ct_profile_read(name.encode(), ctypes.byref(n_l), ctypes.byref(t_l))
+        kern[name] = (n_l.value, t_l.value / 1e3)
+    t_a = kern["A"][1] / max(kern["A"][0], 1)
+    t_b = kern["B"][1] / max(kern["B"][0], 1)
+    t_f = kern["F"][1] / max(kern["F"][0], 1)
 
-    # dominant kernels, timed with events on the stream they run on
-    log("bench: operator timing")
     # exact update counts of this geometry, written by the oracle's counter
     # (tests/golden/make_update_counts.py); read as data, the oracle is not run
     counts_path = os.path.join(ROOT, "tests", "golden", "update_counts.json")
     counts = json.load(open(counts_path))["w3"]
     a_upd, b_upd = counts["A_updates"], counts["B_updates"]
-    xw = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
-    yw = ct.ct_project_A(g, xw)
-    xo = torch.empty_like(xw)
-    t_a = time_op(lambda: ct.ct_project_A(g, xw, out=yw), stream, torch)
-    t_b = time_op(lambda: ct.ct_backproject_B(g, yw, out=xo), stream, torch)
-    t_f = time_op(lambda: ct.ct_ramp_filter(g, yw), stream, torch)
     dom = ("A", t_a, a_upd, FLOP_PER_A_UPDATE) if t_a >= t_b else ("B_un", t_b, b_upd, FLOP_PER_B_UPDATE)
     achieved = dom[2] * dom[3] / dom[1]
+    traffic = None
+    if dom[0] == "A" and projector_src_hash() == A_TRAFFIC_SRC:
+        traffic = A_TRAFFIC_BYTES
     line = {
         "metric": "BA-GMRES iters/s at 256^3 cone-beam; A/B voxel-ray updates/s; rel err vs FP64",
         "value": round(value, 3),
@@ -191,10 +202,11 @@ def main():
                    "iters_per_step": ITERS, "sino_dtype": args.sino_dtype},
         "A_updates_per_s": a_upd / t_a,
         "B_updates_per_s": b_upd / t_b,
-        "op_ms": {"A": t_a * 1e3, "B_un": t_b * 1e3, "F": t_f * 1e3},
+        "kernel_ms_per_launch": {"A": t_a * 1e3, "B_un": t_b * 1e3, "F": t_f * 1e3,
+                                 "CGS_per_iteration": kern["CGS"][1] / max(done, 1) * 1e3},
         "roofline": {"bound": "alu", "kernel": dom[0], "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": None},
+                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
     }
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

@@ -186,6 +186,18 @@ int ct_cgls(const ct_geometry *g, const float *b, float *x,
             const ct_solver_opts *opts, void *ws, size_t ws_bytes,
             double *res_hist, int *iters_done, void *stream);
 
+/* Kernel timing (opt-in tracing).  When enabled, every projector,
+ * back-projector, filter and orthogonalisation kernel launched by the
+ * library is bracketed by two hipEvents recorded on the stream it runs on.
+ * ct_profile_read synchronises those events and returns, for the kernel
+ * class `name` ("A", "AT", "B", "F", "CGS", "ARNOLDI"), the number of
+ * launches and their summed duration in milliseconds since the last reset.
+ * Recording stops when 65536 launches are held.  Not for graph capture.
+ * Errors: CT_ERR_ARG for an unknown name or NULL outputs, CT_ERR_HIP. */
+int ct_profile_enable(int on);
+int ct_profile_reset(void);
+int ct_profile_read(const char *name, long *launches, double *total_ms);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *ct_last_error(void);
 

@@ -19,6 +19,7 @@ EXPORTS = [
     "ct_op_workspace_bytes", "ct_project_A", "ct_backproject_B",
     "ct_backproject_AT", "ct_ramp_filter", "ct_solver_workspace_bytes",
     "ct_ba_gmres", "ct_ab_gmres", "ct_cgls", "ct_last_error", "ct_version",
+    "ct_profile_enable", "ct_profile_reset", "ct_profile_read",
 ]
 
 
@@ -75,6 +76,9 @@ def load(path: str = LIBPATH):
         "ct_ba_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_ab_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_cgls": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_profile_enable": ([i], i),
+        "ct_profile_reset": ([], i),
+        "ct_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp], i),
         "ct_last_error": ([], ctypes.c_char_p),
         "ct_version": ([], ctypes.c_char_p),
     }

@@ -109,6 +109,23 @@ struct ct_geometry {
 
 namespace ct {
 
+// -------------------------------------------------------------- profiling
+// Brackets one kernel launch with two events on its stream when kernel
+// timing is enabled (ct_profile_enable); a no-op otherwise.
+enum { PROF_A = 0, PROF_AT, PROF_B, PROF_F, PROF_CGS, PROF_ARNOLDI, kProfClasses };
+class ProfScope {
+  public:
+    ProfScope(int cls, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    int cls_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
 // --------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return CT_OK or CT_ERR_HIP.  `stop`, when
 // non-null, points to a device flag; kernels exit at once when it is set.

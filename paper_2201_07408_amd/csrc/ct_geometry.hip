@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "ct_common.h"
 
@@ -27,9 +28,97 @@ int launch_fill(float *p, size_t n, float v, hipStream_t s) {
     return CT_OK;
 }
 
+// ------------------------------------------------------------- profiling
+namespace {
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+long g_prof_launches[kProfClasses] = {};
+double g_prof_ms[kProfClasses] = {};
+const char *g_prof_names[kProfClasses] = {"A", "AT", "B", "F", "CGS", "ARNOLDI"};
+constexpr size_t kProfMax = 65536;
+
+hipEvent_t pool_take() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// fold finished records into the totals; caller holds the lock
+int prof_drain() {
+    for (ProfRec &r : g_prof_recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            set_error("ct_profile: event timing failed");
+            return CT_ERR_HIP;
+        }
+        g_prof_launches[r.cls] += 1;
+        g_prof_ms[r.cls] += ms;
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_recs.clear();
+    return CT_OK;
+}
+}  // namespace
+
+ProfScope::ProfScope(int cls, hipStream_t s) : cls_(cls), s_(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on || g_prof_recs.size() >= kProfMax) return;
+    a_ = pool_take();
+    b_ = pool_take();
+    if (!a_ || !b_ || hipEventRecord(a_, s_) != hipSuccess) { a_ = b_ = nullptr; return; }
+}
+
+ProfScope::~ProfScope() {
+    if (!a_) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (hipEventRecord(b_, s_) == hipSuccess) g_prof_recs.push_back(ProfRec{cls_, a_, b_});
+}
+
 }  // namespace ct
 
 using namespace ct;
+
+extern "C" int ct_profile_enable(int on) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_profile_reset(void) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    CT_TRY(prof_drain());
+    for (int i = 0; i < kProfClasses; ++i) { g_prof_launches[i] = 0; g_prof_ms[i] = 0.0; }
+    return CT_OK;
+}
+
+extern "C" int ct_profile_read(const char *name, long *launches, double *total_ms) {
+    clear_error();
+    CT_ARG_CHECK(name && launches && total_ms, "ct_profile_read: NULL argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    CT_TRY(prof_drain());
+    for (int i = 0; i < kProfClasses; ++i)
+        if (std::strcmp(name, g_prof_names[i]) == 0) {
+            *launches = g_prof_launches[i];
+            *total_ms = g_prof_ms[i];
+            return CT_OK;
+        }
+    set_error("ct_profile_read: unknown kernel class");
+    return CT_ERR_ARG;
+}
 
 extern "C" const char *ct_last_error(void) { return g_last_error.c_str(); }
 

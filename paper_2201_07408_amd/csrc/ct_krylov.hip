@@ -521,6 +521,7 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
 constexpr int kCgsChunk = 16;   // basis vectors per streaming pass (register budget)
 
 static int launch_mdot(const GmresBufs &b, int vlo, int cnt, const float *z, bool nrm, int ncol, hipStream_t s) {
+    ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
 #define CT_MDOT(NVV) \
@@ -536,6 +537,7 @@ static int launch_mdot(const GmresBufs &b, int vlo, int cnt, const float *z, boo
 
 static int launch_maxpy(const GmresBufs &b, int vlo, int cnt, const float *zin, float *zout, const double *coef,
                         const double *zscale, bool nrm, int ncol, hipStream_t s) {
+    ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
 #define CT_MAXPY(NVV) \

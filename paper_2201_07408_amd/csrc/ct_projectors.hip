@@ -894,6 +894,7 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
         return CT_ERR_UNSUPPORTED;
     }
     const uint32_t offy = (uint32_t)dy;
+    ProfScope prof(PROF_A, s);
     if (cone) {
         // 16 x 16 ray tiles, flat grid remapped per XCD inside the kernel
         const long ntiles = (long)((g->k.nu + kTU - 1) / kTU) * ((g->k.nv + kTV - 1) / kTV);
@@ -916,6 +917,7 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
 
 int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx, float *vy,
                      const int *stop, hipStream_t s) {
+    ProfScope prof(PROF_AT, s);
     dim3 grid, block;
     ray_grid(g, grid, block);
     const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
@@ -933,6 +935,7 @@ int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx
 int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *x, const float *in_scale,
                        const int *stop, hipStream_t s) {
     const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
+    ProfScope prof(PROF_B, s);
     dim3 block(16, 16);
     if (cone) {
         dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC);
@@ -950,6 +953,7 @@ int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *
 int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int out_dtype, size_t rows,
                 const int *stop, hipStream_t s) {
     const int nu = g->k.nu;
+    ProfScope prof(PROF_F, s);
     const size_t shm = sizeof(float) * 4 * (size_t)nu;
     if (shm > 64 * 1024) {
         set_error("ramp filter: detector rows longer than 4096 are not supported");
