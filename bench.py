@@ -76,26 +76,26 @@ def projector_src_hash():
 
 def cpu_baseline(desc, b_host, x_phantom):
     """FP64 oracle BA-GMRES (ramp) on a bounded sample: the same volume and
-    detector with every 30th view (12 of 360), 2 iterations.  The operator
+    detector with every 8th view (45 of 360), 3 iterations.  The operator
     cost is linear in the number of views, so seconds per full iteration are
-    estimated as (sample seconds per iteration) * 30."""
+    estimated as (sample seconds per iteration) * 8."""
     import oracle
     from synth.geometry import GeometryDesc
-    sub = 30
+    sub = 8
     angles = [2 * math.pi * p / desc.n_views for p in range(0, desc.n_views, sub)]
     gs = GeometryDesc(desc.kind, desc.nx, desc.ny, desc.nz, desc.voxel, len(angles), desc.nu,
                       desc.nv, desc.du, desc.dv, desc.sod, desc.sdd, tuple(angles))
     bs = b_host.reshape(desc.sino_shape)[::sub].astype(np.float64)
     t = time.perf_counter()
-    r = oracle.ba_gmres(gs, bs, 2, B="ramp")
+    r = oracle.ba_gmres(gs, bs, 3, B="ramp")
     dt = time.perf_counter() - t
     # one extra B for the start vector: (iters + 1) back-projections, iters projections
     per_iter = dt / (r.iters_done + 0.5) * sub
     out = {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.num_threads(),
            "kind": "oracle",
-           "sample": "FP64 oracle BA-GMRES (B_un F), 2 iterations on the 256^3 volume and "
-                     "384x384 detector with 12 of the 360 views (every 30th); seconds per "
-                     "iteration scaled by 30 (operator cost is linear in views); %.1f s of CPU "
+           "sample": "FP64 oracle BA-GMRES (B_un F), 3 iterations on the 256^3 volume and "
+                     "384x384 detector with 45 of the 360 views (every 8th); seconds per "
+                     "iteration scaled by 8 (operator cost is linear in views); %.1f s of CPU "
                      "work" % dt}
     return out, oracle
 
