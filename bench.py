@@ -100,6 +100,48 @@ def cpu_baseline(desc, b_host, x_phantom):
     return out, oracle
 
 
+def bench_batched(ct, torch, reps=3):
+    """64 uneven 2D slices (N in {128..512}, 90/180/360 views, ceil(1.5 N)
+    bins, ellipse phantoms, 1 % noise), BA-GMRES(B_un) for 40 iterations
+    each: one batched solve (hipGraph replay) against the same 64 solves
+    one after another.  Inputs are made with the library's own projector."""
+    from synth import workloads
+    K = 40
+    slices = workloads.w5_slices()
+    geoms, bs = [], []
+    for d, pseed, nseed in slices:
+        g = ct.Geometry(d)
+        x = torch.from_numpy(workloads.w5_phantom(d, pseed).astype(np.float32)).cuda()
+        y = ct.ct_project_A(g, x).double().cpu().numpy()
+        y = y + workloads.relative_gaussian_noise(y, 0.01, nseed)
+        geoms.append(g)
+        bs.append(torch.from_numpy(y.astype(np.float32)).cuda())
+    out = ct.ct_ba_gmres_batched(geoms, bs, K)          # autotune + graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = ct.ct_ba_gmres_batched(geoms, bs, K)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    done_b = sum(r.iters_done for r in out)
+    for g, b in zip(geoms[:4], bs[:4]):                  # warm the one-problem path
+        ct.ct_ba_gmres(g, b, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [ct.ct_ba_gmres(g, b, K) for g, b in zip(geoms, bs)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    done_s = sum(r.iters_done for r in seq)
+    diff = max(float(torch.linalg.norm(r.x - s.x) / torch.linalg.norm(s.x)) for r, s in zip(out, seq))
+    graph, a_var, b_var = ct.ct_batched_last_config()
+    return {"workload": "64 2D parallel-beam slices, N in {128,192,256,384,512}, 90/180/360 views, "
+                        "ceil(1.5N) bins, BA-GMRES(B_un) 40 iterations each",
+            "batched_iters_per_s": done_b / tb, "sequential_iters_per_s": done_s / ts,
+            "speedup": ts / tb * done_b / max(done_s, 1), "batched_ms": tb * 1e3, "sequential_ms": ts * 1e3,
+            "max_rel_diff_x_vs_sequential": diff, "hipgraph": graph,
+            "projector_variant": a_var, "backprojector_variant": b_var}
+
+
 def sampled_errors(oracle, desc, ct, g, torch, x_phantom):
     """Relative error of the GPU operators against the FP64 oracle on sampled
     rays / voxels of the benchmark workload."""
@@ -125,6 +167,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sino-dtype", default="f32", choices=["f32", "f16"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -208,6 +251,9 @@ def main():
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
     }
+    if not args.no_batched:
+        log("bench: batched 2D slices")
+        line["batched_2d"] = bench_batched(ct, torch)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         cb, orc = cpu_baseline(desc, b.cpu().numpy(), x_phantom)

@@ -186,6 +186,46 @@ int ct_cgls(const ct_geometry *g, const float *b, float *x,
             const ct_solver_opts *opts, void *ws, size_t ws_bytes,
             double *res_hist, int *iters_done, void *stream);
 
+/* Batched BA-GMRES (Sec. II, Eq. 5) over `count` independent 2D parallel-beam
+ * problems of any sizes, solved together: each step of the iteration runs
+ * as one launch over all problems, and the whole chain is replayed from a
+ * captured hipGraph (see ct_batched_config).  Every problem gets the result
+ * ct_ba_gmres would give it up to the order of FP64 sums.
+ *   g:  HOST array of `count` geometry handles (CT_PARALLEL_2D, all on the
+ *       current device; the same handle may appear more than once).
+ *   b:  HOST array of `count` DEVICE pointers, float[n_views][nu] each.
+ *   x:  HOST array of `count` DEVICE pointers, float[ny][nx] each (outputs).
+ *   opts: as ct_ba_gmres; B = CT_B_UNMATCHED or CT_B_RAMP, sino_dtype CT_F32
+ *       (others: CT_ERR_UNSUPPORTED); the same iteration count for all.
+ *   ws: DEVICE workspace of ct_ba_gmres_batched_workspace_bytes bytes.  It
+ *       holds the per-problem tables, so a cached graph is tied to it: do
+ *       not use one workspace from two calls at once.
+ *   res_hist: HOST double[count][iters+1] or NULL (per problem as in
+ *       ct_ba_gmres; NaN after a problem's breakdown).
+ *   iters_done: HOST int[count] or NULL.
+ * The call synchronises `stream` once at the end.  CT_ERR_NUMERIC if any
+ * problem met a non-finite value (the others' results are valid).
+ * count == 0 is a no-op. */
+int ct_ba_gmres_batched_workspace_bytes(const ct_geometry *const *g, int count,
+                                        const ct_solver_opts *opts, size_t *bytes);
+int ct_ba_gmres_batched(const ct_geometry *const *g, int count,
+                        const float *const *b, float *const *x,
+                        const ct_solver_opts *opts, void *ws, size_t ws_bytes,
+                        double *res_hist, int *iters_done, void *stream);
+
+/* Execution choices of ct_ba_gmres_batched (process-wide):
+ *   use_graph: 1 (default) capture the solve into a hipGraph on the first
+ *       call for a batch shape / workspace / options and replay it; 0 launch
+ *       the kernels directly on the stream.
+ *   a_variant, b_variant: -1 (default) pick by timing every variant on the
+ *       first solve of a batch shape (cached); otherwise force the 2D
+ *       projector variant (0, 1: plane loop unrolled by 4, 8) or the 2D
+ *       back-projector variant (0, 1, 2: 1, 2, 4 pixels per work-item).
+ *       All variants give identical results.
+ * ct_batched_last_config reports the choices of the last batched solve. */
+int ct_batched_config(int use_graph, int a_variant, int b_variant);
+int ct_batched_last_config(int *use_graph, int *a_variant, int *b_variant);
+
 /* Kernel timing (opt-in tracing).  When enabled, every projector,
  * back-projector, filter and orthogonalisation kernel launched by the
  * library is bracketed by two hipEvents recorded on the stream it runs on.

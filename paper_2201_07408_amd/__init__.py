@@ -18,6 +18,9 @@ from .api import (  # noqa: F401
     ct_ba_gmres,
     ct_ab_gmres,
     ct_cgls,
+    ct_ba_gmres_batched,
+    ct_batched_config,
+    ct_batched_last_config,
     ct_last_error,
     CtError,
     SolveResult,

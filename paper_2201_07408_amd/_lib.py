@@ -20,6 +20,8 @@ EXPORTS = [
     "ct_backproject_AT", "ct_ramp_filter", "ct_solver_workspace_bytes",
     "ct_ba_gmres", "ct_ab_gmres", "ct_cgls", "ct_last_error", "ct_version",
     "ct_profile_enable", "ct_profile_reset", "ct_profile_read",
+    "ct_ba_gmres_batched_workspace_bytes", "ct_ba_gmres_batched",
+    "ct_batched_config", "ct_batched_last_config",
 ]
 
 
@@ -76,6 +78,11 @@ def load(path: str = LIBPATH):
         "ct_ba_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_ab_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_cgls": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_ba_gmres_batched_workspace_bytes": ([ctypes.POINTER(vp), i, ctypes.POINTER(SolverOpts), szp], i),
+        "ct_ba_gmres_batched": ([ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                 ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_batched_config": ([i, i, i], i),
+        "ct_batched_last_config": ([ip, ip, ip], i),
         "ct_profile_enable": ([i], i),
         "ct_profile_reset": ([], i),
         "ct_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp], i),

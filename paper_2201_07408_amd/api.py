@@ -75,6 +75,7 @@ class Geometry:
         with torch.cuda.device(self.device):
             _check(lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)), "ct_geometry_create")
         self.handle = h
+        self._lib = lib
         nv, nr = ctypes.c_size_t(), ctypes.c_size_t()
         _check(lib.ct_geometry_sizes(h, ctypes.byref(nv), ctypes.byref(nr)), "ct_geometry_sizes")
         self.n_vox, self.n_rays = nv.value, nr.value
@@ -84,13 +85,15 @@ class Geometry:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            try:
-                torch.cuda.synchronize(self.device)
-            except Exception:
-                pass
-            L.load().ct_geometry_destroy(h)
-            self.handle = None
+        lib = getattr(self, "_lib", None)
+        if h is None or not h.value or lib is None:
+            return
+        try:
+            torch.cuda.synchronize(self.device)
+            lib.ct_geometry_destroy(h)
+        except Exception:
+            pass   # interpreter shutdown: the process releases the memory
+        self.handle = None
 
     # workspace cache: one buffer per purpose, grown on demand
     def workspace(self, key: str, nbytes: int) -> torch.Tensor:
@@ -215,3 +218,58 @@ def ct_cgls(g: Geometry, b: torch.Tensor, iters: int, B: str = "AT",
             out: Optional[torch.Tensor] = None) -> SolveResult:
     """CGLS (Eq. 2) with A^T replaced by B."""
     return _solve("ct_cgls", L.CT_SOLVER_CGLS, g, b, iters, B, torch.float32, 0.0, out)
+
+
+_BATCH_WS = {}
+
+
+def ct_ba_gmres_batched(geoms: List[Geometry], bs: List[torch.Tensor], iters: int, B: str = "un",
+                        breakdown_tol: float = 0.0,
+                        outs: Optional[List[torch.Tensor]] = None) -> List[SolveResult]:
+    """BA-GMRES (Eq. 5) on many independent 2D problems in one batched solve."""
+    count = len(geoms)
+    if len(bs) != count:
+        raise ValueError("one data array per geometry")
+    if count == 0:
+        return []
+    for i, (g, b) in enumerate(zip(geoms, bs)):
+        _need_device(b, "b[%d]" % i, torch.float32)
+        if b.numel() != g.n_rays:
+            raise ValueError("b[%d] must have %d elements" % (i, g.n_rays))
+    if outs is None:
+        outs = [torch.empty(g.vol_shape, dtype=torch.float32, device=b.device) for g, b in zip(geoms, bs)]
+    for i, (g, x) in enumerate(zip(geoms, outs)):
+        _need_device(x, "x[%d]" % i, torch.float32)
+        if x.numel() != g.n_vox:
+            raise ValueError("x[%d] must have %d elements" % (i, g.n_vox))
+    lib = L.load()
+    opts = L.SolverOpts(int(iters), _B[B], L.CT_F32, float(breakdown_tol))
+    garr = (ctypes.c_void_p * count)(*[g.handle.value for g in geoms])
+    barr = (ctypes.c_void_p * count)(*[b.data_ptr() for b in bs])
+    xarr = (ctypes.c_void_p * count)(*[x.data_ptr() for x in outs])
+    n = ctypes.c_size_t()
+    _check(lib.ct_ba_gmres_batched_workspace_bytes(garr, count, ctypes.byref(opts), ctypes.byref(n)),
+           "ct_ba_gmres_batched_workspace_bytes")
+    dev = bs[0].device
+    ws = _BATCH_WS.get(dev)
+    if ws is None or ws.numel() < n.value:
+        _BATCH_WS.pop(dev, None)
+        ws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=dev)
+        _BATCH_WS[dev] = ws
+    K1 = int(iters) + 1
+    res = (ctypes.c_double * (count * K1))()
+    done = (ctypes.c_int * count)()
+    _check(lib.ct_ba_gmres_batched(garr, count, barr, xarr, ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                   res, done, _stream(bs[0])), "ct_ba_gmres_batched")
+    return [SolveResult(outs[i], list(res[i * K1: i * K1 + done[i] + 1]), int(done[i])) for i in range(count)]
+
+
+def ct_batched_config(use_graph: bool = True, a_variant: int = -1, b_variant: int = -1) -> None:
+    _check(L.load().ct_batched_config(int(bool(use_graph)), int(a_variant), int(b_variant)), "ct_batched_config")
+
+
+def ct_batched_last_config():
+    g, a, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(L.load().ct_batched_last_config(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b)),
+           "ct_batched_last_config")
+    return bool(g.value), a.value, b.value

@@ -115,6 +115,9 @@ namespace ct {
 enum { PROF_A = 0, PROF_AT, PROF_B, PROF_F, PROF_CGS, PROF_ARNOLDI, kProfClasses };
 class ProfScope {
   public:
+    // no event pairs while a stream is being captured into a graph
+    static void suppress(bool on);
+
     ProfScope(int cls, hipStream_t s);
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
@@ -152,6 +155,44 @@ struct OpScratch {
 };
 size_t op_scratch_bytes(const ct_geometry *g, int op, int data_dtype);
 OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *ws);
+
+// ------------------------------------------------ batched 2D problems
+// A batched solve concatenates the vectors of its problems: image segment
+// i starts at voff (a multiple of kBVec floats, zero-padded to the next
+// multiple), data segment i at roff (a multiple of 64 floats).  Every
+// batched kernel maps its workgroup to a problem through a prefix sum of
+// per-problem workgroup counts.
+constexpr int kBVec = 4096;
+
+struct BSlice {
+    GeomK g;               // 2D parallel geometry (device tables of its handle)
+    PadLayout L;
+    const float *ramp;     // du * h[j] of its handle
+    const float *b;        // caller data [P][nu]
+    float *x;              // caller image [ny][nx]
+    size_t voff, roff;     // segment offsets in the batched image / data vectors
+    uint32_t pvx, pvy;     // Vx / Vy offsets in the batched padded buffer (elements)
+    const int *stop;       // the problem's stop flag
+};
+
+// workgroups per problem for each batched kernel and variant
+inline int bpad_blocks(const GeomK &g) { return ((g.nx + 31) / 32) * ((g.ny + 31) / 32); }
+inline int bray_blocks(const GeomK &g) { return (g.P * g.nu + 255) / 256; }
+inline int bpix_blocks(const GeomK &g, int ppt) { return ((g.nx + 15) / 16) * ((g.ny + 16 * ppt - 1) / (16 * ppt)); }
+constexpr int kBProjVariants = 2;   // plane loop unrolled by 4 or 8
+constexpr int kBBackVariants = 3;   // 1, 2 or 4 pixels per work-item
+inline int bback_ppt(int variant) { return variant == 0 ? 1 : variant == 1 ? 2 : 4; }
+
+// vec: batched image vector; pad: batched padded buffer (pad_elems floats,
+// borders zero).  q == nullptr reads each problem's caller data b.
+int launch_bpad_copy(const BSlice *sl, int count, const int *pfx, int nblk, const float *vec, float *pad,
+                     hipStream_t s);
+int launch_bproject2d(const BSlice *sl, int count, const int *pfx, int nblk, int variant, const float *pad,
+                      size_t pad_elems, float *q, hipStream_t s);
+int launch_bbackproject2d(const BSlice *sl, int count, const int *pfx, int nblk, int variant, const float *q,
+                          float *z, hipStream_t s);
+int launch_bramp(const BSlice *sl, int count, const int *pfx, int nblk, int max_nu, const float *q, float *out,
+                 hipStream_t s);
 
 // y = A x.  Padding of vx/vy must already be zero (pad_ready) or is zeroed here.
 int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratch &sc,

@@ -72,7 +72,12 @@ int prof_drain() {
 }
 }  // namespace
 
+static thread_local bool t_prof_suppressed = false;
+
+void ProfScope::suppress(bool on) { t_prof_suppressed = on; }
+
 ProfScope::ProfScope(int cls, hipStream_t s) : cls_(cls), s_(s) {
+    if (t_prof_suppressed) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on || g_prof_recs.size() >= kProfMax) return;
     a_ = pool_take();

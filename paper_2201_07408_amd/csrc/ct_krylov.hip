@@ -11,49 +11,24 @@
 // sc[j] * W[j], so no kernel has to rescale a whole vector.
 //
 // Orthonormalisation is classical Gram-Schmidt applied twice (CGS2):
-//   pass 1: d1 = W^T z                         (one sweep over W)
-//   pass 2: z1 = z - W h1,  d2 = W^T z1         (one sweep)
-//   pass 3: z2 = z1 - W h2, ||z2||^2            (one sweep)
-// Each pass stages a tile of all basis vectors in LDS, so every basis element
-// is read from HBM once per pass, and accumulates in FP64.  Partial sums go
-// to a [block][j] array that a one-block kernel reduces in a fixed order
+//   pass 1: d1 = W^T z, ||z||^2                 (one sweep over W)
+//   pass 2: z1 = z - W h1,  d2 = W^T z1          (two sweeps)
+//   pass 3: z2 = z1 - W h2, ||z2||^2             (one sweep)
+// Each sweep streams chunks of up to 16 basis vectors with 16-byte loads
+// and accumulates in FP64.  Per-block partial sums go to a column-major
+// [column][block] table that a one-workgroup kernel reduces in a fixed order
 // (deterministic, no float atomics) before running the scalar step.
 #include <cmath>
 #include <cstring>
 
-#include "ct_common.h"
+#include "ct_krylov_dev.h"
 
 namespace ct {
 namespace {
 
-constexpr int kTile = 256;       // elements per LDS tile (= block size)
-constexpr int kMaxBlk = 1024;    // upper bound on blocks of a sweep kernel
-constexpr int kMaxVec = 57;      // basis vectors per sweep (K+1), bounded by the 64-vector kernel
+using namespace kry;
 
-// Device scalar state carved from the workspace.
-struct KState {
-    int *flags;        // [0] k_done, [1] stop, [2] status
-    double *H;         // (K+1) x K, column-major, rotated in place
-    double *cs, *sn;   // K rotations
-    double *gv;        // K+1 right-hand side of the small problem
-    double *sc;        // K+2 basis scale factors (basis j = sc[j] W[j])
-    double *h1, *h2;   // K+1 CGS coefficients
-    double *coef;      // K+1 coefficients applied by the next sweep
-    double *res;       // K+1 residual history
-    double *misc;      // [0] scale of the raw z, [1] ||z|| before CGS, [2] CGLS gamma, [3] alpha/beta
-    float *fscale;     // [0] A output scale, [1] B input scale (FP16 storage)
-    double *partials;  // [column][block], columns of kMaxBlk doubles
-    int pstride;
-    int K;
-};
-
-enum { F_KDONE = 0, F_STOP = 1, F_STATUS = 2 };
-enum { M_ZS = 0, M_ZN0 = 1, M_GAMMA = 2, M_AB = 3 };
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+constexpr int kTile = 256;       // float4 groups per block per grid-stride step
 
 // -------------------------------------------------------- sweep kernels
 // CGS2 runs as streaming passes over chunks of at most NV basis vectors:
@@ -63,31 +38,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 //            new array, optionally with ||z'||^2 (column ncol).
 // Work-items stride over 16-byte groups of four elements (the last partial
 // group goes element by element), every basis vector of the chunk is read
-// once per pass with 16-byte loads, and all sums accumulate in FP64.  Block
-// partials are reduced with a fixed shuffle tree and a fixed-order sum over
-// the four wavefronts, so results are reproducible run to run.
-template <int NV>
-__device__ __forceinline__ void block_partials(double (&acc)[NV], int cnt, double nacc, bool nrm, int vlo, int ncol,
-                                               double *__restrict__ partials) {
-    __shared__ double red[4][NV + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < cnt) {
-            const double v = wave_sum(acc[j]);
-            if (lane == 0) red[wave][j] = v;
-        }
-    if (nrm) {
-        const double v = wave_sum(nacc);
-        if (lane == 0) red[wave][NV] = v;
-    }
-    __syncthreads();
-    for (int j = tid; j < cnt; j += 256)
-        partials[(size_t)(vlo + j) * kMaxBlk + blockIdx.x] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
-    if (nrm && tid == 0)
-        partials[(size_t)ncol * kMaxBlk + blockIdx.x] = (red[0][NV] + red[1][NV]) + (red[2][NV] + red[3][NV]);
-}
-
+// once per pass with 16-byte loads, and all sums accumulate in FP64.
 template <int NV>
 __global__ __launch_bounds__(256) void k_mdot(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
                                               const float *__restrict__ z, size_t n, int nrm, int ncol,
@@ -98,18 +49,7 @@ __global__ __launch_bounds__(256) void k_mdot(const float *__restrict__ W, size_
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     const float *Wc = W + (size_t)vlo * ldw;
     const size_t n4 = n / 4;
-    const size_t stride = (size_t)gridDim.x * 256;
-    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
-        const float4 zv = reinterpret_cast<const float4 *>(z)[q];
-        const double z0 = zv.x, z1 = zv.y, z2 = zv.z, z3 = zv.w;
-        nacc += z0 * z0 + z1 * z1 + z2 * z2 + z3 * z3;
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            if (j < cnt) {
-                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
-                acc[j] += (double)w.x * z0 + (double)w.y * z1 + (double)w.z * z2 + (double)w.w * z3;
-            }
-    }
+    mdot_groups<NV>(Wc, ldw, cnt, z, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)   // tail of fewer than four elements
         for (size_t i = n4 * 4; i < n; ++i) {
             const double zd = z[i];
@@ -118,7 +58,7 @@ __global__ __launch_bounds__(256) void k_mdot(const float *__restrict__ W, size_
             for (int j = 0; j < NV; ++j)
                 if (j < cnt) acc[j] += (double)Wc[(size_t)j * ldw + i] * zd;
         }
-    block_partials<NV>(acc, cnt, nacc, nrm != 0, vlo, ncol, partials);
+    block_partials<NV>(acc, cnt, nacc, nrm != 0, vlo, ncol, partials, kMaxBlk, blockIdx.x);
 }
 
 template <int NV>
@@ -132,25 +72,10 @@ __global__ __launch_bounds__(256) void k_maxpy(const float *__restrict__ W, size
     for (int j = threadIdx.x; j < cnt; j += 256) cf[j] = coef[vlo + j];
     __syncthreads();
     const double zs = zscale ? *zscale : 1.0;
-    double acc[NV];
     double nacc = 0.0;
     const float *Wc = W + (size_t)vlo * ldw;
     const size_t n4 = n / 4;
-    const size_t stride = (size_t)gridDim.x * 256;
-    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
-        const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
-        double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            if (j < cnt) {
-                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
-                const double c = cf[j];
-                u0 -= c * (double)w.x; u1 -= c * (double)w.y; u2 -= c * (double)w.z; u3 -= c * (double)w.w;
-            }
-        const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
-        reinterpret_cast<float4 *>(zout)[q] = o;
-        nacc += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
-    }
+    maxpy_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (size_t i = n4 * 4; i < n; ++i) {
             double u = zs * (double)zin[i];
@@ -159,150 +84,36 @@ __global__ __launch_bounds__(256) void k_maxpy(const float *__restrict__ W, size
             zout[i] = o;
             nacc += (double)o * o;
         }
+    double acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-    block_partials<NV>(acc, 0, nacc, nrm != 0, vlo, ncol, partials);
+    block_partials<NV>(acc, 0, nacc, nrm != 0, vlo, ncol, partials, kMaxBlk, blockIdx.x);
 }
 
-// out[j] = sum over b < nblk of partials[j][b], for j < count.  One wavefront
-// per column, lanes stride the blocks, a fixed shuffle tree finishes: the
-// order never changes, so the result is bitwise reproducible.
-__device__ void reduce_partials(const double *__restrict__ partials, int nblk, int pstride, int count,
-                                double *out) {
-    (void)pstride;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int j = wave; j < count; j += nw) {
-        const double *col = partials + (size_t)j * kMaxBlk;
-        double s = 0.0;
-        for (int b = lane; b < nblk; b += 64) s += col[b];
-        s = wave_sum(s);
-        if (lane == 0) out[j] = s;
-    }
-}
-
-__device__ __forceinline__ float pow2_scale(double target) {
-    // nearest power of two to target (exact scaling for FP16 storage)
-    if (!(target > 0.0) || !isfinite(target)) return 1.0f;
-    const double e = rint(log2(target));
-    return (float)exp2(fmin(fmax(e, -60.0), 60.0));
-}
-
-// beta = ||r0|| from partials; set up the first basis vector's scale.
 __global__ void k_gmres_init(KState st, int nblk, double qscale_c) {
     __shared__ double d[1];
-    reduce_partials(st.partials, nblk, st.pstride, 1, d);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const double beta = sqrt(d[0]);
-    st.flags[F_KDONE] = 0;
-    st.flags[F_STATUS] = CT_OK;
-    st.res[0] = beta;
-    if (!isfinite(beta)) {
-        st.flags[F_STOP] = 1;
-        st.flags[F_STATUS] = CT_ERR_NUMERIC;
-        return;
-    }
-    if (beta == 0.0) {
-        st.flags[F_STOP] = 1;
-        return;
-    }
-    st.flags[F_STOP] = 0;
-    st.sc[0] = 1.0 / beta;
-    st.gv[0] = beta;
-    const float qs = pow2_scale(st.sc[0] * qscale_c);
-    st.fscale[0] = qs;
-    st.fscale[1] = 1.0f / qs;
+    gmres_init(st, nblk, qscale_c, d);
 }
 
-// After pass 1 at step k: h1 = V_k^T z, coefficients for pass 2.
 __global__ void k_gmres_red1(KState st, int nblk, int k) {
     extern __shared__ double d[];
     if (st.flags[F_STOP]) return;
-    const int nvec = k + 1;
-    reduce_partials(st.partials, nblk, st.pstride, nvec + 1, d);
-    __syncthreads();
-    // the raw new vector is B A W[k] (any FP16 storage scale is already
-    // divided out by the back-projector), so the true vector is sc[k] * raw
-    const double s = st.sc[k];
-    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
-        const double h = st.sc[j] * s * d[j];
-        st.h1[j] = h;
-        st.coef[j] = h * st.sc[j];
-    }
-    if (threadIdx.x == 0) {
-        st.misc[M_ZS] = s;
-        st.misc[M_ZN0] = s * sqrt(d[nvec]);
-    }
+    gmres_red1(st, nblk, k, d);
 }
 
-// After pass 2: h2 = V_k^T z1, coefficients for pass 3.
 __global__ void k_gmres_red2(KState st, int nblk, int k) {
     extern __shared__ double d[];
     if (st.flags[F_STOP]) return;
-    const int nvec = k + 1;
-    reduce_partials(st.partials, nblk, st.pstride, nvec, d);
-    __syncthreads();
-    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
-        const double h = st.sc[j] * d[j];
-        st.h2[j] = h;
-        st.coef[j] = h * st.sc[j];
-    }
+    gmres_red2(st, nblk, k, d);
 }
 
-// After pass 3: new column of H, Givens rotations, residual, breakdown test.
 __global__ void k_gmres_red3(KState st, int nblk, int k, double tol, double qscale_c) {
     __shared__ double d[1];
     if (st.flags[F_STOP]) return;
-    reduce_partials(st.partials, nblk, st.pstride, 1, d);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int K1 = st.K + 1;
-    double *col = st.H + (size_t)k * K1;
-    const double hn = sqrt(d[0]);
-    for (int i = 0; i <= k; ++i) col[i] = st.h1[i] + st.h2[i];
-    col[k + 1] = hn;
-    for (int i = 0; i < k; ++i) {
-        const double a = col[i], b = col[i + 1];
-        col[i] = st.cs[i] * a + st.sn[i] * b;
-        col[i + 1] = -st.sn[i] * a + st.cs[i] * b;
-    }
-    const double rho = hypot(col[k], col[k + 1]);
-    const double c = col[k] / rho, s = col[k + 1] / rho;
-    st.cs[k] = c;
-    st.sn[k] = s;
-    col[k] = rho;
-    col[k + 1] = 0.0;
-    st.gv[k + 1] = -s * st.gv[k];
-    st.gv[k] = c * st.gv[k];
-    st.res[k + 1] = fabs(st.gv[k + 1]);
-    st.flags[F_KDONE] = k + 1;
-    if (!isfinite(rho) || !isfinite(st.gv[k]) || !isfinite(hn) || rho == 0.0) {
-        st.flags[F_STOP] = 1;
-        st.flags[F_STATUS] = CT_ERR_NUMERIC;
-        return;
-    }
-    if (hn <= tol * st.misc[M_ZN0]) {   // (happy) breakdown
-        st.flags[F_STOP] = 1;
-        return;
-    }
-    st.sc[k + 1] = 1.0 / hn;
-    const float qs = pow2_scale(st.sc[k + 1] * qscale_c);
-    st.fscale[0] = qs;
-    st.fscale[1] = 1.0f / qs;
+    gmres_red3(st, nblk, k, tol, qscale_c, d);
 }
 
-// y = R^-1 g (back substitution); coef[j] = y[j] * sc[j]
-__global__ void k_gmres_trsv(KState st) {
-    if (threadIdx.x != 0) return;
-    const int kd = st.flags[F_KDONE];
-    const int K1 = st.K + 1;
-    for (int i = kd - 1; i >= 0; --i) {
-        double s = st.gv[i];
-        for (int j = i + 1; j < kd; ++j) s -= st.H[(size_t)j * K1 + i] * st.coef[j];
-        st.coef[i] = s / st.H[(size_t)i * K1 + i];
-    }
-    for (int i = 0; i < kd; ++i) st.coef[i] *= st.sc[i];
-}
+__global__ void k_gmres_trsv(KState st) { gmres_trsv(st); }
 
 // out = sum_{j < k_done} coef[j] W[j]   (FP64 accumulation)
 __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, size_t ldw, size_t n,
@@ -321,7 +132,7 @@ __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, si
 
 // ------------------------------------------------------------- CGLS
 __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ v, size_t n,
-                                               double *__restrict__ partials, int pstride,
+                                               double *__restrict__ partials,
                                                const int *__restrict__ stop) {
     if (stop && *stop) return;
     double a = 0.0;
@@ -348,7 +159,7 @@ __global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, size_
 // stage 0: res[0] = ||b||;  stage 1: gamma = ||s||^2 (start)
 __global__ void k_cgls_start(KState st, int nblk, int stage) {
     __shared__ double d[1];
-    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    reduce_partials(st.partials, st.pstride, nblk, 1, d);
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (stage == 0) {
@@ -371,7 +182,7 @@ __global__ void k_cgls_start(KState st, int nblk, int stage) {
 __global__ void k_cgls_alpha(KState st, int nblk) {
     __shared__ double d[1];
     if (st.flags[F_STOP]) return;
-    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    reduce_partials(st.partials, st.pstride, nblk, 1, d);
     __syncthreads();
     if (threadIdx.x != 0) return;
     const double a = st.misc[M_GAMMA] / d[0];
@@ -404,7 +215,7 @@ __global__ __launch_bounds__(256) void k_cgls_xr(float *__restrict__ x, const fl
 __global__ void k_cgls_res(KState st, int nblk, int k) {
     __shared__ double d[1];
     if (st.flags[F_STOP]) return;
-    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    reduce_partials(st.partials, st.pstride, nblk, 1, d);
     __syncthreads();
     if (threadIdx.x != 0) return;
     st.res[k + 1] = sqrt(d[0]);
@@ -415,7 +226,7 @@ __global__ void k_cgls_res(KState st, int nblk, int k) {
 __global__ void k_cgls_beta(KState st, int nblk) {
     __shared__ double d[1];
     if (st.flags[F_STOP]) return;
-    reduce_partials(st.partials, nblk, st.pstride, 1, d);
+    reduce_partials(st.partials, st.pstride, nblk, 1, d);
     __syncthreads();
     if (threadIdx.x != 0) return;
     const double gnew = d[0];
@@ -501,7 +312,7 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
     b.opA.filt = b.filt;
     KState &s = b.st;
     s.K = K;
-    s.pstride = K + 3;
+    s.pstride = kMaxBlk;
     s.flags = c.take<int>(16);
     s.H = c.take<double>((size_t)(K + 1) * (K > 0 ? K : 1));
     s.cs = c.take<double>(K + 1);
@@ -514,7 +325,7 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
     s.res = c.take<double>(K + 2);
     s.misc = c.take<double>(8);
     s.fscale = c.take<float>(4);
-    s.partials = c.take<double>((size_t)kMaxBlk * s.pstride);
+    s.partials = c.take<double>((size_t)kMaxBlk * (K + 3));
     return c.off;
 }
 
@@ -622,11 +433,11 @@ size_t carve_cgls(const ct_geometry *g, const ct_solver_opts &o, void *ws, float
     op.vy = c.take<float>(g->pad.nvy);
     op.filt = o.B == CT_B_RAMP ? c.take<float>(g->n_rays) : nullptr;
     st.K = o.iters;
-    st.pstride = 4;
+    st.pstride = kMaxBlk;
     st.flags = c.take<int>(16);
     st.res = c.take<double>(o.iters + 2);
     st.misc = c.take<double>(8);
-    st.partials = c.take<double>((size_t)kMaxBlk * st.pstride);
+    st.partials = c.take<double>((size_t)kMaxBlk * 4);
     st.H = st.cs = st.sn = st.gv = st.sc = st.h1 = st.h2 = st.coef = nullptr;
     st.fscale = nullptr;
     return c.off;
@@ -744,12 +555,12 @@ int cgls_impl(const ct_geometry *g, const float *b, float *x, const ct_solver_op
     CT_TRY(launch_pad_zero(g, op.vx, op.vy, s));
     hipLaunchKernelGGL(k_copy, dim3(grid_1d(m)), dim3(256), 0, s, b, r, m);
     CT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, r, m, st.partials, st.pstride, nullptr);
+    hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, r, m, st.partials, nullptr);
     CT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cgls_start, dim3(1), dim3(256), 0, s, st, nb_m, 0);
     CT_LAUNCH_CHECK();
     CT_TRY(apply_B(g, o->B, r, CT_F32, sv, op, nullptr, stop, s));
-    hipLaunchKernelGGL(k_sumsq, dim3(nb_n), dim3(256), 0, s, sv, n, st.partials, st.pstride, stop);
+    hipLaunchKernelGGL(k_sumsq, dim3(nb_n), dim3(256), 0, s, sv, n, st.partials, stop);
     CT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cgls_start, dim3(1), dim3(256), 0, s, st, nb_n, 1);
     CT_LAUNCH_CHECK();
@@ -758,18 +569,18 @@ int cgls_impl(const ct_geometry *g, const float *b, float *x, const ct_solver_op
     const bool pad_ready = o->B != CT_B_AT;
     for (int k = 0; k < o->iters; ++k) {
         CT_TRY(apply_A(g, p, q, CT_F32, op, pad_ready, nullptr, stop, s));
-        hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, q, m, st.partials, st.pstride, stop);
+        hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, q, m, st.partials, stop);
         CT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cgls_alpha, dim3(1), dim3(256), 0, s, st, nb_m);
         CT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cgls_xr, dim3(grid_1d(n + m)), dim3(256), 0, s, x, p, n, r, q, m, st);
         CT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, r, m, st.partials, st.pstride, stop);
+        hipLaunchKernelGGL(k_sumsq, dim3(nb_m), dim3(256), 0, s, r, m, st.partials, stop);
         CT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cgls_res, dim3(1), dim3(256), 0, s, st, nb_m, k);
         CT_LAUNCH_CHECK();
         CT_TRY(apply_B(g, o->B, r, CT_F32, sv, op, nullptr, stop, s));
-        hipLaunchKernelGGL(k_sumsq, dim3(nb_n), dim3(256), 0, s, sv, n, st.partials, st.pstride, stop);
+        hipLaunchKernelGGL(k_sumsq, dim3(nb_n), dim3(256), 0, s, sv, n, st.partials, stop);
         CT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cgls_beta, dim3(1), dim3(256), 0, s, st, nb_n);
         CT_LAUNCH_CHECK();

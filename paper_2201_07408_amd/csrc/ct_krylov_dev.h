@@ -1,0 +1,249 @@
+// Device-side pieces of the GMRES solvers shared by the single-problem and
+// the batched translation units: the scalar state, the FP64 reductions and
+// the bodies of the small steps of the Arnoldi process (Sec. II: x0 = 0, the
+// normalised right-hand side as first basis vector, one orthonormalised
+// vector and one Givens-updated least-squares problem per step).
+#pragma once
+
+#include "ct_common.h"
+
+namespace ct {
+namespace kry {
+
+constexpr int kMaxBlk = 1024;    // column stride of the single-problem partial sums
+constexpr int kMaxVec = 57;      // basis vectors (K+1) supported
+
+// Device scalar state carved from the workspace (one per problem).
+struct KState {
+    int *flags;        // [0] k_done, [1] stop, [2] status
+    double *H;         // (K+1) x K, column-major, rotated in place
+    double *cs, *sn;   // K rotations
+    double *gv;        // K+1 right-hand side of the small problem
+    double *sc;        // K+2 basis scale factors (basis j = sc[j] W[j])
+    double *h1, *h2;   // K+1 CGS coefficients
+    double *coef;      // K+1 coefficients applied by the next sweep
+    double *res;       // K+1 residual history
+    double *misc;      // [0] scale of the raw z, [1] ||z|| before CGS, [2] CGLS gamma, [3] alpha/beta
+    float *fscale;     // [0] A output scale, [1] B input scale (FP16 storage)
+    double *partials;  // [column][block]
+    size_t pstride;    // column stride of partials (elements)
+    int K;
+};
+
+enum { F_KDONE = 0, F_STOP = 1, F_STATUS = 2 };
+enum { M_ZS = 0, M_ZN0 = 1, M_GAMMA = 2, M_AB = 3 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Reduce per-thread sums of a 256-thread block to one value per column and
+// store it at partials[column * cstride + slot]: a fixed shuffle tree per
+// wavefront, then a fixed-order sum over the four wavefronts.
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&acc)[NV], int cnt, double nacc, bool nrm, int vlo, int ncol,
+                                               double *__restrict__ partials, size_t cstride, size_t slot) {
+    __shared__ double red[4][NV + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        if (j < cnt) {
+            const double v = wave_sum(acc[j]);
+            if (lane == 0) red[wave][j] = v;
+        }
+    if (nrm) {
+        const double v = wave_sum(nacc);
+        if (lane == 0) red[wave][NV] = v;
+    }
+    __syncthreads();
+    for (int j = tid; j < cnt; j += 256)
+        partials[(size_t)(vlo + j) * cstride + slot] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+    if (nrm && tid == 0)
+        partials[(size_t)ncol * cstride + slot] = (red[0][NV] + red[1][NV]) + (red[2][NV] + red[3][NV]);
+}
+
+// Multi-dot over float4 groups q0 + tid, q0 + tid + qstep, ... < q1:
+// acc[j] += W[vlo+j] . z, nacc += z . z, all in FP64 (products of FP32
+// values are exact in FP64).
+template <int NV>
+__device__ __forceinline__ void mdot_groups(const float *__restrict__ Wc, size_t ldw, int cnt,
+                                            const float *__restrict__ z, size_t q0, size_t q1, size_t qstep,
+                                            double (&acc)[NV], double &nacc) {
+    for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
+        const float4 zv = reinterpret_cast<const float4 *>(z)[q];
+        const double z0 = zv.x, z1 = zv.y, z2 = zv.z, z3 = zv.w;
+        nacc += z0 * z0 + z1 * z1 + z2 * z2 + z3 * z3;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) {
+                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                acc[j] += (double)w.x * z0 + (double)w.y * z1 + (double)w.z * z2 + (double)w.w * z3;
+            }
+    }
+}
+
+// Multi-axpy over float4 groups: z' = zs z - sum_j cf[j] W[vlo+j] (FP64),
+// rounded to FP32 and stored; nacc += z' . z'.
+template <int NV>
+__device__ __forceinline__ void maxpy_groups(const float *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
+                                             double zs, const float *zin, float *zout, size_t q0, size_t q1,
+                                             size_t qstep, double &nacc) {
+    for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
+        const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
+        double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) {
+                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                const double c = cf[j];
+                u0 -= c * (double)w.x; u1 -= c * (double)w.y; u2 -= c * (double)w.z; u3 -= c * (double)w.w;
+            }
+        const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
+        reinterpret_cast<float4 *>(zout)[q] = o;
+        nacc += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
+    }
+}
+
+// out[j] = sum over b < nblk of partials[j * cstride + b], j < count.  One
+// wavefront per column, lanes stride the blocks, a fixed shuffle tree
+// finishes: the order never changes, so the result is reproducible.
+__device__ inline void reduce_partials(const double *__restrict__ partials, size_t cstride, int nblk, int count,
+                                       double *out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wave; j < count; j += nw) {
+        const double *col = partials + (size_t)j * cstride;
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += col[b];
+        s = wave_sum(s);
+        if (lane == 0) out[j] = s;
+    }
+}
+
+__device__ __forceinline__ float pow2_scale(double target) {
+    // nearest power of two to target (exact scaling for FP16 storage)
+    if (!(target > 0.0) || !isfinite(target)) return 1.0f;
+    const double e = rint(log2(target));
+    return (float)exp2(fmin(fmax(e, -60.0), 60.0));
+}
+
+// ----------------------------------------------------- step bodies
+// Each body is run by one workgroup (a multiple of 64 threads); `d` is
+// workgroup-shared scratch of at least K+2 doubles.
+
+// beta = ||r0|| from the partials; first basis vector's scale.
+__device__ inline void gmres_init(KState &st, int nblk, double qscale_c, double *d) {
+    reduce_partials(st.partials, st.pstride, nblk, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(d[0]);
+    st.flags[F_KDONE] = 0;
+    st.flags[F_STATUS] = CT_OK;
+    st.res[0] = beta;
+    if (!isfinite(beta)) {
+        st.flags[F_STOP] = 1;
+        st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        return;
+    }
+    if (beta == 0.0) {
+        st.flags[F_STOP] = 1;
+        return;
+    }
+    st.flags[F_STOP] = 0;
+    st.sc[0] = 1.0 / beta;
+    st.gv[0] = beta;
+    if (st.fscale) {
+        const float qs = pow2_scale(st.sc[0] * qscale_c);
+        st.fscale[0] = qs;
+        st.fscale[1] = 1.0f / qs;
+    }
+}
+
+// After pass 1 at step k: h1 = V_k^T z, coefficients for pass 2.  The raw
+// new vector is B A W[k] (any FP16 storage scale already divided out by the
+// back-projector), so the true vector is sc[k] * raw.
+__device__ inline void gmres_red1(KState &st, int nblk, int k, double *d) {
+    const int nvec = k + 1;
+    reduce_partials(st.partials, st.pstride, nblk, nvec + 1, d);
+    __syncthreads();
+    const double s = st.sc[k];
+    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
+        const double h = st.sc[j] * s * d[j];
+        st.h1[j] = h;
+        st.coef[j] = h * st.sc[j];
+    }
+    if (threadIdx.x == 0) {
+        st.misc[M_ZS] = s;
+        st.misc[M_ZN0] = s * sqrt(d[nvec]);
+    }
+}
+
+// After pass 2: h2 = V_k^T z1, coefficients for pass 3.
+__device__ inline void gmres_red2(KState &st, int nblk, int k, double *d) {
+    const int nvec = k + 1;
+    reduce_partials(st.partials, st.pstride, nblk, nvec, d);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
+        const double h = st.sc[j] * d[j];
+        st.h2[j] = h;
+        st.coef[j] = h * st.sc[j];
+    }
+}
+
+// After pass 3: new column of H, Givens rotations, residual, breakdown test.
+__device__ inline void gmres_red3(KState &st, int nblk, int k, double tol, double qscale_c, double *d) {
+    reduce_partials(st.partials, st.pstride, nblk, 1, d);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int K1 = st.K + 1;
+    double *col = st.H + (size_t)k * K1;
+    const double hn = sqrt(d[0]);
+    for (int i = 0; i <= k; ++i) col[i] = st.h1[i] + st.h2[i];
+    col[k + 1] = hn;
+    for (int i = 0; i < k; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = st.cs[i] * a + st.sn[i] * b;
+        col[i + 1] = -st.sn[i] * a + st.cs[i] * b;
+    }
+    const double rho = hypot(col[k], col[k + 1]);
+    const double c = col[k] / rho, s = col[k + 1] / rho;
+    st.cs[k] = c;
+    st.sn[k] = s;
+    col[k] = rho;
+    col[k + 1] = 0.0;
+    st.gv[k + 1] = -s * st.gv[k];
+    st.gv[k] = c * st.gv[k];
+    st.res[k + 1] = fabs(st.gv[k + 1]);
+    st.flags[F_KDONE] = k + 1;
+    if (!isfinite(rho) || !isfinite(st.gv[k]) || !isfinite(hn) || rho == 0.0) {
+        st.flags[F_STOP] = 1;
+        st.flags[F_STATUS] = CT_ERR_NUMERIC;
+        return;
+    }
+    if (hn <= tol * st.misc[M_ZN0]) {   // (happy) breakdown
+        st.flags[F_STOP] = 1;
+        return;
+    }
+    st.sc[k + 1] = 1.0 / hn;
+    if (st.fscale) {
+        const float qs = pow2_scale(st.sc[k + 1] * qscale_c);
+        st.fscale[0] = qs;
+        st.fscale[1] = 1.0f / qs;
+    }
+}
+
+// y = R^-1 g (back substitution); coef[j] = y[j] * sc[j]
+__device__ inline void gmres_trsv(KState &st) {
+    if (threadIdx.x != 0) return;
+    const int kd = st.flags[F_KDONE];
+    const int K1 = st.K + 1;
+    for (int i = kd - 1; i >= 0; --i) {
+        double s = st.gv[i];
+        for (int j = i + 1; j < kd; ++j) s -= st.H[(size_t)j * K1 + i] * st.coef[j];
+        st.coef[i] = s / st.H[(size_t)i * K1 + i];
+    }
+    for (int i = 0; i < kd; ++i) st.coef[i] *= st.sc[i];
+}
+
+}  // namespace kry
+}  // namespace ct

@@ -33,9 +33,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, size_
                                              (int)(uint32_t)(elems * 4u), 0x00020000);
 }
 
-__device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(elem * 4u), 0, 0));
-}
 
 // two adjacent floats (4-byte alignment is enough for buffer loads on gfx9)
 __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
@@ -86,14 +83,13 @@ __global__ void k_pad_zero(float *__restrict__ vx, float *__restrict__ vy, int n
     }
 }
 
-// x[z][y][x] -> Vx[x][z+pz][y+kPad] and Vy[y][z+pz][x+kPad] (interior only).
-__global__ __launch_bounds__(256) void k_pad_copy(const float *__restrict__ x, float *__restrict__ vx,
-                                                  float *__restrict__ vy, int nx, int ny, PadLayout L,
-                                                  const int *__restrict__ stop) {
-    if (stop && *stop) return;
+// x[z][y][x] -> Vx[x][z+pz][y+kPad] and Vy[y][z+pz][x+kPad] (interior only)
+// for the 32 x 32 tile at (x0, y0) of slice z; 256 work-items as 32 x 8.
+__device__ __forceinline__ void pad_tile(const float *__restrict__ x, float *__restrict__ vx,
+                                         float *__restrict__ vy, int nx, int ny, const PadLayout &L, int x0,
+                                         int y0, int z) {
     __shared__ float tile[32][33];
-    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
-    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const size_t zoff = (size_t)z * ny * nx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -111,6 +107,13 @@ __global__ __launch_bounds__(256) void k_pad_copy(const float *__restrict__ x, f
         if (yy < ny && xx < nx)
             vx[(size_t)xx * L.sx + (size_t)(z + L.pz) * L.rx + yy + kPad] = tile[tx][ty + 8 * r];
     }
+}
+
+__global__ __launch_bounds__(256) void k_pad_copy(const float *__restrict__ x, float *__restrict__ vx,
+                                                  float *__restrict__ vy, int nx, int ny, PadLayout L,
+                                                  const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    pad_tile(x, vx, vy, nx, ny, L, blockIdx.x * 32, blockIdx.y * 32, blockIdx.z);
 }
 
 // x[z][y][x] = Vx[x][z+pz][y+kPad] + Vy[y][z+pz][x+kPad]
@@ -844,6 +847,208 @@ __global__ __launch_bounds__(256) void k_ramp_rb(const InT *__restrict__ q, OutT
         if (a0 + r < nu) out[row * nu + a0 + r] = from_f<OutT>(acc[r]);
 }
 
+
+// ------------------------------------------------ batched 2D problems
+// Workgroup b belongs to problem s with pfx[s] <= b < pfx[s+1].  The search
+// is uniform across the workgroup, so its loads are scalar.
+__device__ __forceinline__ int find_slice(const int *__restrict__ pfx, int count, int b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pfx[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// XCD-aware order: the hardware deals workgroups round-robin to the eight
+// XCDs; remap so that each XCD receives a contiguous range of logical
+// workgroups (neighbouring rays / pixels of the same problems, whose image
+// and data then stay in that XCD's L2).  False for the padding workgroups.
+__device__ __forceinline__ bool xcd_block(int nblk, int &b) {
+    const int per = (nblk + 7) >> 3;
+    const int hw = blockIdx.x;
+    if ((hw >> 3) >= per) return false;
+    b = (hw & 7) * per + (hw >> 3);
+    return b < nblk;
+}
+
+__global__ __launch_bounds__(256) void k_bpad2d(const BSlice *__restrict__ sl, int count,
+                                                const int *__restrict__ pfx, const float *__restrict__ vec,
+                                                float *__restrict__ pad) {
+    const int s = find_slice(pfx, count, blockIdx.x);
+    const BSlice &S = sl[s];
+    if (*S.stop) return;
+    const int t = blockIdx.x - pfx[s];
+    const int ntx = (S.g.nx + 31) / 32;
+    pad_tile(vec + S.voff, pad + S.pvx, pad + S.pvy, S.g.nx, S.g.ny, S.L, (t % ntx) * 32, (t / ntx) * 32, 0);
+}
+
+// Samples of one 2D ray, in groups of four summed in FP32 and added to FP64
+// (the same order as the single-problem projector, so results agree bit for
+// bit), U samples' loads in flight per step.
+template <int U>
+__device__ __forceinline__ double samples2d(const RaySetup &R, __amdgpu_buffer_rsrc_t rs, uint32_t base,
+                                            uint32_t S, int ja, int jb) {
+    static_assert(U % 4 == 0, "groups of four");
+    double acc = 0.0;
+    int j = ja;
+    for (; j + U - 1 <= jb; j += U) {
+        float2 v[U];
+        float w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float fb = fmaf((float)(j + u), R.gb, R.fb0);
+            const float ibf = floorf(fb);
+            w[u] = fb - ibf;
+            v[u] = ld2(rs, base + __umul24((uint32_t)(j + u), S) + (uint32_t)(int)ibf);
+        }
+#pragma unroll
+        for (int g4 = 0; g4 < U / 4; ++g4) {
+            float grp = 0.0f;
+#pragma unroll
+            for (int u = 4 * g4; u < 4 * g4 + 4; ++u) grp += fmaf(w[u], v[u].y - v[u].x, v[u].x);
+            acc += (double)grp;
+        }
+    }
+    for (; j + 3 <= jb; j += 4) {
+        float2 v[4];
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float fb = fmaf((float)(j + u), R.gb, R.fb0);
+            const float ibf = floorf(fb);
+            w[u] = fb - ibf;
+            v[u] = ld2(rs, base + __umul24((uint32_t)(j + u), S) + (uint32_t)(int)ibf);
+        }
+        float grp = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) grp += fmaf(w[u], v[u].y - v[u].x, v[u].x);
+        acc += (double)grp;
+    }
+    for (; j <= jb; ++j) {
+        const float fb = fmaf((float)j, R.gb, R.fb0);
+        const float ibf = floorf(fb);
+        const float wb = fb - ibf;
+        const float2 a = ld2(rs, base + __umul24((uint32_t)j, S) + (uint32_t)(int)ibf);
+        acc += (double)fmaf(wb, a.y - a.x, a.x);
+    }
+    return acc;
+}
+
+// One work-item per ray; 256 consecutive rays of one problem (view-major)
+// per workgroup.
+template <int U>
+__global__ __launch_bounds__(256) void k_bproject2d(const BSlice *__restrict__ sl, int count,
+                                                    const int *__restrict__ pfx, int nblk,
+                                                    const float *__restrict__ pad, uint32_t pad_elems,
+                                                    float *__restrict__ q) {
+    int b;
+    if (!xcd_block(nblk, b)) return;
+    const int s = find_slice(pfx, count, b);
+    const BSlice &S = sl[s];
+    if (*S.stop) return;
+    const int r = (b - pfx[s]) * 256 + (int)threadIdx.x;
+    const int nu = S.g.nu;
+    if (r >= S.g.P * nu) return;
+    const int p = r / nu, a = r - p * nu;
+    const RaySetup R = ray_setup<false>(S.g, S.L, p, 0, a);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(pad, pad_elems);
+    const bool isx = R.ax == 0;
+    const double acc = samples2d<U>(R, rs, isx ? S.pvx : S.pvy, isx ? S.L.sx : S.L.sy, R.j0, R.j1);
+    q[S.roff + r] = (float)(acc * (double)R.step);
+}
+
+// Voxel-driven B_un for 2D problems: a workgroup covers 16 columns x 16 PPT
+// rows, each work-item PPT pixels 16 rows apart.  Per pixel the views are
+// summed in FP32 in groups of four and the groups in FP64, as in the
+// single-problem kernel.
+template <int PPT>
+__global__ __launch_bounds__(256) void k_bbp2d(const BSlice *__restrict__ sl, int count,
+                                               const int *__restrict__ pfx, int nblk,
+                                               const float *__restrict__ q, float *__restrict__ z) {
+    int b;
+    if (!xcd_block(nblk, b)) return;
+    const int s = find_slice(pfx, count, b);
+    const BSlice &S = sl[s];
+    if (*S.stop) return;
+    const GeomK &g = S.g;
+    const int t = b - pfx[s];
+    const int ntx = (g.nx + 15) / 16;
+    const int ix = (t % ntx) * 16 + (int)(threadIdx.x & 15);
+    const int iy0 = (t / ntx) * 16 * PPT + (int)(threadIdx.x >> 4);
+    if (ix >= g.nx || iy0 >= g.ny) return;
+    const float *y = q ? q + S.roff : S.b;
+    const double inv_du = 1.0 / g.du;
+    const double px = (ix - 0.5 * (g.nx - 1)) * g.vox * inv_du;
+    double py[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) py[i] = (iy0 + 16 * i - 0.5 * (g.ny - 1)) * g.vox * inv_du;
+    const double cu = 0.5 * (g.nu - 1);
+    const int nu = g.nu;
+    double acc[PPT];
+    float grp[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) { acc[i] = 0.0; grp[i] = 0.0f; }
+    for (int p = 0; p < g.P; ++p) {
+        const double c = g.cs[2 * p], sn = g.cs[2 * p + 1];
+        const float *yp = y + (size_t)p * nu;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const float fu = (float)(px * c + py[i] * sn + cu);
+            const float iuf = floorf(fu);
+            const float wu = fu - iuf;
+            const int iu = (int)iuf;
+            const bool u0 = iu >= 0 && iu < nu, u1 = iu + 1 >= 0 && iu + 1 < nu;
+            const float va = u0 ? yp[u0 ? iu : 0] : 0.0f;
+            const float vb = u1 ? yp[u1 ? iu + 1 : 0] : 0.0f;
+            grp[i] += fmaf(wu, vb - va, va);
+        }
+        if ((p & 3) == 3 || p == g.P - 1) {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) { acc[i] += (double)grp[i]; grp[i] = 0.0f; }
+        }
+    }
+    const double wgt = g.vox * g.vox * inv_du;
+    float *zs = z + S.voff;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int iy = iy0 + 16 * i;
+        if (iy < g.ny) zs[(size_t)iy * g.nx + ix] = (float)(acc[i] * wgt);
+    }
+}
+
+// Ram-Lak filter of one detector row of one problem per workgroup (rows of
+// up to max_nu bins staged in LDS with zeros on both sides); the same
+// multiply-add order as the single-problem filters.
+__global__ __launch_bounds__(256) void k_bramp(const BSlice *__restrict__ sl, int count,
+                                               const int *__restrict__ pfx, const float *__restrict__ q,
+                                               float *__restrict__ out) {
+    extern __shared__ float sm[];
+    const int s = find_slice(pfx, count, blockIdx.x);
+    const BSlice &S = sl[s];
+    if (*S.stop) return;
+    const int nu = S.g.nu;
+    const int row = blockIdx.x - pfx[s];
+    float *qs = sm;            // [nu zeros][row][nu zeros]
+    float *hs = sm + 3 * nu;
+    const float *qr = (q ? q + S.roff : S.b) + (size_t)row * nu;
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
+        qs[i] = 0.0f;
+        qs[nu + i] = qr[i];
+        qs[2 * nu + i] = 0.0f;
+        hs[i] = S.ramp[i];
+    }
+    __syncthreads();
+    float *orow = out + S.roff + (size_t)row * nu;
+    for (int a = threadIdx.x; a < nu; a += blockDim.x) {
+        const float *qa = qs + nu + a;
+        float acc = hs[0] * qa[0];
+        for (int j = 1; j < nu; j += 2) acc = fmaf(hs[j], qa[-j] + qa[j], acc);
+        orow[a] = acc;
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
@@ -863,7 +1068,7 @@ int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s) {
 int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy, const int *stop,
                     hipStream_t s) {
     dim3 grid((g->k.nx + 31) / 32, (g->k.ny + 31) / 32, g->k.nz);
-    hipLaunchKernelGGL(k_pad_copy, grid, dim3(32, 8), 0, s, x, vx, vy, g->k.nx, g->k.ny, g->pad, stop);
+    hipLaunchKernelGGL(k_pad_copy, grid, dim3(256), 0, s, x, vx, vy, g->k.nx, g->k.ny, g->pad, stop);
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
@@ -983,6 +1188,61 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
         hipLaunchKernelGGL((k_ramp<__half, float>), grid, block, shm, s, (const __half *)q, (float *)out, g->d_ramp, nu, stop);
     else
         hipLaunchKernelGGL((k_ramp<float, __half>), grid, block, shm, s, (const float *)q, (__half *)out, g->d_ramp, nu, stop);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+
+// ------------------------------------------------ batched launchers
+int launch_bpad_copy(const BSlice *sl, int count, const int *pfx, int nblk, const float *vec, float *pad,
+                     hipStream_t s) {
+    if (nblk <= 0) return CT_OK;
+    hipLaunchKernelGGL(k_bpad2d, dim3(nblk), dim3(256), 0, s, sl, count, pfx, vec, pad);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+int launch_bproject2d(const BSlice *sl, int count, const int *pfx, int nblk, int variant, const float *pad,
+                      size_t pad_elems, float *q, hipStream_t s) {
+    if (nblk <= 0) return CT_OK;
+    if ((double)pad_elems * 4.0 >= 4294967296.0) {
+        set_error("batched projector: padded buffer exceeds 4 GiB");
+        return CT_ERR_UNSUPPORTED;
+    }
+    ProfScope prof(PROF_A, s);
+    const dim3 grid((unsigned)(8 * ((nblk + 7) / 8)));
+    if (variant == 1)
+        hipLaunchKernelGGL(k_bproject2d<8>, grid, dim3(256), 0, s, sl, count, pfx, nblk, pad, (uint32_t)pad_elems, q);
+    else
+        hipLaunchKernelGGL(k_bproject2d<4>, grid, dim3(256), 0, s, sl, count, pfx, nblk, pad, (uint32_t)pad_elems, q);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+int launch_bbackproject2d(const BSlice *sl, int count, const int *pfx, int nblk, int variant, const float *q,
+                          float *z, hipStream_t s) {
+    if (nblk <= 0) return CT_OK;
+    ProfScope prof(PROF_B, s);
+    const dim3 grid((unsigned)(8 * ((nblk + 7) / 8)));
+    switch (variant) {
+    case 0: hipLaunchKernelGGL(k_bbp2d<1>, grid, dim3(256), 0, s, sl, count, pfx, nblk, q, z); break;
+    case 1: hipLaunchKernelGGL(k_bbp2d<2>, grid, dim3(256), 0, s, sl, count, pfx, nblk, q, z); break;
+    default: hipLaunchKernelGGL(k_bbp2d<4>, grid, dim3(256), 0, s, sl, count, pfx, nblk, q, z); break;
+    }
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+int launch_bramp(const BSlice *sl, int count, const int *pfx, int nblk, int max_nu, const float *q, float *out,
+                 hipStream_t s) {
+    if (nblk <= 0) return CT_OK;
+    const size_t shm = sizeof(float) * 4 * (size_t)max_nu;
+    if (shm > 64 * 1024) {
+        set_error("batched ramp filter: detector rows longer than 4096 are not supported");
+        return CT_ERR_UNSUPPORTED;
+    }
+    ProfScope prof(PROF_F, s);
+    hipLaunchKernelGGL(k_bramp, dim3(nblk), dim3(256), shm, s, sl, count, pfx, q, out);
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
