@@ -318,21 +318,22 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
 // each voxel feeds about three of the tile's samples, so the patch is staged
 // in LDS once and the taps are read from there.  For each chunk of kPC
 // planes the patch (the union box of the chunk's planes) is copied with
-// 16-byte loads of the rows and columns the box needs, then every ray reads
-// its four taps per plane from LDS.  The box comes from the tile's four
-// corner rays: at a fixed plane the in-plane position is monotone in u and
-// in v, and it is linear in the plane index, so the corners at the chunk's
-// first and last planes bound every ray of the tile.  The next chunk's loads
-// are issued into registers before the current chunk is interpolated.
-// Tiles whose rays do not share a dominant axis, and chunks whose box does
-// not fit, take the direct path.
+// 16-byte loads; the box comes from the tile's four corner rays: at a fixed
+// plane the in-plane position is monotone in u and in v, and it is linear in
+// the plane index, so the corners at the chunk's first and last planes bound
+// every ray of the tile.  The next chunk's loads are issued into registers
+// before the current chunk is interpolated.  The kernel is bound by latency
+// more than by issue, so the LDS footprint is kept small (one buffer, rows
+// sized to the boxes that occur, boxes packed in one word) to keep more
+// workgroups resident.  Tiles whose rays do not share a dominant axis, and
+// chunks whose box does not fit, take the direct path.
 constexpr int kTU = 16, kTV = 16;     // rays per workgroup
 constexpr int kPC = 4;                // planes per staged chunk
-constexpr int kSR = 32, kSC = 48;     // staged row slots / row stride per plane; 48 = 16 (mod 32 banks)
-constexpr int kNQ = 10;               // staged 16-byte columns per row (40 floats)
-constexpr int kSlots = (kPC * kSR * kNQ + 255) / 256;   // staging cells per thread
-static_assert(kSR == 32, "row slots are decoded with shifts");
-constexpr int kMaxChunks = 512;       // planes up to 2048
+constexpr int kSR = 24, kSC = 48;     // staged rows / row stride per plane; 48 = 16 (mod 32 banks)
+constexpr int kNQ = 8;                // staged 16-byte columns per row (32 floats)
+constexpr int kStage = kSR * kNQ;     // work-items that stage (one cell per plane each)
+static_assert(kStage <= kTU * kTV && kNQ * 4 <= kSC, "staging layout");
+constexpr int kMaxChunks = 512;       // planes up to 2048 (longer: direct path)
 constexpr int kVGrp = 8;              // consecutive views kept on one XCD
 
 // Workgroup order: the hardware deals workgroups to the eight XCDs in turn,
@@ -367,10 +368,9 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     int tu, tv, p;
     if (!xcd_tile((g.nu + kTU - 1) / kTU, (g.nv + kTV - 1) / kTV, g.P, tu, tv, p)) return;
     __shared__ float4 tile4[kPC * kSR * kSC / 4];
-    __shared__ short s_box[kMaxChunks][3];   // b0 (aligned to 4, -1: direct), c0, rows
+    __shared__ uint32_t s_box[kMaxChunks];   // (b0 + 1) << 16 | c0 << 6 | rows; b0 = -1: direct
     __shared__ float s_corner[4][4];
     __shared__ int s_axes, s_jlo, s_jhi;
-    const float *tile = (const float *)tile4;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx;
     const int au0 = tu * kTU, av0 = tv * kTV;
     const int au = au0 + tx, av = av0 + ty;
@@ -432,85 +432,98 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
         const int c0 = max((int)floorf(cmin) - 1, 0);
         const int c1 = min((int)floorf(cmax) + 2, nrows - 1);
         const int nr = c1 - c0 + 1;
-        const bool fits = nr <= kSR && b1 - b0 < 4 * kNQ;
-        s_box[c][0] = (short)(fits ? b0 : -1);
-        s_box[c][1] = (short)c0;
-        s_box[c][2] = (short)nr;
+        const bool fits = nr <= kSR && b1 - b0 < 4 * kNQ && c0 < 1024 && b0 < 65535;
+        s_box[c] = fits ? ((uint32_t)(b0 + 1) << 16) | ((uint32_t)c0 << 6) | (uint32_t)nr : 0u;
     }
-    // staging cells of this thread, fixed for the whole block: cell q covers
-    // 16-byte column q % kNQ of row slot q / kNQ (= plane * kSR + row)
-    uint32_t goff[kSlots];     // element offset within the chunk's box
-    int lrow[kSlots];          // row within the plane (skip when >= rows)
-    int loff[kSlots];          // float4 index in the tile (-1: none)
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) {
-        const int q = tid + 256 * k;
-        const int rg = q / kNQ, c4 = q - rg * kNQ;
-        const int pl = rg / kSR, r = rg - pl * kSR;
-        const bool ok = q < kPC * kSR * kNQ;
-        goff[k] = __umul24((uint32_t)pl, S) + __umul24((uint32_t)r, Rw) + 4u * (uint32_t)c4;
-        lrow[k] = ok ? r + kSR * pl : (kPC * kSR) | (kSR - 1);   // invalid: plane kPC, never < nplanes
-        loff[k] = ok ? (rg * kSC) / 4 + c4 : -1;
-    }
-    // cells a chunk does not need are pointed past the end of the buffer:
-    // the range check returns zeros, so the loads need neither branches nor
-    // zero fill
-    float4 pre[kSlots];
+    // Staging: work-item t < kStage owns 16-byte column t % kNQ of box row
+    // t / kNQ in every plane of a chunk, so its element offset within the
+    // box is fixed; per chunk it issues one load and one LDS store per plane
+    // (rows outside the box skip both).
+    const bool stager = tid < kStage;
+    const int r_t = tid / kNQ, c4_t = tid % kNQ;
+    const uint32_t toff = __umul24((uint32_t)r_t, Rw) + 4u * (uint32_t)c4_t;
+    float4 pre[kPC];
     auto fetch = [&](int c) {
+        const uint32_t bx = s_box[c];
+        if (bx == 0u) return;
+        const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u), nr = (int)(bx & 63u);
         const int ja = jlo + c * kPC;
-        const int b0 = s_box[c][0], c0 = s_box[c][1], nr = s_box[c][2];
-        const uint32_t cbase = (base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0) * 4u;
         const int nplanes = min(kPC, Na - ja);
-        // valid iff row < rows and plane < nplanes: lrow = row + kSR * plane
+        if (stager && r_t < nr) {
+            const uint32_t e0 = base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0 + toff;
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            const int pl = lrow[k] >> 5, r = lrow[k] & (kSR - 1);
-            const bool ok = b0 >= 0 && r < nr && pl < nplanes;
-            const uint32_t boff = ok ? cbase + goff[k] * 4u : 0xFFFFFFF0u;
-            const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff, 0, 0);
-            pre[k] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]), __builtin_bit_cast(float, (uint32_t)w[1]),
-                                 __builtin_bit_cast(float, (uint32_t)w[2]), __builtin_bit_cast(float, (uint32_t)w[3]));
+            for (int pl = 0; pl < kPC; ++pl)
+                if (pl < nplanes) {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((e0 + pl * S) * 4u), 0, 0);
+                    pre[pl] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]), __builtin_bit_cast(float, (uint32_t)w[1]),
+                                          __builtin_bit_cast(float, (uint32_t)w[2]), __builtin_bit_cast(float, (uint32_t)w[3]));
+                }
         }
     };
+    const float *tile = (const float *)tile4;
     __syncthreads();   // boxes visible
     if (nch > 0) fetch(0);
     double acc = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int ja = jlo + c * kPC;
-        const int b0 = s_box[c][0], c0 = s_box[c][1];
-        if (b0 >= 0) {
+        const uint32_t bx = s_box[c];
+        const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u);
+        if (bx != 0u) {
+            const int nr = (int)(bx & 63u), nplanes = min(kPC, Na - ja);
             __syncthreads();   // previous chunk's readers are done with the tile
+            if (stager && r_t < nr) {
 #pragma unroll
-            for (int k = 0; k < kSlots; ++k)
-                if (loff[k] >= 0) tile4[loff[k]] = pre[k];
+                for (int pl = 0; pl < kPC; ++pl)
+                    if (pl < nplanes) tile4[(pl * kSR + r_t) * (kSC / 4) + c4_t] = pre[pl];
+            }
             __syncthreads();
         }
         if (c + 1 < nch) fetch(c + 1);
         const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
-        if (b0 < 0) {      // box too large: direct loads for this chunk
+        if (!__any(jf <= jb)) continue;   // no lane of this wavefront samples the chunk
+        if (bx == 0u) {    // box too large: direct loads for this chunk
             if (jf <= jb) acc += direct_samples<true>(R, rs, base, S, Rw, jf, jb);
             continue;
         }
-        // the four planes of the chunk, unrolled; each lane masks the planes
-        // outside its own range
-        const int rb = -(c0 * kSC + b0);
+        // Box-relative coordinates at the chunk's first plane.  Subtracting
+        // the integer box origin is exact, and the box keeps one cell of
+        // margin, so inside the lane's plane range the coordinates are >= 0
+        // and truncation is floor.
+        const float fb0c = active ? fmaf((float)ja, R.gb, R.fb0) - (float)b0 : 0.0f;
+        const float fc0c = active ? fmaf((float)ja, R.gc, R.fc0) - (float)c0 : 0.0f;
+        const bool full = !active || (R.j0 <= ja && R.j1 >= ja + kPC - 1);
         float grp = 0.0f;
+        if (__all(full)) {
+            // every lane samples all planes of the chunk: no masks
 #pragma unroll
-        for (int pl = 0; pl < kPC; ++pl) {
-            const int j = ja + pl;
-            if (j >= jf && j <= jb) {
-                // padded coordinates are positive here (>= kPad - 1 at the
-                // first and last sampled planes), so truncation is floor
-                const float fj = (float)j;
-                const float fb = fmaf(fj, R.gb, R.fb0);
-                const float fc = fmaf(fj, R.gc, R.fc0);
+            for (int pl = 0; pl < kPC; ++pl) {
+                const float fb = pl ? fmaf((float)pl, R.gb, fb0c) : fb0c;
+                const float fc = pl ? fmaf((float)pl, R.gc, fc0c) : fc0c;
                 const float wb = __builtin_amdgcn_fractf(fb), wc = __builtin_amdgcn_fractf(fc);
-                const int o = pl * kSR * kSC + rb + (int)__umul24((uint32_t)(int)fc, (uint32_t)kSC) + (int)fb;
-                const float t00 = tile[o], t01 = tile[o + 1];
-                const float t10 = tile[o + kSC], t11 = tile[o + kSC + 1];
+                const float *t = tile + pl * kSR * kSC + __umul24((uint32_t)(int)fc, (uint32_t)kSC) + (uint32_t)(int)fb;
+                const float t00 = t[0], t01 = t[1], t10 = t[kSC], t11 = t[kSC + 1];
                 const float a0 = fmaf(wb, t01 - t00, t00);
                 const float a1 = fmaf(wb, t11 - t10, t10);
                 grp += fmaf(wc, a1 - a0, a0);
+            }
+        } else {
+            // boundary chunk: planes outside a lane's range are dropped; their
+            // coordinates may leave the box, so the tap indices are clamped
+            // into the tile
+#pragma unroll
+            for (int pl = 0; pl < kPC; ++pl) {
+                const int j = ja + pl;
+                const float fb = pl ? fmaf((float)pl, R.gb, fb0c) : fb0c;
+                const float fc = pl ? fmaf((float)pl, R.gc, fc0c) : fc0c;
+                const float wb = __builtin_amdgcn_fractf(fb), wc = __builtin_amdgcn_fractf(fc);
+                const uint32_t ib = (uint32_t)min(max((int)fb, 0), kSC - 2);
+                const uint32_t ic = (uint32_t)min(max((int)fc, 0), kSR - 2);
+                const float *t = tile + pl * kSR * kSC + __umul24(ic, (uint32_t)kSC) + ib;
+                const float t00 = t[0], t01 = t[1], t10 = t[kSC], t11 = t[kSC + 1];
+                const float a0 = fmaf(wb, t01 - t00, t00);
+                const float a1 = fmaf(wb, t11 - t10, t10);
+                const float v = fmaf(wc, a1 - a0, a0);
+                grp += (j >= jf && j <= jb) ? v : 0.0f;
             }
         }
         acc += (double)grp;
