@@ -62,6 +62,7 @@ struct GeomK {
     int P, nu, nv;
     double vox, du, dv, sod, sdd;
     const double *cs;  // device: cos, sin per view (2*P)
+    const float *cs32; // device: the same table rounded to FP32
     const int *axis;   // device: per-view dominant axis for 2D (0 = x, 1 = y)
 };
 
@@ -100,6 +101,7 @@ struct ct_geometry {
     std::vector<double> h_cs;      // cos, sin per view (host copy)
     std::vector<int> h_axis;       // 2D dominant axis per view
     double *d_cs = nullptr;
+    float *d_cs32 = nullptr;
     int *d_axis = nullptr;
     float *d_ramp = nullptr;       // du * h[j], j = 0..nu-1 (FP32)
     size_t n_vox = 0, n_rays = 0;

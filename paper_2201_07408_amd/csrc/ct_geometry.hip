@@ -205,7 +205,10 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
         else h = -1.0 / (M_PI * M_PI * (double)j * (double)j * d.du);
         taps[j] = (float)h;   // du * h[j]
     }
+    std::vector<float> cs32(2 * (size_t)P);
+    for (size_t i = 0; i < cs32.size(); ++i) cs32[i] = (float)g->h_cs[i];
     bool ok = hipMalloc(&g->d_cs, sizeof(double) * 2 * P) == hipSuccess &&
+              hipMalloc(&g->d_cs32, sizeof(float) * 2 * P) == hipSuccess &&
               hipMalloc(&g->d_axis, sizeof(int) * P) == hipSuccess &&
               hipMalloc(&g->d_ramp, sizeof(float) * d.nu) == hipSuccess;
     if (!ok) {
@@ -214,6 +217,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
         return CT_ERR_ALLOC;
     }
     ok = hipMemcpy(g->d_cs, g->h_cs.data(), sizeof(double) * 2 * P, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(g->d_cs32, cs32.data(), sizeof(float) * 2 * P, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(g->d_axis, g->h_axis.data(), sizeof(int) * P, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(g->d_ramp, taps.data(), sizeof(float) * d.nu, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
@@ -230,6 +234,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     k.vox = d.voxel; k.du = d.du; k.dv = (d.kind == CT_PARALLEL_2D) ? 1.0 : d.dv;
     k.sod = d.sod; k.sdd = d.sdd;
     k.cs = g->d_cs;
+    k.cs32 = g->d_cs32;
     k.axis = g->d_axis;
     g->pad = pad_layout(k);
     *out = g;
@@ -239,6 +244,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
 extern "C" void ct_geometry_destroy(ct_geometry *g) {
     if (!g) return;
     if (g->d_cs) (void)hipFree(g->d_cs);
+    if (g->d_cs32) (void)hipFree(g->d_cs32);
     if (g->d_axis) (void)hipFree(g->d_axis);
     if (g->d_ramp) (void)hipFree(g->d_ramp);
     delete g;

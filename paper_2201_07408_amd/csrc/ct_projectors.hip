@@ -688,39 +688,51 @@ __global__ __launch_bounds__(256) void k_bp_cone_staged(GeomK g, const InT *__re
         }
     } else {
         constexpr int Q = kSU / 4;   // 16-byte chunks per staged row
+        // per-column set-up in FP32 (positions within ~2e-5 detector cells)
+        const float pxf = (float)px, pyf = (float)py;
+        const float sodf = (float)g.sod, sddf = (float)g.sdd, inv_duf = (float)(1.0 / g.du);
+        const float cuf = (float)(0.5 * (nu - 1)), cvf = (float)cv;
+        const float dzf = (float)(g.vox * inv_dv), pz0f = (float)(pz0 * inv_dv), wcf = (float)wconst;
+        // FP32 data with rows a multiple of four: 16-byte staging loads
+        const bool vec4 = sizeof(InT) == 4 && (nu & 3) == 0 && ((uintptr_t)y & 15) == 0;
         for (int p0 = 0; p0 < P; p0 += kVG) {
             __syncthreads();
             for (int q = tid; q < kVG * kSV * Q; q += 256) {
                 const int vv = q / (kSV * Q), r = (q / Q) % kSV, c4 = q % Q;
                 const int p = p0 + vv;
-                float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (p < P) {
                     const int v = s_box[p][1] + r, u = s_box[p][0] + 4 * c4;
                     if (v >= 0 && v < nv) {
                         const InT *row = y + ((size_t)p * nv + v) * nu;
+                        if (vec4 && u >= 0 && u + 3 < nu) {
+                            e = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(row) + u);
+                        } else {
+                            float t4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            if (u + k >= 0 && u + k < nu) e[k] = to_f(row[u + k]);
+                            for (int k = 0; k < 4; ++k)
+                                if (u + k >= 0 && u + k < nu) t4[k] = to_f(row[u + k]);
+                            e = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                        }
                     }
                 }
-                tile4[q] = make_float4(e[0], e[1], e[2], e[3]);
+                tile4[q] = e;
             }
             __syncthreads();
             if (active) {
                 for (int vv = 0; vv < kVG && p0 + vv < P; ++vv) {
                     const int p = p0 + vv;
-                    const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
-                    double fu, M;
-                    project_point(g, px, py, c, s, fu, M);
-                    const float dfv = (float)(M * g.vox * inv_dv);
-                    const float w = (float)(M * M * wconst);
+                    const float c = g.cs32[2 * p], s = g.cs32[2 * p + 1];
+                    const float M = sddf * __builtin_amdgcn_rcpf(fmaf(-pxf, c, fmaf(-pyf, s, sodf)));
+                    const float dfv = M * dzf;
+                    const float w = M * M * wcf;
                     // coordinates relative to the staged box are >= 1 (one
                     // cell of margin), so truncation is floor; the clamps only
                     // guard the tile against rounding
-                    const float fur = (float)(fu - (double)s_box[p][0]);
+                    const float fur = fmaf(M * inv_duf, fmaf(pyf, c, -pxf * s), cuf - (float)s_box[p][0]);
                     const float wu = __builtin_amdgcn_fractf(fur);
                     const int lu = min(max((int)fur, 0), kSU - 2);
-                    const float fv0r = (float)(M * pz0 * inv_dv + cv - (double)s_box[p][1]);
+                    const float fv0r = fmaf(M, pz0f, cvf - (float)s_box[p][1]);
                     const float *tv = tile + vv * kSV * kSU + lu;
 #pragma unroll
                     for (int z = 0; z < kZC; ++z) {
