@@ -66,7 +66,10 @@ def test_batched_matches_sequential_and_oracle(B):
         if np.linalg.norm(ref.x) == 0.0:
             assert np.count_nonzero(xb) == 0
             continue
-        assert rel(xb, xs) <= 1e-6, i
+        # B_un: the same arithmetic as the single-problem path up to FP64 sum
+        # order; B_un F: the single-problem filter sums on the matrix cores,
+        # the batched one on the vector units (each within 1e-5 of the oracle)
+        assert rel(xb, xs) <= (1e-6 if B == "un" else 1e-5), i
         assert rel(xb, ref.x.reshape(d.vol_shape)) <= TOL, i
         assert rel(np.array(r.res), np.array(ref.res)) <= TOL, i
 
