@@ -44,6 +44,7 @@ class _Geom(ctypes.Structure):
         ("nu", ctypes.c_int), ("nv", ctypes.c_int),
         ("du", ctypes.c_double), ("dv", ctypes.c_double),
         ("sod", ctypes.c_double), ("sdd", ctypes.c_double),
+        ("projector", ctypes.c_int),
     ]
 
 
@@ -108,7 +109,7 @@ class Geometry:
                        desc.n_views,
                        self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        uniform, desc.nu, desc.nv, desc.du, desc.dv,
-                       desc.sod, desc.sdd)
+                       desc.sod, desc.sdd, int(getattr(desc, "projector", 0)))
         self.n = desc.nx * desc.ny * desc.nz
         self.m = desc.n_views * desc.nv * desc.nu
         self.vol_shape = (desc.nz, desc.ny, desc.nx)

@@ -11,10 +11,13 @@
  * Operators (Sec. III of the paper names them; the formulas are the readings
  * written out below because the paper defers the discretisation to a
  * textbook):
- *   A     ray-driven forward projector.  Joseph's method: for the dominant
- *         axis a of the ray direction r, sample the ray in every voxel-centre
- *         plane along a, interpolate bilinearly (linearly in 2D) in the plane
- *         with zero outside the grid, sum, and multiply by vox*|r|/|r_a|.
+ *   A     ray-driven forward projector, one of
+ *         Joseph's method (projector 0): for the dominant axis a of the ray
+ *         direction r, sample the ray in every voxel-centre plane along a,
+ *         interpolate bilinearly (linearly in 2D) in the plane with zero
+ *         outside the grid, sum, and multiply by vox*|r|/|r_a|;
+ *         the line-intersection method the paper uses (projector 1,
+ *         Siddon's): A_ij is the length of the part of ray i inside voxel j.
  *   A^T   exact transpose of the same weights (scatter form).
  *   B_un  voxel-driven back-projector: project each voxel centre onto the
  *         detector, interpolate the data linearly (bilinearly in 3D) with zero
@@ -56,6 +59,7 @@ typedef struct {
     int nu, nv;
     double du, dv;
     double sod, sdd;
+    int projector;         /* 0: Joseph, 1: line intersection (Siddon) */
 } orc_geom;
 
 static const double PI = 3.14159265358979323846;
@@ -159,6 +163,81 @@ static double joseph_walk(const orc_geom *g, int p, int av, int au,
     return acc * step;
 }
 
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Line-intersection walk of one ray {o + t r}: every parameter where the ray
+ * crosses a voxel boundary plane inside the volume box is collected and
+ * sorted; each segment between consecutive parameters lies in one voxel,
+ * found from the segment's midpoint, and has length (t2 - t1) |r|.  mode 0:
+ * return sum of length * x; mode 1: scatter val * length into xo; mode 2:
+ * count segments of positive length.  2D rays have r_z = 0 and o_z = 0 and
+ * never leave the single slice.
+ */
+static double siddon_walk(const orc_geom *g, int p, int av, int au,
+                          const double *x, double *xo, double val, int mode,
+                          long *count)
+{
+    double o[3], r[3];
+    int N[3] = { g->nx, g->ny, g->nz };
+    ray_of(g, p, av, au, o, r);
+    double lo[3], t_in = -INFINITY, t_out = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = -0.5 * N[a] * g->vox;
+        double hi = -lo[a];
+        if (r[a] == 0.0) {
+            if (!(o[a] > lo[a] && o[a] < hi)) return 0.0;
+            continue;
+        }
+        double t1 = (lo[a] - o[a]) / r[a], t2 = (hi - o[a]) / r[a];
+        t_in = fmax(t_in, fmin(t1, t2));
+        t_out = fmin(t_out, fmax(t1, t2));
+    }
+    if (!(t_in < t_out)) return 0.0;
+    int cap = N[0] + N[1] + N[2] + 2, n = 0;
+    double *ts = (double *)malloc(sizeof(double) * (size_t)cap);
+    if (!ts) return NAN;
+    ts[n++] = t_in;
+    for (int a = 0; a < 3; ++a) {
+        if (r[a] == 0.0) continue;
+        for (int k = 1; k < N[a]; ++k) {
+            double t = (lo[a] + k * g->vox - o[a]) / r[a];
+            if (t > t_in && t < t_out) ts[n++] = t;
+        }
+    }
+    ts[n++] = t_out;
+    qsort(ts, (size_t)n, sizeof(double), cmp_double);
+    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double acc = 0.0;
+    for (int k = 0; k + 1 < n; ++k) {
+        double len = (ts[k + 1] - ts[k]) * rn;
+        if (!(len > 0.0)) continue;
+        double tm = 0.5 * (ts[k] + ts[k + 1]);
+        int ii[3];
+        for (int a = 0; a < 3; ++a) {
+            int i = (int)floor((o[a] + tm * r[a] - lo[a]) / g->vox);
+            ii[a] = i < 0 ? 0 : (i >= N[a] ? N[a] - 1 : i);
+        }
+        if (mode == 0) acc += len * x[vidx(g, ii)];
+        else if (mode == 1) xo[vidx(g, ii)] += val * len;
+        else (*count)++;
+    }
+    free(ts);
+    return acc;
+}
+
+static double ray_walk(const orc_geom *g, int p, int av, int au, const double *x, double *xo, double val,
+                       int mode, long *count)
+{
+    if (g->projector == 1) return siddon_walk(g, p, av, au, x, xo, val, mode, count);
+    return joseph_walk(g, p, av, au, x, xo, val, mode, count);
+}
+
 /* y = A x */
 void orc_project_A(const orc_geom *g, const double *x, double *y)
 {
@@ -168,7 +247,7 @@ void orc_project_A(const orc_geom *g, const double *x, double *y)
         int au = (int)(rid % g->nu);
         int av = (int)((rid / g->nu) % g->nv);
         int p = (int)(rid / ((long)g->nu * g->nv));
-        y[rid] = joseph_walk(g, p, av, au, x, NULL, 0.0, 0, NULL);
+        y[rid] = ray_walk(g, p, av, au, x, NULL, 0.0, 0, NULL);
     }
 }
 
@@ -182,7 +261,7 @@ void orc_project_A_rays(const orc_geom *g, const double *x, long nsel,
         int au = (int)(rid % g->nu);
         int av = (int)((rid / g->nu) % g->nv);
         int p = (int)(rid / ((long)g->nu * g->nv));
-        out[i] = joseph_walk(g, p, av, au, x, NULL, 0.0, 0, NULL);
+        out[i] = ray_walk(g, p, av, au, x, NULL, 0.0, 0, NULL);
     }
 }
 
@@ -208,7 +287,7 @@ void orc_backproject_AT(const orc_geom *g, const double *y, double *x)
             int au = (int)(rid % g->nu);
             int av = (int)((rid / g->nu) % g->nv);
             int p = (int)(rid / ((long)g->nu * g->nv));
-            joseph_walk(g, p, av, au, NULL, mine, val, 1, NULL);
+            ray_walk(g, p, av, au, NULL, mine, val, 1, NULL);
         }
     }
 #pragma omp parallel for schedule(static)
@@ -220,8 +299,9 @@ void orc_backproject_AT(const orc_geom *g, const double *y, double *x)
     free(buf);
 }
 
-/* Exact number of Joseph samples whose point lies inside the open support
- * box of the grid, i.e. whose bilinear taps touch the volume. */
+/* Exact number of A-updates: Joseph samples whose point lies inside the open
+ * support box of the grid (bilinear taps touch the volume), or, for the
+ * line-intersection projector, ray-voxel segments of positive length. */
 int64_t orc_count_A_updates(const orc_geom *g)
 {
     long nrays = (long)g->nviews * g->nv * g->nu;
@@ -232,7 +312,7 @@ int64_t orc_count_A_updates(const orc_geom *g)
         int av = (int)((rid / g->nu) % g->nv);
         int p = (int)(rid / ((long)g->nu * g->nv));
         long c = 0;
-        joseph_walk(g, p, av, au, NULL, NULL, 0.0, 2, &c);
+        ray_walk(g, p, av, au, NULL, NULL, 0.0, 2, &c);
         total += c;
     }
     return (int64_t)total;

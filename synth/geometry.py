@@ -28,6 +28,7 @@ class GeometryDesc:
     sod: float = 0.0          # source to isocentre (cone only)
     sdd: float = 0.0          # source to detector (cone only)
     angles: Optional[Sequence[float]] = field(default=None)  # None -> uniform set
+    projector: int = 0        # forward model: 0 Joseph, 1 line intersection (Siddon)
 
     @property
     def n_vox(self) -> int:
@@ -47,16 +48,17 @@ class GeometryDesc:
 
 
 def parallel2d(n: int, n_views: int, n_bins: int, voxel: float = 1.0,
-               du: float = 1.0, angles=None) -> GeometryDesc:
+               du: float = 1.0, angles=None, projector: int = 0) -> GeometryDesc:
     return GeometryDesc(PARALLEL_2D, n, n, 1, float(voxel), int(n_views),
                         int(n_bins), 1, float(du), 1.0, 0.0, 0.0,
-                        None if angles is None else tuple(float(a) for a in angles))
+                        None if angles is None else tuple(float(a) for a in angles),
+                        int(projector))
 
 
 def cone3d(n: int, n_views: int, n_det: int, voxel: float = 1.0,
            sod_factor: float = 4.0, sdd_factor: float = 8.0,
            pitch: Optional[float] = None, angles=None, nz: Optional[int] = None,
-           nv: Optional[int] = None) -> GeometryDesc:
+           nv: Optional[int] = None, projector: int = 0) -> GeometryDesc:
     """Circular cone beam with SOD and SDD given as multiples of the volume
     width N*voxel.  The default detector pitch is one voxel seen at the
     isocentre, i.e. voxel*SDD/SOD."""
@@ -68,4 +70,5 @@ def cone3d(n: int, n_views: int, n_det: int, voxel: float = 1.0,
     return GeometryDesc(CONE_3D, n, n, n if nz is None else nz, float(voxel),
                         int(n_views), int(n_det), int(n_det if nv is None else nv),
                         float(pitch), float(pitch), float(sod), float(sdd),
-                        None if angles is None else tuple(float(a) for a in angles))
+                        None if angles is None else tuple(float(a) for a in angles),
+                        int(projector))
