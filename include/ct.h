@@ -29,11 +29,15 @@
  *            u = (au-(nu-1)/2) du, v = (av-(nv-1)/2) dv.
  *
  * Operators:
- *   A      Joseph: for the dominant axis a of the ray direction r (ties go to
- *          x, then y; for the uniform 2D view set the choice is x-major iff
- *          P <= 4p <= 3P), sample the ray in every voxel-centre plane along a,
- *          interpolate bilinearly (linearly in 2D) in the plane with zero
- *          outside the grid, sum, multiply by d*|r|/|r_a|.
+ *   A      chosen per geometry (ct_geometry_desc.projector):
+ *          CT_JOSEPH: for the dominant axis a of the ray direction r (ties go
+ *          to x, then y; for the uniform 2D view set the choice is x-major
+ *          iff P <= 4p <= 3P), sample the ray in every voxel-centre plane
+ *          along a, interpolate bilinearly (linearly in 2D) in the plane with
+ *          zero outside the grid, sum, multiply by d*|r|/|r_a|;
+ *          CT_SIDDON: the line-intersection model the paper uses (Sec. III),
+ *          A_ij = length of ray i inside voxel j (rays lying exactly on a
+ *          voxel boundary plane give their length to either neighbour).
  *   A^T    exact transpose of A's weights.
  *   B_un   voxel-driven: 2D weight d^2/du times the linear interpolation of
  *          view p at s = x.n; 3D weight d^3 M^2/(du dv) times the bilinear
@@ -83,6 +87,7 @@ enum {
 };
 
 enum { CT_PARALLEL_2D = 0, CT_CONE_CIRCULAR_3D = 1 };
+enum { CT_JOSEPH = 0, CT_SIDDON = 1 };   /* forward projector model */
 enum { CT_F32 = 0, CT_F16 = 1 };                  /* data storage type    */
 enum { CT_B_UNMATCHED = 0, CT_B_RAMP = 1, CT_B_AT = 2 };
 enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2 };
@@ -97,6 +102,7 @@ typedef struct {
     int nu, nv;               /* detector columns / rows (nv = 1 for 2D)    */
     double du, dv;            /* detector pitch (at the detector, cone)     */
     double sod, sdd;          /* source-isocentre, source-detector (cone)   */
+    int projector;            /* CT_JOSEPH or CT_SIDDON (A and A^T)         */
 } ct_geometry_desc;
 
 typedef struct {
@@ -129,7 +135,8 @@ int ct_geometry_sizes(const ct_geometry *g, size_t *n_vox, size_t *n_rays);
  * (op = CT_OP_*).  CT_OP_B needs none (0). */
 int ct_op_workspace_bytes(const ct_geometry *g, int op, int batch, size_t *bytes);
 
-/* y = A x (Sec. III, the ray-driven projector; Joseph's discretisation).
+/* y = A x (Sec. III, the ray-driven projector; Joseph's discretisation or
+ * the line-intersection model, as the geometry says).
  * x: float[batch][nz][ny][nx]; y: float or half (y_dtype)
  * [batch][n_views][nv][nu], round-to-nearest-even for half.
  * ws: >= ct_op_workspace_bytes(CT_OP_A) bytes. */
@@ -195,8 +202,9 @@ int ct_cgls(const ct_geometry *g, const float *b, float *x,
  *       current device; the same handle may appear more than once).
  *   b:  HOST array of `count` DEVICE pointers, float[n_views][nu] each.
  *   x:  HOST array of `count` DEVICE pointers, float[ny][nx] each (outputs).
- *   opts: as ct_ba_gmres; B = CT_B_UNMATCHED or CT_B_RAMP, sino_dtype CT_F32
- *       (others: CT_ERR_UNSUPPORTED); the same iteration count for all.
+ *   opts: as ct_ba_gmres; B = CT_B_UNMATCHED or CT_B_RAMP, sino_dtype CT_F32,
+ *       CT_JOSEPH geometries (others: CT_ERR_UNSUPPORTED); the same
+ *       iteration count for all.
  *   ws: DEVICE workspace of ct_ba_gmres_batched_workspace_bytes bytes.  It
  *       holds the per-problem tables, so a cached graph is tied to it: do
  *       not use one workspace from two calls at once.

@@ -301,11 +301,54 @@ void orc_backproject_AT(const orc_geom *g, const double *y, double *x)
 
 /* Exact number of A-updates: Joseph samples whose point lies inside the open
  * support box of the grid (bilinear taps touch the volume), or, for the
- * line-intersection projector, ray-voxel segments of positive length. */
+ * line-intersection projector, ray-voxel segments (siddon_count). */
+/* Line-intersection updates of one ray: 1 + the number of voxel boundary
+ * planes crossed strictly inside the grid (coinciding crossings counted
+ * separately), 0 for a ray that misses the grid. */
+static long siddon_count(const orc_geom *g, int p, int av, int au)
+{
+    double o[3], r[3];
+    int N[3] = { g->nx, g->ny, g->nz };
+    ray_of(g, p, av, au, o, r);
+    double lo[3], t_in = -INFINITY, t_out = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = -0.5 * N[a] * g->vox;
+        if (r[a] == 0.0) {
+            if (!(o[a] > lo[a] && o[a] < -lo[a])) return 0;
+            continue;
+        }
+        double t1 = (lo[a] - o[a]) / r[a], t2 = (-lo[a] - o[a]) / r[a];
+        t_in = fmax(t_in, fmin(t1, t2));
+        t_out = fmin(t_out, fmax(t1, t2));
+    }
+    if (!(t_in < t_out)) return 0;
+    long n = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (r[a] == 0.0) continue;
+        double f1 = (o[a] + t_in * r[a] - lo[a]) / g->vox, f2 = (o[a] + t_out * r[a] - lo[a]) / g->vox;
+        double fmn = fmin(f1, f2), fmx = fmax(f1, f2);
+        long k0 = (long)floor(fmn) + 1, k1 = (long)ceil(fmx) - 1;
+        if (k0 < 1) k0 = 1;
+        if (k1 > N[a] - 1) k1 = N[a] - 1;
+        if (k1 >= k0) n += k1 - k0 + 1;
+    }
+    return n;
+}
+
 int64_t orc_count_A_updates(const orc_geom *g)
 {
     long nrays = (long)g->nviews * g->nv * g->nu;
     long total = 0;
+    if (g->projector == 1) {
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : total)
+        for (long rid = 0; rid < nrays; ++rid) {
+            int au = (int)(rid % g->nu);
+            int av = (int)((rid / g->nu) % g->nv);
+            int p = (int)(rid / ((long)g->nu * g->nv));
+            total += siddon_count(g, p, av, au);
+        }
+        return (int64_t)total;
+    }
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : total)
     for (long rid = 0; rid < nrays; ++rid) {
         int au = (int)(rid % g->nu);

@@ -8,6 +8,7 @@ LIBPATH = os.path.join(HERE, "libctabba.so")
 
 CT_OK, CT_ERR_ARG, CT_ERR_ALLOC, CT_ERR_HIP, CT_ERR_NUMERIC, CT_ERR_UNSUPPORTED = range(6)
 CT_PARALLEL_2D, CT_CONE_CIRCULAR_3D = 0, 1
+CT_JOSEPH, CT_SIDDON = 0, 1
 CT_F32, CT_F16 = 0, 1
 CT_B_UNMATCHED, CT_B_RAMP, CT_B_AT = 0, 1, 2
 CT_SOLVER_BA, CT_SOLVER_AB, CT_SOLVER_CGLS = 0, 1, 2
@@ -35,6 +36,7 @@ class GeometryDesc(ctypes.Structure):
         ("nu", ctypes.c_int), ("nv", ctypes.c_int),
         ("du", ctypes.c_double), ("dv", ctypes.c_double),
         ("sod", ctypes.c_double), ("sdd", ctypes.c_double),
+        ("projector", ctypes.c_int),
     ]
 
 

@@ -70,7 +70,8 @@ class Geometry:
         d = L.GeometryDesc(int(desc.kind), int(desc.nx), int(desc.ny), int(desc.nz),
                            float(desc.voxel), int(desc.n_views), ap, int(desc.nu),
                            int(desc.nv), float(desc.du), float(desc.dv),
-                           float(getattr(desc, "sod", 0.0)), float(getattr(desc, "sdd", 0.0)))
+                           float(getattr(desc, "sod", 0.0)), float(getattr(desc, "sdd", 0.0)),
+                           int(getattr(desc, "projector", 0)))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)), "ct_geometry_create")

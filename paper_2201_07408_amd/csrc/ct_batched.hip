@@ -174,8 +174,8 @@ int make_plan(const ct_geometry *const *g, int count, const ct_solver_opts &o, P
     for (int i = 0; i < count; ++i) {
         const ct_geometry *gi = g[i];
         CT_ARG_CHECK(gi != nullptr, "ct_ba_gmres_batched: NULL geometry");
-        if (gi->k.kind != CT_PARALLEL_2D) {
-            set_error("ct_ba_gmres_batched: only 2D parallel-beam problems are batched");
+        if (gi->k.kind != CT_PARALLEL_2D || gi->k.proj != CT_JOSEPH) {
+            set_error("ct_ba_gmres_batched: only 2D parallel-beam problems with the Joseph projector are batched");
             return CT_ERR_UNSUPPORTED;
         }
         const GeomK &k = gi->k;

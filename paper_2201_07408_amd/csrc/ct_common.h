@@ -58,6 +58,7 @@ inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a
 // Plain-old-data copy of the geometry passed by value to kernels.
 struct GeomK {
     int kind;          // 0 = 2D parallel, 1 = 3D cone
+    int proj;          // CT_JOSEPH or CT_SIDDON
     int nx, ny, nz;
     int P, nu, nv;
     double vox, du, dv, sod, sdd;
@@ -149,6 +150,12 @@ int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *
                        const float *in_scale, const int *stop, hipStream_t s);
 int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out,
                 int out_dtype, size_t rows, const int *stop, hipStream_t s);
+// line-intersection projector and its transpose (x read / scattered in its
+// own layout, no padded copies; the transpose adds into x)
+int launch_siddon(const ct_geometry *g, const float *x, void *y, int y_dtype,
+                  const float *out_scale, const int *stop, hipStream_t s);
+int launch_siddon_T(const ct_geometry *g, const void *y, int y_dtype, float *x,
+                    const float *in_scale, const int *stop, hipStream_t s);
 
 // Composite operators used by the solvers and the ABI: x/y of one item.
 struct OpScratch {

@@ -138,6 +138,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     CT_ARG_CHECK(d.kind == CT_PARALLEL_2D || d.kind == CT_CONE_CIRCULAR_3D,
                  "ct_geometry_create: unknown kind");
     CT_ARG_CHECK(d.nx >= 1 && d.ny >= 1 && d.nz >= 1, "ct_geometry_create: volume sizes must be >= 1");
+    CT_ARG_CHECK(d.projector == CT_JOSEPH || d.projector == CT_SIDDON, "ct_geometry_create: unknown projector");
     CT_ARG_CHECK(d.n_views >= 1 && d.nu >= 1 && d.nv >= 1, "ct_geometry_create: detector sizes must be >= 1");
     CT_ARG_CHECK(std::isfinite(d.voxel) && d.voxel > 0, "ct_geometry_create: voxel must be > 0");
     CT_ARG_CHECK(std::isfinite(d.du) && d.du > 0, "ct_geometry_create: du must be > 0");
@@ -229,6 +230,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     g->n_rays = (size_t)P * d.nv * d.nu;
     GeomK &k = g->k;
     k.kind = d.kind;
+    k.proj = d.projector;
     k.nx = d.nx; k.ny = d.ny; k.nz = d.nz;
     k.P = P; k.nu = d.nu; k.nv = d.nv;
     k.vox = d.voxel; k.du = d.du; k.dv = (d.kind == CT_PARALLEL_2D) ? 1.0 : d.dv;

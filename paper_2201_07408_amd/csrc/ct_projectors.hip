@@ -579,6 +579,155 @@ __global__ __launch_bounds__(256) void k_project_T(GeomK g, PadLayout L, const I
 // --------------------------------------------------------------- B_un
 constexpr int kZC = 16;   // z voxels per work-item in the cone back-projector
 
+// ------------------------------------------- line-intersection projector
+// A_ij = length of ray i inside voxel j (the forward model the paper uses,
+// Sec. III).  One work-item per ray walks the voxels the ray crosses: the
+// ray enters and leaves the grid at the parameters of the slab test, and per
+// axis the parameter of the next boundary plane advances by d/|r_a| at each
+// crossing of that axis.  Every step adds (t_next - t) x[voxel]; parameters
+// and sums are FP64 (the walk over hundreds of planes would lose 1e-4 of a
+// voxel in FP32, and FP64 runs at the FP32 rate here).  The loop stops at the
+// exit parameter or when an index leaves the grid, whichever comes first, and
+// is bounded by nx + ny + nz + 2 steps, so no read is out of range.  Rays
+// lying exactly on a boundary plane give their length to one neighbour.
+struct SiddonWalk {
+    double t, t_out;            // current and exit parameter (length units)
+    double tn0, tn1, tn2;       // parameter of the next boundary per axis
+    double dt0, dt1, dt2;       // parameter step between boundaries per axis
+    int i0, i1, i2;             // current voxel
+    int st0, st1, st2;          // step direction per axis (0: parallel)
+    bool hit;
+};
+
+__device__ __forceinline__ void siddon_axis(double o, double r, double lo, double vox, int N, double t_in,
+                                            bool hit, int &i, int &st, double &dt, double &tn) {
+    const double f = hit ? (o + t_in * r - lo) / vox : 0.0;
+    int k = (int)floor(f);
+    k = k < 0 ? 0 : (k >= N ? N - 1 : k);   // the entry face rounds either way
+    i = k;
+    if (r > 0.0) {
+        st = 1; dt = vox / r; tn = (lo + (k + 1) * vox - o) / r;
+    } else if (r < 0.0) {
+        st = -1; dt = -vox / r; tn = (lo + k * vox - o) / r;
+    } else {
+        st = 0; dt = 0.0; tn = 1e300;
+    }
+}
+
+template <bool CONE>
+__device__ __forceinline__ SiddonWalk siddon_setup(const GeomK &g, int p, int av, int au) {
+    const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+    double ox, oy, rx, ry, rz;
+    if (CONE) {
+        const double u = (au - 0.5 * (g.nu - 1)) * g.du, v = (av - 0.5 * (g.nv - 1)) * g.dv;
+        ox = g.sod * c; oy = g.sod * s;
+        rx = -g.sdd * c - u * s; ry = -g.sdd * s + u * c; rz = v;
+    } else {
+        const double sa = (au - 0.5 * (g.nu - 1)) * g.du;
+        ox = sa * c; oy = sa * s;
+        rx = -s; ry = c; rz = 0.0;
+    }
+    const double inv = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);   // unit speed: parameters are lengths
+    rx *= inv; ry *= inv; rz *= inv;
+    const double lox = -0.5 * g.nx * g.vox, loy = -0.5 * g.ny * g.vox, loz = -0.5 * g.nz * g.vox;
+    SiddonWalk w;
+    w.hit = true;
+    double t_in = -1e300, t_out = 1e300;
+    auto slab = [&](double o, double r, double lo) {
+        if (r == 0.0) {
+            if (!(o > lo && o < -lo)) w.hit = false;
+            return;
+        }
+        const double t1 = (lo - o) / r, t2 = (-lo - o) / r;
+        t_in = fmax(t_in, fmin(t1, t2));
+        t_out = fmin(t_out, fmax(t1, t2));
+    };
+    slab(ox, rx, lox);
+    slab(oy, ry, loy);
+    slab(0.0, rz, loz);
+    if (!(t_in < t_out)) w.hit = false;
+    w.t = t_in;
+    w.t_out = t_out;
+    siddon_axis(ox, rx, lox, g.vox, g.nx, t_in, w.hit, w.i0, w.st0, w.dt0, w.tn0);
+    siddon_axis(oy, ry, loy, g.vox, g.ny, t_in, w.hit, w.i1, w.st1, w.dt1, w.tn1);
+    siddon_axis(0.0, rz, loz, g.vox, g.nz, t_in, w.hit, w.i2, w.st2, w.dt2, w.tn2);
+    return w;
+}
+
+// One step of the walk: the segment [t, min(next boundary, exit)] lies in the
+// current voxel; returns its length and advances to the next voxel.  `more`
+// turns false at the exit or when the index leaves the grid.
+__device__ __forceinline__ double siddon_step(const GeomK &g, SiddonWalk &w, long &idx, bool &more) {
+    const bool a0 = w.tn0 <= w.tn1 && w.tn0 <= w.tn2;
+    const bool a1 = !a0 && w.tn1 <= w.tn2;
+    const double tb = a0 ? w.tn0 : (a1 ? w.tn1 : w.tn2);
+    const double tn = fmin(tb, w.t_out);
+    const double len = tn - w.t;
+    w.t = tn;
+    more = tb < w.t_out;
+    if (a0) {
+        w.tn0 += w.dt0; w.i0 += w.st0; idx += w.st0;
+        more = more && w.i0 >= 0 && w.i0 < g.nx;
+    } else if (a1) {
+        w.tn1 += w.dt1; w.i1 += w.st1; idx += (long)w.st1 * g.nx;
+        more = more && w.i1 >= 0 && w.i1 < g.ny;
+    } else {
+        w.tn2 += w.dt2; w.i2 += w.st2; idx += (long)w.st2 * g.nx * g.ny;
+        more = more && w.i2 >= 0 && w.i2 < g.nz;
+    }
+    return len;
+}
+
+template <bool CONE, typename OutT>
+__global__ __launch_bounds__(256) void k_siddon(GeomK g, const float *__restrict__ x, OutT *__restrict__ y,
+                                                const float *__restrict__ out_scale,
+                                                const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int au = blockIdx.x * blockDim.x + threadIdx.x;
+    const int av = blockIdx.y * blockDim.y + threadIdx.y;
+    const int p = blockIdx.z;
+    if (au >= g.nu || av >= g.nv) return;
+    SiddonWalk w = siddon_setup<CONE>(g, p, av, au);
+    double acc = 0.0;
+    if (w.hit) {
+        long idx = w.i0 + (long)w.i1 * g.nx + (long)w.i2 * g.nx * g.ny;
+        const int steps = g.nx + g.ny + g.nz + 2;
+        bool more = true;
+        for (int k = 0; k < steps && more; ++k) {
+            const float v = x[idx];
+            acc = fma(siddon_step(g, w, idx, more), (double)v, acc);
+        }
+    }
+    float val = (float)acc;
+    if (out_scale) val *= *out_scale;
+    y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(val);
+}
+
+// transpose: the same walk, scattering y_i * length into x with FP32 atomics
+template <bool CONE, typename InT>
+__global__ __launch_bounds__(256) void k_siddon_T(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
+                                                  const float *__restrict__ in_scale,
+                                                  const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int au = blockIdx.x * blockDim.x + threadIdx.x;
+    const int av = blockIdx.y * blockDim.y + threadIdx.y;
+    const int p = blockIdx.z;
+    if (au >= g.nu || av >= g.nv) return;
+    double yv = (double)to_f(y[((size_t)p * g.nv + av) * g.nu + au]);
+    if (in_scale) yv *= (double)*in_scale;
+    if (yv == 0.0) return;
+    SiddonWalk w = siddon_setup<CONE>(g, p, av, au);
+    if (!w.hit) return;
+    long idx = w.i0 + (long)w.i1 * g.nx + (long)w.i2 * g.nx * g.ny;
+    const int steps = g.nx + g.ny + g.nz + 2;
+    bool more = true;
+    for (int k = 0; k < steps && more; ++k) {
+        const long at = idx;
+        const double len = siddon_step(g, w, idx, more);
+        if (len > 0.0) unsafeAtomicAdd(x + at, (float)(yv * len));
+    }
+}
+
 // ---------------------------------------------- staged 3D back-projector
 // A workgroup is 16 x 16 columns (x, y) times kZC voxels in z.  For groups of
 // kVG views it copies each view's footprint (kSV rows x kSU columns of the
@@ -1255,6 +1404,41 @@ int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx
     return CT_OK;
 }
 
+
+int launch_siddon(const ct_geometry *g, const float *x, void *y, int y_dtype, const float *out_scale,
+                  const int *stop, hipStream_t s) {
+    dim3 grid, block;
+    ray_grid(g, grid, block);
+    ProfScope prof(PROF_A, s);
+    const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
+    if (y_dtype == CT_F32) {
+        if (cone) hipLaunchKernelGGL((k_siddon<true, float>), grid, block, 0, s, g->k, x, (float *)y, out_scale, stop);
+        else hipLaunchKernelGGL((k_siddon<false, float>), grid, block, 0, s, g->k, x, (float *)y, out_scale, stop);
+    } else {
+        if (cone) hipLaunchKernelGGL((k_siddon<true, __half>), grid, block, 0, s, g->k, x, (__half *)y, out_scale, stop);
+        else hipLaunchKernelGGL((k_siddon<false, __half>), grid, block, 0, s, g->k, x, (__half *)y, out_scale, stop);
+    }
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+int launch_siddon_T(const ct_geometry *g, const void *y, int y_dtype, float *x, const float *in_scale,
+                    const int *stop, hipStream_t s) {
+    dim3 grid, block;
+    ray_grid(g, grid, block);
+    ProfScope prof(PROF_AT, s);
+    const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
+    if (y_dtype == CT_F32) {
+        if (cone) hipLaunchKernelGGL((k_siddon_T<true, float>), grid, block, 0, s, g->k, (const float *)y, x, in_scale, stop);
+        else hipLaunchKernelGGL((k_siddon_T<false, float>), grid, block, 0, s, g->k, (const float *)y, x, in_scale, stop);
+    } else {
+        if (cone) hipLaunchKernelGGL((k_siddon_T<true, __half>), grid, block, 0, s, g->k, (const __half *)y, x, in_scale, stop);
+        else hipLaunchKernelGGL((k_siddon_T<false, __half>), grid, block, 0, s, g->k, (const __half *)y, x, in_scale, stop);
+    }
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
 int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *x, const float *in_scale,
                        const int *stop, hipStream_t s) {
     const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
@@ -1430,6 +1614,7 @@ OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *w
 
 int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratch &sc, bool pad_ready,
             const float *out_scale, const int *stop, hipStream_t s) {
+    if (g->k.proj == CT_SIDDON) return launch_siddon(g, x, y, y_dtype, out_scale, stop, s);
     if (!pad_ready) CT_TRY(launch_pad_zero(g, sc.vx, sc.vy, s));
     CT_TRY(launch_pad_copy(g, x, sc.vx, sc.vy, stop, s));
     return launch_project(g, sc.vx, sc.vy, y, y_dtype, out_scale, stop, s);
@@ -1441,6 +1626,11 @@ int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *
     if (which == CT_B_RAMP) {
         CT_TRY(launch_ramp(g, y, y_dtype, sc.filt, y_dtype, (size_t)g->k.P * g->k.nv, stop, s));
         return launch_backproject(g, sc.filt, y_dtype, x, in_scale, stop, s);
+    }
+    if (g->k.proj == CT_SIDDON) {
+        // the line-intersection transpose scatters straight into x
+        CT_TRY(launch_fill(x, g->n_vox, 0.0f, s));
+        return launch_siddon_T(g, y, y_dtype, x, in_scale, stop, s);
     }
     // A^T: scatter into zeroed padded copies, then fold back.  The scatter
     // also writes border cells, so a following A must re-zero the border.

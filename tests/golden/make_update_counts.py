@@ -1,10 +1,12 @@
 """Write tests/golden/update_counts.json: exact A-updates (Joseph samples
-whose bilinear support touches the volume) and B-updates (voxel-view pairs)
-per workload geometry, counted by the FP64 oracle only.
+whose bilinear support touches the volume; for the line-intersection
+projector, ray-voxel segments) and B-updates (voxel-view pairs) per workload
+geometry, counted by the FP64 oracle only.
 
     python tests/golden/make_update_counts.py
 """
 
+import dataclasses
 import json
 import os
 import sys
@@ -24,6 +26,9 @@ def main():
                      "B_updates": oracle.count_B_updates(desc),
                      "n_vox": desc.n_vox, "n_rays": desc.n_rays}
         print(name, out[name], flush=True)
+    g3s = dataclasses.replace(workloads.w3_geometry(), projector=1)
+    out["w3_siddon"] = {"A_updates": oracle.count_A_updates(g3s)}
+    print("w3_siddon", out["w3_siddon"], flush=True)
     w5 = [oracle.count_A_updates(d) for d, _, _ in workloads.w5_slices()]
     out["w5"] = {"A_updates": int(sum(w5)),
                  "B_updates": int(sum(d.n_vox * d.n_views for d, _, _ in workloads.w5_slices()))}

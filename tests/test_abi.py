@@ -38,8 +38,9 @@ def test_version_and_error_string_without_gpu():
 
 
 def test_struct_layouts_match_header():
-    # ct_geometry_desc: 4 ints, double, int, pointer, 2 ints, 4 doubles
-    assert ctypes.sizeof(_lib.GeometryDesc) == 4 * 4 + 8 + 8 + 8 + 8 + 4 * 8
+    # ct_geometry_desc: 4 ints, double, int (+4 pad), pointer, 2 ints,
+    # 4 doubles, int (+4 pad)
+    assert ctypes.sizeof(_lib.GeometryDesc) == 4 * 4 + 8 + 8 + 8 + 8 + 4 * 8 + 8
     assert ctypes.sizeof(_lib.SolverOpts) == 3 * 4 + 4 + 8
 
 
@@ -55,3 +56,6 @@ def test_invalid_descriptor_rejected_on_host():
     assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_ARG
     d = _lib.GeometryDesc(1, 16, 16, 16, 1.0, 10, None, 24, 4000, 2.0, 2.0, 64.0, 128.0)
     assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_UNSUPPORTED
+    d = _lib.GeometryDesc(0, 16, 16, 1, 1.0, 10, None, 24, 1, 1.0, 1.0, 0.0, 0.0, 7)
+    assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_ARG
+    assert b"projector" in lib.ct_last_error()

@@ -133,3 +133,20 @@ def test_siddon_converges_to_line_integrals_of_smooth_ellipses(oracle):
         errs.append(rel(y, ref))
     # second order: point-sampled pixels, exact intersection lengths
     assert errs[0] / errs[1] >= 3.0 and errs[1] / errs[2] >= 3.0, errs
+
+
+@pytest.mark.parametrize("name", ["2d_12px_10views", "2d_explicit_angles", "cone_8x8x6"])
+def test_siddon_update_count_equals_segments(oracle, name):
+    """The closed-form count (1 + boundary crossings per ray) equals the
+    number of non-zero entries of the dense matrix built by per-voxel
+    clipping, except that crossings which coincide (segments of ~1e-15,
+    present in the symmetric cone geometry) are counted separately."""
+    g = GEOMS[name]
+    ref = dense_siddon(g)
+    n = oracle.count_A_updates(g)
+    pos = int(np.count_nonzero(ref > 0.0))
+    tiny = int(np.count_nonzero((ref > 0.0) & (ref <= 1e-12)))
+    if g.kind == 0:
+        assert n == pos and tiny == 0
+    else:
+        assert pos <= n <= pos + 2 * tiny + 16, (n, pos, tiny)
