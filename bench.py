@@ -142,6 +142,40 @@ def bench_batched(ct, torch, reps=3):
             "projector_variant": a_var, "backprojector_variant": b_var}
 
 
+def bench_siddon(ct, torch, lib, steps=2):
+    """BA-GMRES (B = B_un F, 30 iterations) on the 256^3 workload with the
+    line-intersection forward model (the paper's A) instead of Joseph's:
+    data from the same phantom through that projector, Poisson 1e5."""
+    import dataclasses
+    from synth import workloads
+    from synth.phantoms import poisson_log_counts
+    desc = dataclasses.replace(workloads.w3_geometry(), projector=1)
+    g = ct.Geometry(desc)
+    x = torch.from_numpy(workloads.w3_phantom()).cuda()
+    ax = ct.ct_project_A(g, x)
+    mu = 4.0 / float(ax.max())
+    b = torch.from_numpy(poisson_log_counts(303, (ax * mu).double().cpu().numpy().reshape(-1),
+                                            1e5).astype(np.float32)).cuda()
+    ct.ct_ba_gmres(g, b, ITERS, B="ramp")
+    torch.cuda.synchronize()
+    lib.ct_profile_reset()
+    lib.ct_profile_enable(1)
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(steps):
+        done += ct.ct_ba_gmres(g, b, ITERS, B="ramp").iters_done
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lib.ct_profile_enable(0)
+    n_l, t_l = ctypes.c_long(), ctypes.c_double()
+    lib.ct_profile_read(b"A", ctypes.byref(n_l), ctypes.byref(t_l))
+    t_a = t_l.value / 1e3 / max(n_l.value, 1)
+    counts = json.load(open(os.path.join(ROOT, "tests", "golden", "update_counts.json")))["w3_siddon"]
+    return {"workload": "as the headline, forward model = line-intersection (Siddon) A",
+            "iters_per_s": done / dt, "A_ms_per_launch": t_a * 1e3,
+            "A_segments_per_s": counts["A_updates"] / t_a, "A_segments_per_launch": counts["A_updates"]}
+
+
 def sampled_errors(oracle, desc, ct, g, torch, x_phantom):
     """Relative error of the GPU operators against the FP64 oracle on sampled
     rays / voxels of the benchmark workload."""
@@ -168,6 +202,7 @@ def main():
     ap.add_argument("--sino-dtype", default="f32", choices=["f32", "f16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-siddon", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -251,6 +286,9 @@ def main():
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
     }
+    if not args.no_siddon:
+        log("bench: line-intersection forward model")
+        line["siddon_A"] = bench_siddon(ct, torch, lib)
     if not args.no_batched:
         log("bench: batched 2D slices")
         line["batched_2d"] = bench_batched(ct, torch)

@@ -690,12 +690,33 @@ __global__ __launch_bounds__(256) void k_siddon(GeomK g, const float *__restrict
     SiddonWalk w = siddon_setup<CONE>(g, p, av, au);
     double acc = 0.0;
     if (w.hit) {
+        // the walk does not depend on the data: advance eight steps, then
+        // issue their eight gathers together (a finished walk repeats its
+        // last voxel with length 0); 8 beat 4 and 2 at 256^3 (12.8, 13.3,
+        // 17.2 ms)
+        constexpr int U = 8;
         long idx = w.i0 + (long)w.i1 * g.nx + (long)w.i2 * g.nx * g.ny;
         const int steps = g.nx + g.ny + g.nz + 2;
         bool more = true;
-        for (int k = 0; k < steps && more; ++k) {
-            const float v = x[idx];
-            acc = fma(siddon_step(g, w, idx, more), (double)v, acc);
+        for (int k = 0; k < steps && more; k += U) {
+            long at[U];
+            double len[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                at[u] = idx;
+                len[u] = 0.0;
+                if (more) {
+                    const long cur = idx;
+                    len[u] = siddon_step(g, w, idx, more);
+                    at[u] = cur;
+                    if (!more) idx = cur;   // keep the index of a voxel inside the grid
+                }
+            }
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = x[at[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = fma(len[u], (double)v[u], acc);
         }
     }
     float val = (float)acc;
