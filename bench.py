@@ -76,12 +76,12 @@ def projector_src_hash():
 
 def cpu_baseline(desc, b_host, x_phantom):
     """FP64 oracle BA-GMRES (ramp) on a bounded sample: the same volume and
-    detector with every 8th view (45 of 360), 3 iterations.  The operator
+    detector with every 4th view (90 of 360), 3 iterations.  The operator
     cost is linear in the number of views, so seconds per full iteration are
-    estimated as (sample seconds per iteration) * 8."""
+    estimated as (sample seconds per iteration) * 4."""
     import oracle
     from synth.geometry import GeometryDesc
-    sub = 8
+    sub = 4
     angles = [2 * math.pi * p / desc.n_views for p in range(0, desc.n_views, sub)]
     gs = GeometryDesc(desc.kind, desc.nx, desc.ny, desc.nz, desc.voxel, len(angles), desc.nu,
                       desc.nv, desc.du, desc.dv, desc.sod, desc.sdd, tuple(angles))
@@ -94,8 +94,8 @@ def cpu_baseline(desc, b_host, x_phantom):
     out = {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.num_threads(),
            "kind": "oracle",
            "sample": "FP64 oracle BA-GMRES (B_un F), 3 iterations on the 256^3 volume and "
-                     "384x384 detector with 45 of the 360 views (every 8th); seconds per "
-                     "iteration scaled by 8 (operator cost is linear in views); %.1f s of CPU "
+                     "384x384 detector with 90 of the 360 views (every 4th); seconds per "
+                     "iteration scaled by 4 (operator cost is linear in views); %.1f s of CPU "
                      "work" % dt}
     return out, oracle
 
