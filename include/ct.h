@@ -90,7 +90,7 @@ enum { CT_PARALLEL_2D = 0, CT_CONE_CIRCULAR_3D = 1 };
 enum { CT_JOSEPH = 0, CT_SIDDON = 1 };   /* forward projector model */
 enum { CT_F32 = 0, CT_F16 = 1 };                  /* data storage type    */
 enum { CT_B_UNMATCHED = 0, CT_B_RAMP = 1, CT_B_AT = 2 };
-enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2 };
+enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2, CT_SOLVER_BA_MONITOR = 3 };
 enum { CT_OP_A = 0, CT_OP_B = 1, CT_OP_B_RAMP = 2, CT_OP_AT = 3 };
 
 typedef struct {
@@ -162,7 +162,8 @@ int ct_backproject_AT(const ct_geometry *g, const void *y, int y_dtype, float *x
 int ct_ramp_filter(const ct_geometry *g, const float *q, float *y, int batch,
                    void *stream);
 
-/* Workspace bytes for a solver (CT_SOLVER_*) with the given options. */
+/* Workspace bytes for a solver (CT_SOLVER_*, CT_SOLVER_BA_MONITOR for
+ * ct_ba_gmres_monitor) with the given options. */
 int ct_solver_workspace_bytes(const ct_geometry *g, int solver,
                               const ct_solver_opts *opts, size_t *bytes);
 
@@ -177,6 +178,25 @@ int ct_solver_workspace_bytes(const ct_geometry *g, int solver,
 int ct_ba_gmres(const ct_geometry *g, const float *b, float *x,
                 const ct_solver_opts *opts, void *ws, size_t ws_bytes,
                 double *res_hist, int *iters_done, void *stream);
+
+/* BA-GMRES as ct_ba_gmres, plus the per-iteration curves the paper plots
+ * (Sec. IV: data residual and image error against the iteration number),
+ * without applying A again: the projections A w_k computed by the
+ * iteration are kept (n_views*nv*nu floats per iteration in the
+ * workspace; query with solver CT_SOLVER_BA_MONITOR) and combined with the
+ * coefficients of each iterate x_k.
+ *   x_ref:    DEVICE float[nz][ny][nx] reference image, or NULL.
+ *   data_res: HOST double[iters+1] or NULL; data_res[k] = ||b - A x_k||
+ *             (data_res[0] = ||b||).
+ *   img_rmse: HOST double[iters+1] or NULL; img_rmse[k] =
+ *             sqrt(sum (x_k - x_ref)^2 / n) (NaN without x_ref).
+ * Entries after a breakdown are NaN.  opts->sino_dtype must be CT_F32
+ * (CT_ERR_UNSUPPORTED otherwise).  x and res_hist equal ct_ba_gmres's. */
+int ct_ba_gmres_monitor(const ct_geometry *g, const float *b, float *x,
+                        const float *x_ref, const ct_solver_opts *opts,
+                        void *ws, size_t ws_bytes, double *res_hist,
+                        double *data_res, double *img_rmse, int *iters_done,
+                        void *stream);
 
 /* AB-GMRES (Sec. II, Eq. 4): y_K minimises ||b - A B y|| over
  * K_K(A B, b), x = B y.  Basis in data space.  res_hist[k] = ||b - A x_k||

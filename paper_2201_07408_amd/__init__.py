@@ -16,6 +16,8 @@ from .api import (  # noqa: F401
     ct_backproject_AT,
     ct_ramp_filter,
     ct_ba_gmres,
+    ct_ba_gmres_monitor,
+    MonitorResult,
     ct_ab_gmres,
     ct_cgls,
     ct_ba_gmres_batched,

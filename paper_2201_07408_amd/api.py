@@ -209,6 +209,46 @@ def ct_ba_gmres(g: Geometry, b: torch.Tensor, iters: int, B: str = "un", sino_dt
     return _solve("ct_ba_gmres", L.CT_SOLVER_BA, g, b, iters, B, sino_dtype, breakdown_tol, out)
 
 
+@dataclass
+class MonitorResult:
+    x: torch.Tensor
+    res: List[float]
+    data_res: List[float]      # ||b - A x_k||, k = 0..iters_done
+    img_rmse: List[float]      # RMSE(x_k - x_ref) (NaN without x_ref)
+    iters_done: int
+
+
+def ct_ba_gmres_monitor(g: Geometry, b: torch.Tensor, iters: int, B: str = "un",
+                        x_ref: Optional[torch.Tensor] = None, breakdown_tol: float = 0.0,
+                        out: Optional[torch.Tensor] = None) -> MonitorResult:
+    """BA-GMRES with the per-iteration data residual and image error."""
+    _need_device(b, "b", torch.float32)
+    if b.numel() != g.n_rays:
+        raise ValueError("b must have %d elements" % g.n_rays)
+    if x_ref is not None:
+        _need_device(x_ref, "x_ref", torch.float32)
+        if x_ref.numel() != g.n_vox:
+            raise ValueError("x_ref must have %d elements" % g.n_vox)
+    lib = L.load()
+    opts = L.SolverOpts(int(iters), _B[B], L.CT_F32, float(breakdown_tol))
+    n = ctypes.c_size_t()
+    _check(lib.ct_solver_workspace_bytes(g.handle, L.CT_SOLVER_BA_MONITOR, ctypes.byref(opts), ctypes.byref(n)),
+           "ct_solver_workspace_bytes")
+    ws = g.workspace("monitor", n.value)
+    if out is None:
+        out = torch.empty(g.vol_shape, dtype=torch.float32, device=b.device)
+    _need_device(out, "out", torch.float32)
+    K1 = int(iters) + 1
+    res, dres, img = (ctypes.c_double * K1)(), (ctypes.c_double * K1)(), (ctypes.c_double * K1)()
+    done = ctypes.c_int(0)
+    st = lib.ct_ba_gmres_monitor(g.handle, _ptr(b), _ptr(out), None if x_ref is None else _ptr(x_ref),
+                                 ctypes.byref(opts), _ptr(ws), ws.numel(), res, dres, img,
+                                 ctypes.byref(done), _stream(b))
+    _check(st, "ct_ba_gmres_monitor")
+    k = done.value + 1
+    return MonitorResult(out, list(res)[:k], list(dres)[:k], list(img)[:k], done.value)
+
+
 def ct_ab_gmres(g: Geometry, b: torch.Tensor, iters: int, B: str = "un", breakdown_tol: float = 0.0,
                 out: Optional[torch.Tensor] = None) -> SolveResult:
     """AB-GMRES (Eq. 4): GMRES on A B y = b, x = B y."""

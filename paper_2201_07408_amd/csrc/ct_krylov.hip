@@ -130,6 +130,60 @@ __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, si
     }
 }
 
+// ----------------------------------------------------- monitoring
+// Per-iteration curves of BA-GMRES without extra applications of A: the
+// projections q_j = A W[j] are kept (Q), and after step k the coefficients
+// c of the current iterate x_{k+1} = sum_j c_j W[j] give
+//   ||b - A x_{k+1}|| = ||b - sum_j c_j Q[j]||  and  x_{k+1} - x_ref.
+// Each kernel runs only if step k completed (k_done == k + 1, status OK).
+__device__ __forceinline__ bool mon_active(const KState &st, int k) {
+    return st.flags[F_KDONE] == k + 1 && st.flags[F_STATUS] == CT_OK;
+}
+
+// c = R^-1 g for the first k+1 columns, scaled to the raw basis
+__global__ void k_mon_coef(KState st, int k, double *__restrict__ cd) {
+    if (threadIdx.x != 0 || !mon_active(st, k)) return;
+    const int kd = k + 1, K1 = st.K + 1;
+    for (int i = kd - 1; i >= 0; --i) {
+        double sum = st.gv[i];
+        for (int j = i + 1; j < kd; ++j) sum -= st.H[(size_t)j * K1 + i] * cd[j];
+        cd[i] = sum / st.H[(size_t)i * K1 + i];
+    }
+    for (int i = 0; i < kd; ++i) cd[i] *= st.sc[i];
+}
+
+// block partials of sum_i (base_i - sum_{j<=k} c_j V[j][i])^2 (FP64)
+__global__ __launch_bounds__(256) void k_mon_resid(const float *__restrict__ base, const float *__restrict__ V,
+                                                   size_t ldv, size_t n, int k, KState st,
+                                                   const double *__restrict__ cd, double *__restrict__ partials) {
+    if (!mon_active(st, k)) return;
+    __shared__ double cf[kMaxVec];
+    __shared__ double red[4];
+    const int kd = k + 1;
+    for (int j = threadIdx.x; j < kd; j += 256) cf[j] = cd[j];
+    __syncthreads();
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        double r = base ? (double)base[i] : 0.0;
+        for (int j = 0; j < kd; ++j) r -= cf[j] * (double)V[(size_t)j * ldv + i];
+        acc += r * r;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[k+1] = sqrt(sum / div)
+__global__ void k_mon_store(const double *__restrict__ partials, int nblk, int k, KState st, double div,
+                            double *__restrict__ out) {
+    __shared__ double d[1];
+    if (!mon_active(st, k)) return;
+    reduce_partials(partials, kMaxBlk, nblk, 1, d);
+    __syncthreads();
+    if (threadIdx.x == 0) out[k + 1] = sqrt(d[0] / div);
+}
+
 // ------------------------------------------------------------- CGLS
 __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ v, size_t n,
                                                double *__restrict__ partials,
@@ -286,10 +340,15 @@ struct GmresBufs {
     void *filt = nullptr;   // ramp-filtered data
     float *z = nullptr;     // raw new vector
     KState st{};
+    // monitoring (BA-GMRES only)
+    float *Q = nullptr;     // K projections A W[j], stride ldq
+    size_t ldq = 0;
+    double *mon_c = nullptr, *mon_data = nullptr, *mon_img = nullptr, *mon_part = nullptr;
 };
 
 // Carve (or size, when ws == nullptr) the GMRES workspace.
-size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, void *ws, GmresBufs &b) {
+size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, void *ws, GmresBufs &b,
+                   bool monitor = false) {
     Carver c(ws);
     const int K = o.iters;
     const bool ba = solver == CT_SOLVER_BA;
@@ -326,6 +385,14 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
     s.misc = c.take<double>(8);
     s.fscale = c.take<float>(4);
     s.partials = c.take<double>((size_t)kMaxBlk * (K + 3));
+    if (monitor) {
+        b.ldq = align_up(g->n_rays, 64);
+        b.Q = c.take<float>(b.ldq * (size_t)(K > 0 ? K : 1));
+        b.mon_c = c.take<double>(K + 2);
+        b.mon_data = c.take<double>(K + 2);
+        b.mon_img = c.take<double>(K + 2);
+        b.mon_part = c.take<double>(kMaxBlk);
+    }
     return c.off;
 }
 
@@ -467,12 +534,32 @@ double fp16_scale_const(const ct_geometry *g) {
     return std::sqrt((double)g->n_vox) / ((double)nmax * g->k.vox);
 }
 
+// Host side of the monitored solve: the curves to return (either may be
+// NULL) and the reference image (device, may be NULL).
+struct MonitorOut {
+    const float *x_ref;
+    double *data_res;
+    double *img_rmse;
+};
+
+// b_i - sum c_j V[j]_i over n elements -> out[k+1] (divided by div inside the root)
+static int mon_curve(const GmresBufs &bf, const float *base, const float *V, size_t ldv, size_t n, int k,
+                     double div, double *out, hipStream_t s) {
+    const int nblk = grid_1d(n) < kMaxBlk ? grid_1d(n) : kMaxBlk;
+    hipLaunchKernelGGL(k_mon_resid, dim3(nblk), dim3(256), 0, s, base, V, ldv, n, k, bf.st, bf.mon_c, bf.mon_part);
+    CT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mon_store, dim3(1), dim3(64), 0, s, bf.mon_part, nblk, k, bf.st, div, out);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
 int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const ct_solver_opts *o, void *ws,
-               size_t ws_bytes, double *res_hist, int *iters_done, hipStream_t s) {
+               size_t ws_bytes, double *res_hist, int *iters_done, hipStream_t s,
+               const MonitorOut *mon = nullptr) {
     GmresBufs bf;
-    size_t need = carve_gmres(g, solver, *o, nullptr, bf);
+    size_t need = carve_gmres(g, solver, *o, nullptr, bf, mon != nullptr);
     CT_TRY(check_solver_args(g, solver, o, b, x, ws, ws_bytes, need));
-    carve_gmres(g, solver, *o, ws, bf);
+    carve_gmres(g, solver, *o, ws, bf, mon != nullptr);
     const int K = o->iters;
     const double tol = o->breakdown_tol > 0.0 ? o->breakdown_tol : 64.0 * 5.9604644775390625e-08;
     const bool ba = solver == CT_SOLVER_BA;
@@ -499,6 +586,10 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
     CT_TRY(run_cgs(2, bf, 0, bf.W, bf.W, st.coef, nullptr, s));   // ||r0||^2 (no update)
     hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, s, st, nblk, qc);
     CT_LAUNCH_CHECK();
+    if (mon) {   // x_0 = 0: ||b|| and RMS(x_ref)
+        CT_TRY(mon_curve(bf, b, bf.Q, bf.ldq, g->n_rays, -1, 1.0, bf.mon_data, s));
+        if (mon->x_ref) CT_TRY(mon_curve(bf, mon->x_ref, bf.W, bf.ldw, g->n_vox, -1, (double)g->n_vox, bf.mon_img, s));
+    }
 
     const float *oscale = f16 ? st.fscale : nullptr;
     const float *iscale = f16 ? st.fscale + 1 : nullptr;
@@ -507,8 +598,9 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
         float *wn = bf.W + (size_t)(k + 1) * bf.ldw;
         const bool pad_ready = o->B != CT_B_AT;
         if (ba) {
-            CT_TRY(apply_A(g, wk, bf.q, dt, op, pad_ready, oscale, stop, s));
-            CT_TRY(apply_B(g, o->B, bf.q, dt, bf.z, op, iscale, stop, s));
+            void *qk = mon ? (void *)(bf.Q + (size_t)k * bf.ldq) : bf.q;
+            CT_TRY(apply_A(g, wk, qk, dt, op, pad_ready, oscale, stop, s));
+            CT_TRY(apply_B(g, o->B, qk, dt, bf.z, op, iscale, stop, s));
         } else {
             CT_TRY(apply_B(g, o->B, wk, CT_F32, (float *)bf.q, op, nullptr, stop, s));
             CT_TRY(apply_A(g, (const float *)bf.q, bf.z, CT_F32, op, pad_ready, nullptr, stop, s));
@@ -523,6 +615,13 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
         CT_TRY(run_cgs(2, bf, nvec, wn, wn, st.coef, nullptr, s));
         hipLaunchKernelGGL(k_gmres_red3, dim3(1), dim3(64), 0, s, st, nblk, k, tol, qc);
         CT_LAUNCH_CHECK();
+        if (mon) {
+            hipLaunchKernelGGL(k_mon_coef, dim3(1), dim3(64), 0, s, st, k, bf.mon_c);
+            CT_LAUNCH_CHECK();
+            CT_TRY(mon_curve(bf, b, bf.Q, bf.ldq, g->n_rays, k, 1.0, bf.mon_data, s));
+            if (mon->x_ref)
+                CT_TRY(mon_curve(bf, mon->x_ref, bf.W, bf.ldw, g->n_vox, k, (double)g->n_vox, bf.mon_img, s));
+        }
     }
     hipLaunchKernelGGL(k_gmres_trsv, dim3(1), dim3(64), 0, s, st);
     CT_LAUNCH_CHECK();
@@ -534,6 +633,18 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
         hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, bf.z);
         CT_LAUNCH_CHECK();
         CT_TRY(apply_B(g, o->B, bf.z, CT_F32, x, op, nullptr, nullptr, s));
+    }
+    if (mon) {
+        std::vector<double> dr(K + 1), im(K + 1);
+        CT_HIP_CHECK(hipMemcpyAsync(dr.data(), bf.mon_data, sizeof(double) * (K + 1), hipMemcpyDeviceToHost, s));
+        CT_HIP_CHECK(hipMemcpyAsync(im.data(), bf.mon_img, sizeof(double) * (K + 1), hipMemcpyDeviceToHost, s));
+        int kd = 0;
+        CT_HIP_CHECK(hipMemcpyAsync(&kd, st.flags + F_KDONE, sizeof(int), hipMemcpyDeviceToHost, s));
+        CT_HIP_CHECK(hipStreamSynchronize(s));
+        for (int i = 0; i <= K; ++i) {
+            if (mon->data_res) mon->data_res[i] = i <= kd ? dr[i] : NAN;
+            if (mon->img_rmse) mon->img_rmse[i] = (i <= kd && mon->x_ref) ? im[i] : NAN;
+        }
     }
     return finish(st, K, res_hist, iters_done, s);
 }
@@ -604,9 +715,10 @@ extern "C" int ct_solver_workspace_bytes(const ct_geometry *g, int solver, const
         set_error("ct_solver_workspace_bytes: GMRES supports at most 56 iterations");
         return CT_ERR_UNSUPPORTED;
     }
-    if (solver == CT_SOLVER_BA || solver == CT_SOLVER_AB) {
+    if (solver == CT_SOLVER_BA || solver == CT_SOLVER_AB || solver == CT_SOLVER_BA_MONITOR) {
         GmresBufs bf;
-        *bytes = carve_gmres(g, solver, *opts, nullptr, bf);
+        *bytes = carve_gmres(g, solver == CT_SOLVER_AB ? CT_SOLVER_AB : CT_SOLVER_BA, *opts, nullptr, bf,
+                             solver == CT_SOLVER_BA_MONITOR);
     } else if (solver == CT_SOLVER_CGLS) {
         float *r, *q, *sv, *p;
         OpScratch op;
@@ -635,4 +747,17 @@ extern "C" int ct_cgls(const ct_geometry *g, const float *b, float *x, const ct_
                        size_t ws_bytes, double *res_hist, int *iters_done, void *stream) {
     clear_error();
     return cgls_impl(g, b, x, opts, ws, ws_bytes, res_hist, iters_done, (hipStream_t)stream);
+}
+
+extern "C" int ct_ba_gmres_monitor(const ct_geometry *g, const float *b, float *x, const float *x_ref,
+                                   const ct_solver_opts *opts, void *ws, size_t ws_bytes, double *res_hist,
+                                   double *data_res, double *img_rmse, int *iters_done, void *stream) {
+    clear_error();
+    CT_ARG_CHECK(opts != nullptr, "ct_ba_gmres_monitor: NULL options");
+    if (opts->sino_dtype != CT_F32) {
+        set_error("ct_ba_gmres_monitor: the kept projections are FP32 (sino_dtype must be CT_F32)");
+        return CT_ERR_UNSUPPORTED;
+    }
+    MonitorOut mon{x_ref, data_res, img_rmse};
+    return gmres_impl(g, CT_SOLVER_BA, b, x, opts, ws, ws_bytes, res_hist, iters_done, (hipStream_t)stream, &mon);
 }

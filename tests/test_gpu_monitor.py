@@ -1,0 +1,122 @@
+"""Per-iteration curves of BA-GMRES (ct_ba_gmres_monitor): the data
+residual ||b - A x_k|| and the image RMSE against a reference, for every
+k, checked against the oracle's iterate x_k (k iterations of its own
+BA-GMRES) put through the oracle's A.
+
+Bounds.  An iterate within 1e-4 of the oracle's moves ||b - A x_k|| by at
+most about 1e-4 ||b|| and the image RMSE by about 1e-4 RMS(x_ref), so
+those are the scales of the bounds.  On the 64x64 case with B_un the exact
+iterates between k ~ 15 and 26 amplify FP32 rounding like the 40-iteration
+slice problems do (the oracle with only its operator outputs rounded to
+FP32 moves by up to ~1e-2 there and returns to 1e-6 by k = 30).  FP32 runs
+follow the same delayed path but may leave the FP64 one a few steps
+earlier or later, so the GPU curve must stay within three times the largest
+excursion of that envelope over all k."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_07408_amd as ct
+from paper_2201_07408_amd import _lib as L
+from synth import workloads
+from synth.geometry import cone3d
+from tests.gpu_helpers import dev, f32, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _curves_of(desc, b, x_ref, iterates):
+    data = [float(np.linalg.norm(b))]
+    img = [float(np.sqrt(np.mean(x_ref.astype(np.float64) ** 2)))]
+    for xk in iterates:
+        data.append(float(np.linalg.norm(b.reshape(-1) - np.asarray(oracle.project_A(desc, xk)).reshape(-1))))
+        img.append(float(np.sqrt(np.mean((xk.reshape(-1) - x_ref.reshape(-1)) ** 2))))
+    return np.array(data), np.array(img)
+
+
+def oracle_curves(desc, b, x_ref, K, B):
+    return _curves_of(desc, b, x_ref, [oracle.ba_gmres(desc, b, k, B=B).x for k in range(1, K + 1)])
+
+
+def oracle_curves_fp32_outputs(desc, b, x_ref, K, B):
+    """The same curves for iterates of the oracle's GMRES whose operator
+    outputs are rounded to FP32 (the envelope any FP32 path lives in)."""
+    r32 = lambda v: np.asarray(v, np.float64).astype(np.float32).astype(np.float64)
+    A = lambda v: np.asarray(oracle.project_A(desc, v.reshape(desc.vol_shape))).reshape(-1)
+    Bop = oracle.back_projector(desc, B)
+    S = lambda v: r32(np.asarray(Bop(r32(A(r32(v))))).reshape(-1))
+    r0 = r32(np.asarray(Bop(b)).reshape(-1))
+    its = []
+    for k in range(1, K + 1):
+        co, W, res, done, _ = oracle.gmres(S, r0, k)
+        its.append(W[:done].T @ co)
+    return _curves_of(desc, b, x_ref, its)
+
+
+def check_curve(got, ref, env, scale):
+    got, ref, env = np.asarray(got), np.asarray(ref), np.asarray(env)
+    bound = max(TOL * scale, 3.0 * float(np.max(np.abs(env - ref))))
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref)) / bound)
+
+
+@pytest.mark.parametrize("B", ["un", "ramp"])
+def test_monitor_curves_2d(B):
+    desc = workloads.w1_geometry()
+    g = ct.Geometry(desc)
+    x_true = workloads.w1_phantom()
+    clean = oracle.project_A(desc, x_true)
+    b = f32(clean + workloads.relative_gaussian_noise(clean, 0.01, 102))
+    xr = f32(x_true)
+    K = 30
+    say("monitor 2d", B)
+    r = ct.ct_ba_gmres_monitor(g, dev(b), K, B=B, x_ref=dev(xr))
+    plain = ct.ct_ba_gmres(g, dev(b), K, B=B)
+    assert torch.equal(r.x, plain.x) and r.res == plain.res
+    d_ref, i_ref = oracle_curves(desc, b, xr, K, B)
+    d_env, i_env = oracle_curves_fp32_outputs(desc, b, xr, K, B)
+    assert r.iters_done == K
+    check_curve(r.data_res, d_ref, d_env, d_ref[0])
+    check_curve(r.img_rmse, i_ref, i_env, i_ref[0])
+    # outside the sensitive window the curves agree to 1e-4 of their scale
+    for k in list(range(0, 13)) + [29, 30]:
+        assert abs(r.data_res[k] - d_ref[k]) <= TOL * d_ref[0]
+        assert abs(r.img_rmse[k] - i_ref[k]) <= TOL * i_ref[0]
+
+
+def test_monitor_curves_cone_siddon():
+    desc = cone3d(32, 30, 48, projector=1)
+    g = ct.Geometry(desc)
+    vol = workloads.w2_phantom(n=32)
+    b = f32(oracle.project_A(desc, vol))
+    K = 10
+    r = ct.ct_ba_gmres_monitor(g, dev(b), K, x_ref=dev(vol))
+    d_ref, i_ref = oracle_curves(desc, b, f32(vol), K, "un")
+    for k in range(K + 1):
+        assert abs(r.data_res[k] - d_ref[k]) <= TOL * d_ref[0]
+        assert abs(r.img_rmse[k] - i_ref[k]) <= TOL * i_ref[0]
+
+
+def test_monitor_without_reference_and_errors():
+    desc = workloads.w1_geometry()
+    g = ct.Geometry(desc)
+    b = torch.rand(desc.n_rays, device="cuda")
+    r = ct.ct_ba_gmres_monitor(g, b, 5)
+    assert all(np.isnan(r.img_rmse)) and len(r.data_res) == 6
+    assert r.data_res[0] == pytest.approx(float(torch.linalg.norm(b.double())), rel=1e-12)
+    zero = ct.ct_ba_gmres_monitor(g, torch.zeros_like(b), 5)
+    assert zero.iters_done == 0 and zero.data_res == [0.0]
+    import ctypes
+    lib = L.load()
+    opts = L.SolverOpts(5, L.CT_B_UNMATCHED, L.CT_F16, 0.0)
+    x = torch.empty(desc.vol_shape, device="cuda")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    st = lib.ct_ba_gmres_monitor(g.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), None,
+                                 ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, None, None,
+                                 None, None)
+    assert st == L.CT_ERR_UNSUPPORTED
