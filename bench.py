@@ -176,6 +176,30 @@ def bench_siddon(ct, torch, lib, steps=2):
             "A_segments_per_s": counts["A_updates"] / t_a, "A_segments_per_launch": counts["A_updates"]}
 
 
+def bench_monitor(ct, torch, b, x_phantom, plain_ms):
+    """Semi-convergence on the headline workload: the per-iteration image
+    RMSE against the attenuation that made the data and the data residual,
+    for B = B_un and B = B_un F, and the monitor's cost per iteration."""
+    x_ref = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
+    g = ct.Geometry(__import__("synth").workloads.w3_geometry())
+    out = {}
+    for B in ("un", "ramp"):
+        ct.ct_ba_gmres_monitor(g, b, ITERS, B=B, x_ref=x_ref)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ct.ct_ba_gmres_monitor(g, b, ITERS, B=B, x_ref=x_ref)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        img = np.array(r.img_rmse)
+        k = int(np.nanargmin(img))
+        out["B_un" if B == "un" else "B_FBP"] = {
+            "min_image_rmse": float(img[k]), "at_iteration": k,
+            "image_rmse_at_30": float(img[-1]), "data_residual_at_30": float(r.data_res[-1]),
+            "data_residual_at_0": float(r.data_res[0]), "ms_per_solve": dt * 1e3}
+    out["monitor_overhead_ms_per_iteration"] = (out["B_FBP"]["ms_per_solve"] - plain_ms) / ITERS
+    return out
+
+
 def sampled_errors(oracle, desc, ct, g, torch, x_phantom):
     """Relative error of the GPU operators against the FP64 oracle on sampled
     rays / voxels of the benchmark workload."""
@@ -203,6 +227,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-siddon", action="store_true")
+    ap.add_argument("--no-monitor", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -286,6 +311,9 @@ def main():
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
     }
+    if not args.no_monitor:
+        log("bench: monitored solves")
+        line["monitor"] = bench_monitor(ct, torch, b, x_phantom, ms_per_step)
     if not args.no_siddon:
         log("bench: line-intersection forward model")
         line["siddon_A"] = bench_siddon(ct, torch, lib)
