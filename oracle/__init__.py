@@ -188,6 +188,33 @@ def ramp(g, y) -> np.ndarray:
     return out
 
 
+def fbp(g, y) -> np.ndarray:
+    """One-shot filtered back-projection with the paper's B_un and F (the
+    reference reconstruction it compares against, Sec. IV), scaled to
+    approximate the inverse Radon / cone-beam transform:
+      2D parallel beam:  x = (pi / P) (du / vox^2) B_un F y
+         (the ramp-filtered projection interpolated at x . n and summed over
+         P views spread over pi; B_un carries the weight vox^2 / du);
+      3D circular cone beam (Feldkamp-Davis-Kress):
+         x = (pi / P) (SOD / SDD) (du dv / vox^3) B_un F (w . y),
+         w = SDD / sqrt(SDD^2 + u^2 + v^2)  (cosine pre-weighting),
+         where B_un's weight vox^3 M^2 / (du dv) carries the distance factor
+         (SDD / U)^2 = (SDD / SOD)^2 (SOD / U)^2 and filtering in detector
+         pitch instead of isocentre pitch contributes SDD / SOD; the full
+         turn of P views counts every ray twice (the 1/2 of the formula)."""
+    g = _geom(g)
+    d = g.desc
+    y = _f64(y).reshape(d.n_views, d.nv, d.nu)
+    if d.kind == 0:
+        scale = (math.pi / d.n_views) * d.du / (d.voxel ** 2)
+        return scale * backproject_Bun(g, ramp(g, y))
+    u = (np.arange(d.nu) - 0.5 * (d.nu - 1)) * d.du
+    v = (np.arange(d.nv) - 0.5 * (d.nv - 1)) * d.dv
+    w = d.sdd / np.sqrt(d.sdd ** 2 + u[None, :] ** 2 + v[:, None] ** 2)
+    scale = (math.pi / d.n_views) * (d.sod / d.sdd) * d.du * d.dv / (d.voxel ** 3)
+    return scale * backproject_Bun(g, ramp(g, y * w[None, :, :]))
+
+
 def count_A_updates(g) -> int:
     g = _geom(g)
     return int(_load().orc_count_A_updates(ctypes.byref(g.c)))
