@@ -197,6 +197,15 @@ def bench_monitor(ct, torch, b, x_phantom, plain_ms):
             "image_rmse_at_30": float(img[-1]), "data_residual_at_30": float(r.data_res[-1]),
             "data_residual_at_0": float(r.data_res[0]), "ms_per_solve": dt * 1e3}
     out["monitor_overhead_ms_per_iteration"] = (out["B_FBP"]["ms_per_solve"] - plain_ms) / ITERS
+    # the one-shot FDK reconstruction of the same data, for comparison
+    xf = ct.ct_fbp(g, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xf = ct.ct_fbp(g, b, out=xf)
+    torch.cuda.synchronize()
+    fdk_ms = (time.perf_counter() - t0) * 1e3
+    out["FDK"] = {"image_rmse": float(torch.sqrt(torch.mean((xf.double() - x_ref.double()) ** 2))),
+                  "ms": fdk_ms}
     return out
 
 

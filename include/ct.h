@@ -91,7 +91,7 @@ enum { CT_JOSEPH = 0, CT_SIDDON = 1 };   /* forward projector model */
 enum { CT_F32 = 0, CT_F16 = 1 };                  /* data storage type    */
 enum { CT_B_UNMATCHED = 0, CT_B_RAMP = 1, CT_B_AT = 2 };
 enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2, CT_SOLVER_BA_MONITOR = 3 };
-enum { CT_OP_A = 0, CT_OP_B = 1, CT_OP_B_RAMP = 2, CT_OP_AT = 3 };
+enum { CT_OP_A = 0, CT_OP_B = 1, CT_OP_B_RAMP = 2, CT_OP_AT = 3, CT_OP_FBP = 4 };
 
 typedef struct {
     int kind;                 /* CT_PARALLEL_2D or CT_CONE_CIRCULAR_3D      */
@@ -161,6 +161,17 @@ int ct_backproject_AT(const ct_geometry *g, const void *y, int y_dtype, float *x
  * [batch][n_views][nv][nu]; q == y is not allowed. */
 int ct_ramp_filter(const ct_geometry *g, const float *q, float *y, int batch,
                    void *stream);
+
+/* One-shot filtered back-projection, the reference reconstruction the paper
+ * compares against (Sec. IV), built from B_un and F:
+ *   2D parallel beam:  x = (pi/P) (du/d^2) B_un F y;
+ *   3D circular cone:  x = (pi/P) (SOD/SDD) (du dv/d^3) B_un F (w . y),
+ *     w = SDD / sqrt(SDD^2 + u^2 + v^2) (Feldkamp-Davis-Kress cosine
+ *     pre-weighting; B_un's M^2 weight carries the distance weighting).
+ * y: float or half [batch][n_views][nv][nu]; x: float[batch][nz][ny][nx].
+ * ws: >= ct_op_workspace_bytes(CT_OP_FBP) bytes. */
+int ct_fbp(const ct_geometry *g, const void *y, int y_dtype, float *x, int batch,
+           void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes for a solver (CT_SOLVER_*, CT_SOLVER_BA_MONITOR for
  * ct_ba_gmres_monitor) with the given options. */

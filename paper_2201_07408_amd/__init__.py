@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     ct_backproject_B,
     ct_backproject_AT,
     ct_ramp_filter,
+    ct_fbp,
     ct_ba_gmres,
     ct_ba_gmres_monitor,
     MonitorResult,

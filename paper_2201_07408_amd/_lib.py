@@ -12,13 +12,13 @@ CT_JOSEPH, CT_SIDDON = 0, 1
 CT_F32, CT_F16 = 0, 1
 CT_B_UNMATCHED, CT_B_RAMP, CT_B_AT = 0, 1, 2
 CT_SOLVER_BA, CT_SOLVER_AB, CT_SOLVER_CGLS, CT_SOLVER_BA_MONITOR = 0, 1, 2, 3
-CT_OP_A, CT_OP_B, CT_OP_B_RAMP, CT_OP_AT = 0, 1, 2, 3
+CT_OP_A, CT_OP_B, CT_OP_B_RAMP, CT_OP_AT, CT_OP_FBP = 0, 1, 2, 3, 4
 
 # every symbol the header declares
 EXPORTS = [
     "ct_geometry_create", "ct_geometry_destroy", "ct_geometry_sizes",
     "ct_op_workspace_bytes", "ct_project_A", "ct_backproject_B",
-    "ct_backproject_AT", "ct_ramp_filter", "ct_solver_workspace_bytes",
+    "ct_backproject_AT", "ct_ramp_filter", "ct_fbp", "ct_solver_workspace_bytes",
     "ct_ba_gmres", "ct_ab_gmres", "ct_cgls", "ct_last_error", "ct_version", "ct_ba_gmres_monitor",
     "ct_profile_enable", "ct_profile_reset", "ct_profile_read",
     "ct_ba_gmres_batched_workspace_bytes", "ct_ba_gmres_batched",
@@ -76,6 +76,7 @@ def load(path: str = LIBPATH):
         "ct_backproject_B": ([gp, vp, i, vp, i, i, vp, sz, vp], i),
         "ct_backproject_AT": ([gp, vp, i, vp, i, vp, sz, vp], i),
         "ct_ramp_filter": ([gp, vp, vp, i, vp], i),
+        "ct_fbp": ([gp, vp, i, vp, i, vp, sz, vp], i),
         "ct_solver_workspace_bytes": ([gp, i, ctypes.POINTER(SolverOpts), szp], i),
         "ct_ba_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_ab_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),

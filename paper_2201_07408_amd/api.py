@@ -165,6 +165,20 @@ def ct_backproject_AT(g: Geometry, y: torch.Tensor, out: Optional[torch.Tensor] 
     return out
 
 
+def ct_fbp(g: Geometry, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One-shot FBP (2D) / FDK (cone) reconstruction from B_un and F."""
+    _need_device(y, "y")
+    batch = _batch_of(y, g.n_rays, "y")
+    lead = y.shape[:-3] if y.dim() >= 3 else ()
+    if out is None:
+        out = torch.empty(tuple(lead) + g.vol_shape, dtype=torch.float32, device=y.device)
+    _need_device(out, "out", torch.float32)
+    ws = g.op_workspace(L.CT_OP_FBP, batch)
+    _check(L.load().ct_fbp(g.handle, _ptr(y), _DT[y.dtype], _ptr(out), batch, _ptr(ws), ws.numel(),
+                           _stream(y)), "ct_fbp")
+    return out
+
+
 def ct_ramp_filter(g: Geometry, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     _need_device(q, "q", torch.float32)
     batch = _batch_of(q, g.n_rays, "q")

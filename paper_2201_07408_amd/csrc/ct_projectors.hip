@@ -1337,6 +1337,22 @@ static size_t ramp_mfma_lds(int nu, int nrg) {
     const int lmax = 2 * (nep > nop ? nep : nop) + 1;
     return sizeof(float) * ((size_t)16 * nrg * (se + so) + 2 * (size_t)lmax + 1);
 }
+
+// FBP / FDK pre-weighting: out = scale * w(u, v) * y with the cone-beam
+// cosine weight w = SDD / sqrt(SDD^2 + u^2 + v^2) (1 in 2D).
+template <typename InT>
+__global__ __launch_bounds__(256) void k_fbp_weight(GeomK g, const InT *__restrict__ y, float *__restrict__ out,
+                                                    size_t n, double scale) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double w = scale;
+        if (g.kind == 1) {
+            const int au = (int)(i % g.nu), av = (int)((i / g.nu) % g.nv);
+            const double u = (au - 0.5 * (g.nu - 1)) * g.du, v = (av - 0.5 * (g.nv - 1)) * g.dv;
+            w *= g.sdd / sqrt(g.sdd * g.sdd + u * u + v * v);
+        }
+        out[i] = (float)(w * (double)to_f(y[i]));
+    }
+}
 }  // namespace
 
 // ------------------------------------------------------------ launchers
@@ -1614,6 +1630,8 @@ size_t op_scratch_bytes(const ct_geometry *g, int op, int data_dtype) {
         return align_up(g->pad.nvx * 4) + align_up(g->pad.nvy * 4);
     case CT_OP_B_RAMP:
         return align_up(g->n_rays * dtype_size(data_dtype));
+    case CT_OP_FBP:
+        return 2 * align_up(g->n_rays * 4);
     default:
         return 0;
     }
@@ -1671,7 +1689,7 @@ static int check_dtype(int dt) { return dt == CT_F32 || dt == CT_F16; }
 extern "C" int ct_op_workspace_bytes(const ct_geometry *g, int op, int batch, size_t *bytes) {
     clear_error();
     CT_ARG_CHECK(g && bytes, "ct_op_workspace_bytes: NULL argument");
-    CT_ARG_CHECK(op >= CT_OP_A && op <= CT_OP_AT, "ct_op_workspace_bytes: unknown op");
+    CT_ARG_CHECK(op >= CT_OP_A && op <= CT_OP_FBP, "ct_op_workspace_bytes: unknown op");
     CT_ARG_CHECK(batch >= 0, "ct_op_workspace_bytes: negative batch");
     // items are processed one after another; the scratch is reused
     *bytes = op_scratch_bytes(g, op, CT_F32);
@@ -1751,4 +1769,39 @@ extern "C" int ct_ramp_filter(const ct_geometry *g, const float *q, float *y, in
     CT_ARG_CHECK(q && y && q != y, "ct_ramp_filter: bad arrays");
     return launch_ramp(g, q, CT_F32, y, CT_F32, (size_t)batch * g->k.P * g->k.nv, nullptr,
                        (hipStream_t)stream);
+}
+
+extern "C" int ct_fbp(const ct_geometry *g, const void *y, int y_dtype, float *x, int batch, void *ws,
+                      size_t ws_bytes, void *stream) {
+    clear_error();
+    CT_ARG_CHECK(g, "ct_fbp: geometry is NULL");
+    CT_ARG_CHECK(batch >= 0, "ct_fbp: negative batch");
+    CT_ARG_CHECK(check_dtype(y_dtype), "ct_fbp: bad y_dtype");
+    if (batch == 0) return CT_OK;
+    CT_ARG_CHECK(x && y, "ct_fbp: NULL array");
+    const size_t need = op_scratch_bytes(g, CT_OP_FBP, CT_F32);
+    CT_ARG_CHECK(ws && ws_bytes >= need, "ct_fbp: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const GeomK &k = g->k;
+    const double scale = k.kind == CT_PARALLEL_2D
+                             ? (M_PI / k.P) * k.du / (k.vox * k.vox)
+                             : (M_PI / k.P) * (k.sod / k.sdd) * k.du * k.dv / (k.vox * k.vox * k.vox);
+    float *wy = (float *)ws;
+    float *fy = (float *)((char *)ws + align_up(g->n_rays * 4));
+    const size_t es = y_dtype == CT_F16 ? 2 : 4;
+    size_t blocks = (g->n_rays + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    for (int b = 0; b < batch; ++b) {
+        const char *yb = (const char *)y + (size_t)b * g->n_rays * es;
+        if (y_dtype == CT_F32)
+            hipLaunchKernelGGL(k_fbp_weight<float>, dim3((unsigned)blocks), dim3(256), 0, s, k, (const float *)yb, wy,
+                               g->n_rays, scale);
+        else
+            hipLaunchKernelGGL(k_fbp_weight<__half>, dim3((unsigned)blocks), dim3(256), 0, s, k, (const __half *)yb,
+                               wy, g->n_rays, scale);
+        CT_LAUNCH_CHECK();
+        CT_TRY(launch_ramp(g, wy, CT_F32, fy, CT_F32, (size_t)k.P * k.nv, nullptr, s));
+        CT_TRY(launch_backproject(g, fy, CT_F32, x + (size_t)b * g->n_vox, nullptr, nullptr, s));
+    }
+    return CT_OK;
 }

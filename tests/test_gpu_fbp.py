@@ -1,0 +1,40 @@
+"""One-shot FBP / FDK (ct_fbp) against the oracle's composition of its own
+weights, ramp filter and B_un."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_07408_amd as ct
+from synth.geometry import GeometryDesc, parallel2d, cone3d, CONE_3D
+from tests.gpu_helpers import dev, f32, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = {
+    "2d_64": parallel2d(64, 90, 96),
+    "2d_ragged": parallel2d(37, 41, 61, voxel=0.8, du=0.9),
+    "cone_32": cone3d(32, 40, 48),
+    "cone_ragged": GeometryDesc(CONE_3D, 33, 30, 17, 1.0, 13, 45, 29, 1.7, 2.3, 140.0, 290.0),
+}
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_fbp_matches_oracle(name):
+    desc = GEOMS[name]
+    g = ct.Geometry(desc)
+    y = f32(np.random.default_rng(31).uniform(size=desc.sino_shape))
+    say("fbp", name)
+    assert rel(host(ct.ct_fbp(g, dev(y))), oracle.fbp(desc, y)) <= 1e-5
+
+
+def test_fbp_half_input_and_batch():
+    desc = GEOMS["cone_32"]
+    g = ct.Geometry(desc)
+    y = f32(np.random.default_rng(32).uniform(size=(2,) + desc.sino_shape))
+    yh = torch.from_numpy(y).cuda().half()
+    xb = host(ct.ct_fbp(g, yh))
+    for i in range(2):
+        ref = oracle.fbp(desc, yh[i].float().cpu().numpy())
+        assert rel(xb[i], ref) <= 1e-5
