@@ -90,7 +90,8 @@ enum { CT_PARALLEL_2D = 0, CT_CONE_CIRCULAR_3D = 1 };
 enum { CT_JOSEPH = 0, CT_SIDDON = 1 };   /* forward projector model */
 enum { CT_F32 = 0, CT_F16 = 1 };                  /* data storage type    */
 enum { CT_B_UNMATCHED = 0, CT_B_RAMP = 1, CT_B_AT = 2 };
-enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2, CT_SOLVER_BA_MONITOR = 3 };
+enum { CT_SOLVER_BA = 0, CT_SOLVER_AB = 1, CT_SOLVER_CGLS = 2, CT_SOLVER_BA_MONITOR = 3,
+       CT_SOLVER_BA_RESTARTED = 4 };
 enum { CT_OP_A = 0, CT_OP_B = 1, CT_OP_B_RAMP = 2, CT_OP_AT = 3, CT_OP_FBP = 4 };
 
 typedef struct {
@@ -208,6 +209,22 @@ int ct_ba_gmres_monitor(const ct_geometry *g, const float *b, float *x,
                         void *ws, size_t ws_bytes, double *res_hist,
                         double *data_res, double *img_rmse, int *iters_done,
                         void *stream);
+
+/* Restarted BA-GMRES(m): `cycles` cycles of opts->iters = m BA-GMRES steps
+ * (Sec. II, Eq. 5), each on the data residual of the current iterate:
+ * x <- x + argmin over K_m(BA, B(b - A x)) of ||B(b - A x) - B A d||.  The
+ * basis holds m + 1 vectors instead of K + 1 (the storage the paper names as
+ * the method's burden), at the price of the convergence a full Krylov space
+ * would give.  Cycle 1 equals ct_ba_gmres with m iterations.
+ *   res_hist: HOST double[cycles][m+1] or NULL, each cycle's residual
+ *             history as in ct_ba_gmres (NaN after a breakdown);
+ *   iters_done: HOST, total iterations over the cycles.
+ * Workspace: ct_solver_workspace_bytes(CT_SOLVER_BA_RESTARTED) with
+ * opts->iters = m.  Other arguments as ct_ba_gmres. */
+int ct_ba_gmres_restarted(const ct_geometry *g, const float *b, float *x,
+                          const ct_solver_opts *opts, int cycles, void *ws,
+                          size_t ws_bytes, double *res_hist, int *iters_done,
+                          void *stream);
 
 /* AB-GMRES (Sec. II, Eq. 4): y_K minimises ||b - A B y|| over
  * K_K(A B, b), x = B y.  Basis in data space.  res_hist[k] = ||b - A x_k||

@@ -364,3 +364,20 @@ def cgls(g, b, iters: int, B: str = "AT") -> CglsResult:
         res.append(float(np.linalg.norm(r)))
         done += 1
     return CglsResult(x, res, done)
+
+
+def ba_gmres_restarted(g, b, m: int, cycles: int, B: str = "un"):
+    """Restarted BA-GMRES(m): each cycle runs m steps of BA-GMRES on the
+    data residual of the current iterate and adds the correction
+    (x <- x + d, d from K_m(BA, B(b - A x))).  Returns (x, list of the
+    cycles' residual histories)."""
+    g = _geom(g)
+    b = _f64(b).reshape(-1)
+    x = np.zeros(g.n)
+    hist = []
+    for _ in range(cycles):
+        r = b - np.asarray(project_A(g, x.reshape(g.vol_shape))).reshape(-1)
+        res = ba_gmres(g, r, m, B=B)
+        x = x + np.asarray(res.x).reshape(-1)
+        hist.append(list(res.res))
+    return x, hist

@@ -18,6 +18,7 @@ from .api import (  # noqa: F401
     ct_fbp,
     ct_ba_gmres,
     ct_ba_gmres_monitor,
+    ct_ba_gmres_restarted,
     MonitorResult,
     ct_ab_gmres,
     ct_cgls,

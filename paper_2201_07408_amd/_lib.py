@@ -11,7 +11,7 @@ CT_PARALLEL_2D, CT_CONE_CIRCULAR_3D = 0, 1
 CT_JOSEPH, CT_SIDDON = 0, 1
 CT_F32, CT_F16 = 0, 1
 CT_B_UNMATCHED, CT_B_RAMP, CT_B_AT = 0, 1, 2
-CT_SOLVER_BA, CT_SOLVER_AB, CT_SOLVER_CGLS, CT_SOLVER_BA_MONITOR = 0, 1, 2, 3
+CT_SOLVER_BA, CT_SOLVER_AB, CT_SOLVER_CGLS, CT_SOLVER_BA_MONITOR, CT_SOLVER_BA_RESTARTED = 0, 1, 2, 3, 4
 CT_OP_A, CT_OP_B, CT_OP_B_RAMP, CT_OP_AT, CT_OP_FBP = 0, 1, 2, 3, 4
 
 # every symbol the header declares
@@ -20,6 +20,7 @@ EXPORTS = [
     "ct_op_workspace_bytes", "ct_project_A", "ct_backproject_B",
     "ct_backproject_AT", "ct_ramp_filter", "ct_fbp", "ct_solver_workspace_bytes",
     "ct_ba_gmres", "ct_ab_gmres", "ct_cgls", "ct_last_error", "ct_version", "ct_ba_gmres_monitor",
+    "ct_ba_gmres_restarted",
     "ct_profile_enable", "ct_profile_reset", "ct_profile_read",
     "ct_ba_gmres_batched_workspace_bytes", "ct_ba_gmres_batched",
     "ct_batched_config", "ct_batched_last_config",
@@ -81,6 +82,7 @@ def load(path: str = LIBPATH):
         "ct_ba_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_ab_gmres": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_cgls": ([gp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
+        "ct_ba_gmres_restarted": ([gp, vp, vp, ctypes.POINTER(SolverOpts), i, vp, sz, dp, ip, vp], i),
         "ct_ba_gmres_monitor": ([gp, vp, vp, vp, ctypes.POINTER(SolverOpts), vp, sz, dp, dp, dp, ip, vp], i),
         "ct_ba_gmres_batched_workspace_bytes": ([ctypes.POINTER(vp), i, ctypes.POINTER(SolverOpts), szp], i),
         "ct_ba_gmres_batched": ([ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),

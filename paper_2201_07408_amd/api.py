@@ -224,6 +224,37 @@ def ct_ba_gmres(g: Geometry, b: torch.Tensor, iters: int, B: str = "un", sino_dt
 
 
 @dataclass
+class RestartResult:
+    x: torch.Tensor
+    res: List[List[float]]     # per cycle, as ct_ba_gmres's history
+    iters_done: int
+
+
+def ct_ba_gmres_restarted(g: Geometry, b: torch.Tensor, m: int, cycles: int, B: str = "un",
+                          breakdown_tol: float = 0.0, out: Optional[torch.Tensor] = None) -> RestartResult:
+    """Restarted BA-GMRES(m): `cycles` cycles of m steps on the data residual."""
+    _need_device(b, "b", torch.float32)
+    if b.numel() != g.n_rays:
+        raise ValueError("b must have %d elements" % g.n_rays)
+    lib = L.load()
+    opts = L.SolverOpts(int(m), _B[B], L.CT_F32, float(breakdown_tol))
+    n = ctypes.c_size_t()
+    _check(lib.ct_solver_workspace_bytes(g.handle, L.CT_SOLVER_BA_RESTARTED, ctypes.byref(opts), ctypes.byref(n)),
+           "ct_solver_workspace_bytes")
+    ws = g.workspace("restarted", n.value)
+    if out is None:
+        out = torch.empty(g.vol_shape, dtype=torch.float32, device=b.device)
+    _need_device(out, "out", torch.float32)
+    K1 = int(m) + 1
+    res = (ctypes.c_double * (K1 * int(cycles)))()
+    done = ctypes.c_int(0)
+    _check(lib.ct_ba_gmres_restarted(g.handle, _ptr(b), _ptr(out), ctypes.byref(opts), int(cycles), _ptr(ws),
+                                     ws.numel(), res, ctypes.byref(done), _stream(b)), "ct_ba_gmres_restarted")
+    hist = [[v for v in res[c * K1:(c + 1) * K1] if v == v] for c in range(int(cycles))]
+    return RestartResult(out, hist, done.value)
+
+
+@dataclass
 class MonitorResult:
     x: torch.Tensor
     res: List[float]

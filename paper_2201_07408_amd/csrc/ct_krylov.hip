@@ -115,16 +115,16 @@ __global__ void k_gmres_red3(KState st, int nblk, int k, double tol, double qsca
 
 __global__ void k_gmres_trsv(KState st) { gmres_trsv(st); }
 
-// out = sum_{j < k_done} coef[j] W[j]   (FP64 accumulation)
+// out = sum_{j < k_done} coef[j] W[j] (or out + that sum), FP64 accumulation
 __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, size_t ldw, size_t n,
-                                                 KState st, float *__restrict__ out) {
+                                                 KState st, float *__restrict__ out, int accumulate) {
     __shared__ double cf[kMaxVec + 1];
     const int kd = st.flags[F_KDONE];
     for (int j = threadIdx.x; j < kd; j += blockDim.x) cf[j] = st.coef[j];
     __syncthreads();
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
-        double a = 0.0;
+        double a = accumulate ? (double)out[i] : 0.0;
         for (int j = 0; j < kd; ++j) a += cf[j] * (double)W[(size_t)j * ldw + i];
         out[i] = (float)a;
     }
@@ -182,6 +182,13 @@ __global__ void k_mon_store(const double *__restrict__ partials, int nblk, int k
     reduce_partials(partials, kMaxBlk, nblk, 1, d);
     __syncthreads();
     if (threadIdx.x == 0) out[k + 1] = sqrt(d[0] / div);
+}
+
+// r = b - q
+__global__ __launch_bounds__(256) void k_residual(const float *__restrict__ b, const float *__restrict__ q,
+                                                  float *__restrict__ r, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        r[i] = b[i] - q[i];
 }
 
 // ------------------------------------------------------------- CGLS
@@ -555,7 +562,7 @@ static int mon_curve(const GmresBufs &bf, const float *base, const float *V, siz
 
 int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const ct_solver_opts *o, void *ws,
                size_t ws_bytes, double *res_hist, int *iters_done, hipStream_t s,
-               const MonitorOut *mon = nullptr) {
+               const MonitorOut *mon = nullptr, bool accumulate = false) {
     GmresBufs bf;
     size_t need = carve_gmres(g, solver, *o, nullptr, bf, mon != nullptr);
     CT_TRY(check_solver_args(g, solver, o, b, x, ws, ws_bytes, need));
@@ -626,11 +633,12 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
     hipLaunchKernelGGL(k_gmres_trsv, dim3(1), dim3(64), 0, s, st);
     CT_LAUNCH_CHECK();
     if (ba) {
-        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, x);
+        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, x,
+                           (int)accumulate);
         CT_LAUNCH_CHECK();
     } else {
         // x = B (W c): combine in data space, then back-project
-        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, bf.z);
+        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, bf.z, 0);
         CT_LAUNCH_CHECK();
         CT_TRY(apply_B(g, o->B, bf.z, CT_F32, x, op, nullptr, nullptr, s));
     }
@@ -701,6 +709,28 @@ int cgls_impl(const ct_geometry *g, const float *b, float *x, const ct_solver_op
     return finish(st, o->iters, res_hist, iters_done, s);
 }
 
+// ------------------------------------------------------ restarted BA-GMRES
+// Workspace of the restarted solver: the GMRES workspace for m iterations,
+// then the data residual, the projection of the current x and the padded
+// copies used to form it.
+struct RestartBufs {
+    size_t gm_bytes = 0;
+    float *r = nullptr, *q = nullptr;
+    OpScratch op;
+};
+
+size_t carve_restart(const ct_geometry *g, const ct_solver_opts &o, void *ws, RestartBufs &rb) {
+    GmresBufs bf;
+    rb.gm_bytes = align_up(carve_gmres(g, CT_SOLVER_BA, o, nullptr, bf));
+    Carver c(ws ? (char *)ws + rb.gm_bytes : nullptr);
+    rb.r = c.take<float>(g->n_rays);
+    rb.q = c.take<float>(g->n_rays);
+    rb.op.vx = c.take<float>(g->pad.nvx);
+    rb.op.vy = c.take<float>(g->pad.nvy);
+    if (!ws) rb.r = rb.q = rb.op.vx = rb.op.vy = nullptr;
+    return rb.gm_bytes + c.off;
+}
+
 }  // namespace
 }  // namespace ct
 
@@ -719,6 +749,9 @@ extern "C" int ct_solver_workspace_bytes(const ct_geometry *g, int solver, const
         GmresBufs bf;
         *bytes = carve_gmres(g, solver == CT_SOLVER_AB ? CT_SOLVER_AB : CT_SOLVER_BA, *opts, nullptr, bf,
                              solver == CT_SOLVER_BA_MONITOR);
+    } else if (solver == CT_SOLVER_BA_RESTARTED) {
+        RestartBufs rb;
+        *bytes = carve_restart(g, *opts, nullptr, rb);
     } else if (solver == CT_SOLVER_CGLS) {
         float *r, *q, *sv, *p;
         OpScratch op;
@@ -760,4 +793,36 @@ extern "C" int ct_ba_gmres_monitor(const ct_geometry *g, const float *b, float *
     }
     MonitorOut mon{x_ref, data_res, img_rmse};
     return gmres_impl(g, CT_SOLVER_BA, b, x, opts, ws, ws_bytes, res_hist, iters_done, (hipStream_t)stream, &mon);
+}
+
+extern "C" int ct_ba_gmres_restarted(const ct_geometry *g, const float *b, float *x, const ct_solver_opts *opts,
+                                     int cycles, void *ws, size_t ws_bytes, double *res_hist, int *iters_done,
+                                     void *stream) {
+    clear_error();
+    CT_ARG_CHECK(g && opts, "ct_ba_gmres_restarted: NULL geometry or options");
+    CT_ARG_CHECK(cycles >= 1, "ct_ba_gmres_restarted: cycles must be >= 1");
+    CT_ARG_CHECK(b && x, "ct_ba_gmres_restarted: NULL b or x");
+    RestartBufs rb;
+    const size_t need = carve_restart(g, *opts, nullptr, rb);
+    CT_ARG_CHECK(ws != nullptr && ws_bytes >= need, "ct_ba_gmres_restarted: workspace too small");
+    carve_restart(g, *opts, ws, rb);
+    hipStream_t s = (hipStream_t)stream;
+    const int m = opts->iters;
+    int total = 0;
+    for (int c = 0; c < cycles; ++c) {
+        const float *rhs = b;
+        if (c > 0) {
+            // data residual of the current iterate: r = b - A x
+            CT_TRY(apply_A(g, x, rb.q, CT_F32, rb.op, c > 1, nullptr, nullptr, s));
+            hipLaunchKernelGGL(k_residual, dim3(grid_1d(g->n_rays)), dim3(256), 0, s, b, rb.q, rb.r, g->n_rays);
+            CT_LAUNCH_CHECK();
+            rhs = rb.r;
+        }
+        int done = 0;
+        CT_TRY(gmres_impl(g, CT_SOLVER_BA, rhs, x, opts, ws, rb.gm_bytes, res_hist ? res_hist + (size_t)c * (m + 1) : nullptr,
+                          &done, s, nullptr, c > 0));
+        total += done;
+    }
+    if (iters_done) *iters_done = total;
+    return CT_OK;
 }
