@@ -209,6 +209,74 @@ def bench_monitor(ct, torch, b, x_phantom, plain_ms):
     return out
 
 
+def bench_paper_scale(ct, torch, lib):
+    """BA-GMRES (B = B_un F) at the paper's data size: 1024 x 1024 x 300
+    volume, 180 views of a 1088 x 896 detector (synthetic geometry, see
+    synth.workloads.paper_geometry), Poisson data at 1e5 photons.  Full
+    30-iteration solve (31 basis vectors), restarted BA-GMRES(10) x 3 cycles
+    (11 basis vectors), and the one-shot FDK, each with its image RMSE
+    against the attenuation that made the data."""
+    import ctypes as C
+    from synth import workloads
+    from synth.phantoms import rasterize_ellipsoids_torch, poisson_log_counts
+    desc = workloads.paper_geometry()
+    g = ct.Geometry(desc)
+    t0 = time.perf_counter()
+    x = rasterize_ellipsoids_torch(workloads.paper_phantom_ellipsoids(), desc.nx, desc.voxel, desc.nz, "cuda")
+    ax = ct.ct_project_A(g, x)
+    mu = 4.0 / float(ax.max())
+    b = torch.from_numpy(poisson_log_counts(703, (ax * mu).double().cpu().numpy().reshape(-1),
+                                            1e5).astype(np.float32)).cuda()
+    x_ref = x * mu
+    del ax
+    prep_s = time.perf_counter() - t0
+
+    def rmse(v):
+        return float(torch.sqrt(torch.mean((v.double() - x_ref.double()) ** 2)))
+
+    def ws_bytes(solver, iters):
+        opts = ct.api.L.SolverOpts(iters, ct.api.L.CT_B_RAMP, ct.api.L.CT_F32, 0.0)
+        n = C.c_size_t()
+        lib.ct_solver_workspace_bytes(g.handle, solver, C.byref(opts), C.byref(n))
+        return n.value
+
+    out = {"workload": "1024x1024x300 volume, 180 views over 360 deg, 1088x896 detector (0.278 mm), "
+                       "magnification 2, 12 ellipsoids, Poisson 1e5", "input_generation_s": prep_s}
+    ct.ct_ba_gmres(g, b, 2, B="ramp")          # load kernels, size the workspace
+    torch.cuda.synchronize()
+    lib.ct_profile_reset()
+    lib.ct_profile_enable(1)
+    t0 = time.perf_counter()
+    r = ct.ct_ba_gmres(g, b, ITERS, B="ramp")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lib.ct_profile_enable(0)
+    kern = {}
+    for name in ("A", "B", "F", "CGS"):
+        n_l, t_l = C.c_long(), C.c_double()
+        lib.ct_profile_read(name.encode(), C.byref(n_l), C.byref(t_l))
+        kern[name] = t_l.value / max(n_l.value, 1)
+    out["full"] = {"iters": r.iters_done, "s": dt, "iters_per_s": r.iters_done / dt,
+                   "image_rmse": rmse(r.x), "workspace_GB": ws_bytes(ct.api.L.CT_SOLVER_BA, ITERS) / 1e9,
+                   "kernel_ms_per_launch": {"A": kern["A"], "B_un": kern["B"], "F": kern["F"]}}
+    del r
+    t0 = time.perf_counter()
+    rr = ct.ct_ba_gmres_restarted(g, b, 10, 3, B="ramp")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["restarted_10x3"] = {"iters": rr.iters_done, "s": dt, "iters_per_s": rr.iters_done / dt,
+                             "image_rmse": rmse(rr.x),
+                             "workspace_GB": ws_bytes(ct.api.L.CT_SOLVER_BA_RESTARTED, 10) / 1e9}
+    del rr
+    xf = ct.ct_fbp(g, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xf = ct.ct_fbp(g, b, out=xf)
+    torch.cuda.synchronize()
+    out["FDK"] = {"s": time.perf_counter() - t0, "image_rmse": rmse(xf)}
+    return out
+
+
 def sampled_errors(oracle, desc, ct, g, torch, x_phantom):
     """Relative error of the GPU operators against the FP64 oracle on sampled
     rays / voxels of the benchmark workload."""
@@ -237,6 +305,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-siddon", action="store_true")
     ap.add_argument("--no-monitor", action="store_true")
+    ap.add_argument("--paper-scale", action="store_true",
+                    help="also solve at the paper's data size (1024x1024x300, 180 x 1088x896)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -326,6 +396,9 @@ def main():
     if not args.no_siddon:
         log("bench: line-intersection forward model")
         line["siddon_A"] = bench_siddon(ct, torch, lib)
+    if args.paper_scale:
+        log("bench: paper-size problem")
+        line["paper_scale"] = bench_paper_scale(ct, torch, lib)
     if not args.no_batched:
         log("bench: batched 2D slices")
         line["batched_2d"] = bench_batched(ct, torch)

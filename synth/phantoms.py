@@ -127,6 +127,37 @@ def rasterize_ellipsoids(ells, n: int, voxel: float, profile: str = "uniform",
     return vol
 
 
+def rasterize_ellipsoids_torch(ells, n: int, voxel: float, nz: int, device):
+    """The uniform-profile rasterisation of rasterize_ellipsoids (point
+    samples at voxel centres, additive densities), evaluated with torch on
+    `device` slab by slab for volumes too large for the numpy version.
+    Returns a float32 tensor [nz][n][n]."""
+    import torch
+    vol = torch.zeros((nz, n, n), dtype=torch.float32, device=device)
+    xc = torch.as_tensor(_centres(n, voxel), dtype=torch.float64, device=device)
+    zc = torch.as_tensor(_centres(nz, voxel), dtype=torch.float64, device=device)
+    for e in ells:
+        ext = np.sqrt(((e["R"] * e["semi"][None, :]) ** 2).sum(axis=1))
+        lo = np.floor((e["centre"] - ext) / voxel + 0.5 * (np.array([n, n, nz]) - 1)) - 1
+        hi = np.ceil((e["centre"] + ext) / voxel + 0.5 * (np.array([n, n, nz]) - 1)) + 2
+        ix0, iy0, iz0 = [int(max(0, v)) for v in lo]
+        ix1, iy1, iz1 = [int(min(m, v)) for v, m in zip(hi, (n, n, nz))]
+        if ix0 >= ix1 or iy0 >= iy1 or iz0 >= iz1:
+            continue
+        Rt = e["R"].T
+        X = (xc[ix0:ix1] - e["centre"][0])[None, :]
+        Y = (xc[iy0:iy1] - e["centre"][1])[:, None]
+        for z0 in range(iz0, iz1, 16):
+            z1 = min(z0 + 16, iz1)
+            Z = (zc[z0:z1] - e["centre"][2])[:, None, None]
+            u = (Rt[0, 0] * X + Rt[0, 1] * Y)[None] + Rt[0, 2] * Z
+            v = (Rt[1, 0] * X + Rt[1, 1] * Y)[None] + Rt[1, 2] * Z
+            w = (Rt[2, 0] * X + Rt[2, 1] * Y)[None] + Rt[2, 2] * Z
+            r2 = (u / e["semi"][0]) ** 2 + (v / e["semi"][1]) ** 2 + (w / e["semi"][2]) ** 2
+            vol[z0:z1, iy0:iy1, ix0:ix1] += float(e["rho"]) * (r2 <= 1.0).float()
+    return vol
+
+
 # ------------------------------------------------------------ noise draws
 def smooth_texture(seed: int, shape, sigma: float = 2.0) -> np.ndarray:
     """White Gaussian noise smoothed by a Gaussian of ``sigma`` voxels and

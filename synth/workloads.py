@@ -11,6 +11,10 @@ W3  3D cone beam, 256^3, 360 views, 384x384 detector, same ratios, ellipsoids
     plus 5 % smoothed Gaussian texture, Poisson data at 1e5 photons per ray.
 W4  batch of four 128^3 volumes in the W2 geometry (autograd check).
 W5  64 independent 2D slices of seeded uneven sizes.
+Paper size: the dimensions of the paper's scanner data (1024 x 1024 x 300
+    volume, 180 views over 360 deg, 1088 x 896 detector of 0.278 mm pixels)
+    with a synthetic circular geometry of magnification 2 (SOD = 4 W,
+    SDD = 8 W) and one voxel per detector pixel at the isocentre.
 """
 
 import math
@@ -84,3 +88,18 @@ def relative_gaussian_noise(clean: np.ndarray, level: float, seed: int) -> np.nd
     """e = level * ||clean|| * eta / ||eta||, eta ~ N(0, I)."""
     eta = gaussian_noise(seed, clean.size).reshape(clean.shape)
     return level * np.linalg.norm(clean) * eta / np.linalg.norm(eta)
+
+
+def paper_geometry():
+    pitch = 0.278
+    voxel = pitch / 2.0
+    w = 1024 * voxel
+    return cone3d(1024, 180, 1088, voxel=voxel, sod_factor=4.0, sdd_factor=8.0, pitch=pitch,
+                  nz=300, nv=896)
+
+
+def paper_phantom_ellipsoids(seed: int = 701):
+    """12 random ellipsoids over 0.7 of the volume width, so that they stay
+    inside the field of view of the 1088-pixel detector."""
+    g = paper_geometry()
+    return random_ellipsoids(seed, 12, 0.7 * g.nx * g.voxel)
