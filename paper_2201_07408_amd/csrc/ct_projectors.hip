@@ -1251,12 +1251,13 @@ __global__ __launch_bounds__(256) void k_bramp(const BSlice *__restrict__ sl, in
 //   out[2i]   = h0 q[2i]   + sum_m hh[2(i-m) - 1] q[2m+1]
 //   out[2i+1] = h0 q[2i+1] + sum_m hh[2(i-m) + 1] q[2m]
 // (hh[j] = du h[|j|]), half the multiply-adds of the dense convolution.  A
-// workgroup stages 16 NRG rows, split into even and odd halves, in LDS, plus
-// the taps as a table over signed lags.  A wavefront task is one parity and
-// 16 outputs for all the rows: v_mfma_f32_16x16x4f32 with M = output index,
-// N = row, K = input index, the A operand (16 x 4 Toeplitz block) read from
-// the tap table and the B operand from the staged rows, one accumulator per
-// 16-row group, initialised with the h0 term.
+// workgroup takes 16 NRG rows and the two parities in turn: it stages the
+// inputs of the other parity (half of each row) in LDS, next to the taps as
+// a table over signed lags, and its wavefronts take tasks of 16 outputs for
+// all the rows: v_mfma_f32_16x16x4f32 with M = output index, N = row,
+// K = input index, the A operand (16 x 4 Toeplitz block) read from the tap
+// table and the B operand from the staged half-rows, one accumulator per
+// 16-row group; the h0 term is read from global memory and added last.
 template <typename InT, typename OutT, int NRG>
 __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, OutT *__restrict__ out,
                                                    const float *__restrict__ taps, int nu, size_t rows,
@@ -1266,65 +1267,68 @@ __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, Ou
     constexpr int R = 16 * NRG;
     const int ne = (nu + 1) / 2, no = nu / 2;
     const int nep = (ne + 15) & ~15, nop = (no + 15) & ~15;
-    const int se = ((nep + 31) & ~31) + 2, so = ((nop + 31) & ~31) + 2;   // strides = 2 (mod 32 banks)
+    const int ss = ((nep > nop ? nep : nop) + 31 & ~31) + 2;   // half-row stride = 2 (mod 32 banks)
     const int lmax = 2 * (nep > nop ? nep : nop) + 1;
-    float *Qe = sm, *Qo = sm + R * se, *hsym = sm + R * (se + so);
+    float *Qs = sm, *hsym = sm + R * ss;
     const size_t r0 = (size_t)blockIdx.x * R;
     const int tid = threadIdx.x;
-    for (int t = tid; t < R * se; t += 256) Qe[t] = 0.0f;
-    for (int t = tid; t < R * so; t += 256) Qo[t] = 0.0f;
     for (int t = tid; t <= 2 * lmax; t += 256) {
         const int L = t - lmax, aL = L < 0 ? -L : L;
         hsym[t] = aL < nu ? taps[aL] : 0.0f;
     }
-    __syncthreads();
-    for (int t = tid; t < R * nu; t += 256) {
-        const int r = t / nu, a = t - r * nu;
-        if (r0 + r < rows) {
-            const float v = to_f(q[(r0 + r) * nu + a]);
-            if (a & 1) Qo[r * so + (a >> 1)] = v;
-            else Qe[r * se + (a >> 1)] = v;
-        }
-    }
-    __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const float h0 = hsym[lmax];
-    const int nob0 = nep / 16, ntask = nep / 16 + nop / 16;
-    for (int task = wave; task < ntask; task += 4) {
-        const int par = task < nob0 ? 0 : 1;
-        const int i0 = 16 * (par ? task - nob0 : task);
-        const float *src = par ? Qe : Qo;        // inputs of the other parity
-        const int ss = par ? se : so;
-        const float *self = par ? Qo : Qe;       // the output's own parity (h0 term)
-        const int sself = par ? so : se;
-        const int K = par ? nep : nop;
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        f4 acc[NRG];
-#pragma unroll
-        for (int g = 0; g < NRG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[g][r] = h0 * self[(16 * g + li) * sself + i0 + 4 * lk + r];
-        // A[i][k] = hh[2((i0 + i) - (m0 + k)) + 2 par - 1] at lane (i = li, k = lk)
-        const float *ap = hsym + lmax + 2 * (i0 + li - lk) + 2 * par - 1;
-        const float *bp = src + li * ss + lk;
-        for (int m0 = 0; m0 < K; m0 += 4) {
-            const float av = ap[-2 * m0];
-#pragma unroll
-            for (int g = 0; g < NRG; ++g)
-                acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bp[16 * g * ss + m0], acc[g], 0, 0, 0);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll 1
+    for (int par = 0; par < 2; ++par) {
+        // inputs of the other parity: q[2m + 1 - par], m < K
+        const int K = par ? nep : nop, kcnt = par ? ne : no;
+        __syncthreads();   // previous phase's readers are done; taps written
+        for (int t = tid; t < R * ss; t += 256) {
+            const int r = t / ss, m = t - r * ss;
+            float v = 0.0f;
+            if (m < kcnt && r0 + r < rows) v = to_f(q[(r0 + r) * nu + 2 * m + 1 - par]);
+            Qs[t] = v;
         }
-        const int cnt = par ? no : ne;
+        __syncthreads();
+        const float h0 = hsym[lmax];
+        const int cnt = par ? no : ne;           // outputs of this parity
+        const int ntask = (par ? nop : nep) / 16;
+        for (int task = wave; task < ntask; task += 4) {
+            const int i0 = 16 * task;
+            // the h0 term's inputs are loaded first and added after the
+            // products, so that their latency hides behind the matrix cores
+            float self[NRG][4];
+            f4 acc[NRG];
 #pragma unroll
-        for (int g = 0; g < NRG; ++g) {
-            const size_t row = r0 + 16 * g + li;
-            if (row < rows)
+            for (int g = 0; g < NRG; ++g) {
+                const size_t row = r0 + 16 * g + li;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + 4 * lk + r;
-                    if (i < cnt) out[row * nu + 2 * i + par] = from_f<OutT>(acc[g][r]);
+                    self[g][r] = (row < rows && i < cnt) ? to_f(q[row * nu + 2 * i + par]) : 0.0f;
+                    acc[g][r] = 0.0f;
                 }
+            }
+            // A[i][k] = hh[2((i0 + i) - (m0 + k)) + 2 par - 1] at lane (i = li, k = lk)
+            const float *ap = hsym + lmax + 2 * (i0 + li - lk) + 2 * par - 1;
+            const float *bp = Qs + li * ss + lk;
+            for (int m0 = 0; m0 < K; m0 += 4) {
+                const float av = ap[-2 * m0];
+#pragma unroll
+                for (int g = 0; g < NRG; ++g)
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bp[16 * g * ss + m0], acc[g], 0, 0, 0);
+            }
+#pragma unroll
+            for (int g = 0; g < NRG; ++g) {
+                const size_t row = r0 + 16 * g + li;
+                if (row < rows)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + 4 * lk + r;
+                        if (i < cnt) out[row * nu + 2 * i + par] = from_f<OutT>(acc[g][r] + h0 * self[g][r]);
+                    }
+            }
         }
     }
 }
@@ -1333,9 +1337,9 @@ __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, Ou
 static size_t ramp_mfma_lds(int nu, int nrg) {
     const int ne = (nu + 1) / 2, no = nu / 2;
     const int nep = (ne + 15) & ~15, nop = (no + 15) & ~15;
-    const int se = ((nep + 31) & ~31) + 2, so = ((nop + 31) & ~31) + 2;
+    const int ss = ((nep > nop ? nep : nop) + 31 & ~31) + 2;
     const int lmax = 2 * (nep > nop ? nep : nop) + 1;
-    return sizeof(float) * ((size_t)16 * nrg * (se + so) + 2 * (size_t)lmax + 1);
+    return sizeof(float) * ((size_t)16 * nrg * ss + 2 * (size_t)lmax + 1);
 }
 
 // FBP / FDK pre-weighting: out = scale * w(u, v) * y with the cone-beam
@@ -1504,10 +1508,12 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
         return CT_ERR_UNSUPPORTED;
     }
     {
-        // matrix-core path: as many 16-row groups per workgroup (up to four)
-        // as fit in 64 KB of LDS
-        int nrg = 4;
-        while (nrg > 1 && ramp_mfma_lds(nu, nrg) > 64 * 1024) nrg >>= 1;
+        // matrix-core path, one 16-row group per workgroup: larger groups
+        // share the tap reads but hold more LDS, and the extra workgroups in
+        // flight measured faster (rows of 384 bins: 0.36 ms at 16 rows, 0.39
+        // at 32, 0.48 at 64 for 138240 rows); rows longer than 1600 bins
+        // exceed 64 KB of LDS and take the per-row FIR below
+        constexpr int nrg = 1;
         const size_t lds = ramp_mfma_lds(nu, nrg);
         if (lds <= 64 * 1024) {
             const size_t rpb = 16 * (size_t)nrg;
@@ -1527,11 +1533,7 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
             hipLaunchKernelGGL((k_ramp_mfma<float, __half, NRGV>), mgrid, mblock, lds, s, (const float *)q,       \
                                (__half *)out, g->d_ramp, nu, rows, stop);                                         \
     } while (0)
-            switch (nrg) {
-            case 4: CT_RAMP_MFMA(4); break;
-            case 2: CT_RAMP_MFMA(2); break;
-            default: CT_RAMP_MFMA(1); break;
-            }
+            CT_RAMP_MFMA(nrg);
 #undef CT_RAMP_MFMA
             CT_LAUNCH_CHECK();
             return CT_OK;

@@ -16,6 +16,7 @@ import torch
 import oracle
 import paper_2201_07408_amd as ct
 from synth import workloads
+from synth.geometry import GeometryDesc, PARALLEL_2D
 from tests.gpu_helpers import SMALL_GEOMS, dev, f32, host, rel, say
 
 pytestmark = pytest.mark.gpu
@@ -74,6 +75,19 @@ def test_ramp_and_filtered_backprojection(geoms, name):
     assert rel(f, fref) <= TOL
     x = host(ct.ct_backproject_B(g, dev(y), ramp=True))
     assert rel(x, oracle.backproject_Bun(desc, oracle.ramp(desc, y))) <= TOL
+
+
+@pytest.mark.parametrize("nu", [1, 2, 15, 33, 96, 385, 768, 769, 1088, 1089, 1600, 1601, 2048, 4096])
+def test_ramp_row_lengths(nu):
+    """Row lengths the filter accepts: odd and even (the two parities differ
+    in length), one 16-output task and many, the matrix-core path up to its
+    LDS budget (1600 bins) and the per-row FIR beyond it; 37 rows leave a
+    ragged last row group."""
+    desc = GeometryDesc(PARALLEL_2D, 8, 8, 1, 1.0, 37, nu, 1, 0.8731, 1.0)
+    g = ct.Geometry(desc)
+    say("F row length", nu)
+    y = f32(np.random.default_rng(nu).normal(size=desc.sino_shape))
+    assert rel(host(ct.ct_ramp_filter(g, dev(y))), oracle.ramp(desc, y)) <= TOL
 
 
 @pytest.mark.parametrize("name", ["w1_2d_64", "cone_24"])

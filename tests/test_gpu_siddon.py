@@ -15,7 +15,7 @@ import paper_2201_07408_amd as ct
 from paper_2201_07408_amd import _lib as L
 from synth import workloads
 from synth.geometry import GeometryDesc, parallel2d, cone3d, PARALLEL_2D, CONE_3D
-from tests.gpu_helpers import dev, f32, host, rel, say
+from tests.gpu_helpers import dev, f32, fp32_envelope, host, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -63,17 +63,22 @@ def test_siddon_full_size_sampled(which):
 
 
 def test_siddon_ba_gmres_2d_matches_oracle():
+    """1e-4 at 15 iterations; at 30 the noisy-data iterate amplifies FP32-size
+    perturbations to 1e-4..2e-3 (fp32_envelope) and is held to three times
+    that envelope, its residual history to 1e-4."""
     desc = GEOMS["w1_2d_64"]
     g = ct.Geometry(desc)
     x_true = workloads.w1_phantom()
     clean = oracle.project_A(desc, x_true)
     b = f32(clean + workloads.relative_gaussian_noise(clean, 0.01, 102))
     for B in ("un", "ramp"):
-        r = ct.ct_ba_gmres(g, dev(b), 30, B=B)
-        ref = oracle.ba_gmres(desc, b, 30, B=B)
-        assert r.iters_done == ref.iters_done == 30
-        assert rel(host(r.x), ref.x) <= SOLVE_TOL, B
-        assert rel(np.array(r.res), np.array(ref.res)) <= SOLVE_TOL, B
+        for K in (15, 30):
+            r = ct.ct_ba_gmres(g, dev(b), K, B=B)
+            ref = oracle.ba_gmres(desc, b, K, B=B)
+            tol = SOLVE_TOL if K == 15 else max(SOLVE_TOL, 3.0 * fp32_envelope(desc, b, K, B))
+            assert r.iters_done == ref.iters_done == K
+            assert rel(host(r.x), ref.x) <= tol, (B, K)
+            assert rel(np.array(r.res), np.array(ref.res)) <= SOLVE_TOL, (B, K)
 
 
 def test_siddon_ba_gmres_cone_and_cgls():
