@@ -93,7 +93,6 @@ def relative_gaussian_noise(clean: np.ndarray, level: float, seed: int) -> np.nd
 def paper_geometry():
     pitch = 0.278
     voxel = pitch / 2.0
-    w = 1024 * voxel
     return cone3d(1024, 180, 1088, voxel=voxel, sod_factor=4.0, sdd_factor=8.0, pitch=pitch,
                   nz=300, nv=896)
 
