@@ -322,11 +322,14 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
 // plane the in-plane position is monotone in u and in v, and it is linear in
 // the plane index, so the corners at the chunk's first and last planes bound
 // every ray of the tile.  The next chunk's loads are issued into registers
-// before the current chunk is interpolated.  The kernel is bound by latency
-// more than by issue, so the LDS footprint is kept small (one buffer, rows
-// sized to the boxes that occur, boxes packed in one word) to keep more
-// workgroups resident.  Tiles whose rays do not share a dominant axis, and
-// chunks whose box does not fit, take the direct path.
+// before the current chunk is interpolated.  The kernel is bound by VALU
+// issue, so the per-chunk decisions (skip, unmasked, masked) are taken on
+// the scalar unit from per-wavefront plane ranges that lane shuffles reduce
+// once per ray (no LDS atomics, which serialise across the 64 lanes), and
+// the LDS footprint is kept small (one buffer, rows sized to the boxes that
+// occur, boxes packed in one word) to keep more workgroups resident.  Tiles
+// whose rays do not share a dominant axis, and chunks whose box does not
+// fit, take the direct path.
 constexpr int kTU = 16, kTV = 16;     // rays per workgroup
 constexpr int kPC = 4;                // planes per staged chunk
 constexpr int kSR = 24, kSC = 48;     // staged rows / row stride per plane; 48 = 16 (mod 32 banks)
@@ -335,6 +338,18 @@ constexpr int kStage = kSR * kNQ;     // work-items that stage (one cell per pla
 static_assert(kStage <= kTU * kTV && kNQ * 4 <= kSC, "staging layout");
 constexpr int kMaxChunks = 512;       // planes up to 2048 (longer: direct path)
 constexpr int kVGrp = 8;              // consecutive views kept on one XCD
+constexpr int kWaves = kTU * kTV / 64;
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
 
 // Workgroup order: the hardware deals workgroups to the eight XCDs in turn,
 // so the flat index is remapped such that each XCD receives a contiguous
@@ -370,19 +385,22 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     __shared__ float4 tile4[kPC * kSR * kSC / 4];
     __shared__ uint32_t s_box[kMaxChunks];   // (b0 + 1) << 16 | c0 << 6 | rows; b0 = -1: direct
     __shared__ float s_corner[4][4];
-    __shared__ int s_axes, s_jlo, s_jhi;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx;
+    __shared__ int s_wj[kWaves][5];   // per wavefront: min j0, max j1 (non-empty rays), max j0, min j1, axes
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx, wv = tid >> 6;
     const int au0 = tu * kTU, av0 = tv * kTV;
     const int au = au0 + tx, av = av0 + ty;
     const bool active = au < g.nu && av < g.nv;
-    if (tid == 0) { s_axes = 0; s_jlo = 0x7fffffff; s_jhi = -1; }
-    __syncthreads();
-    RaySetup R;
-    R.j0 = 1; R.j1 = 0; R.ax = 0; R.fb0 = R.gb = R.fc0 = R.gc = R.step = 0.0f;
+    // Lanes outside the detector repeat the ray of the tile's nearest
+    // detector pixel: their samples are valid (inside the tile's boxes) and
+    // are not stored, so no lane needs a separate inactive path.
+    const RaySetup R = ray_setup<true>(g, L, p, min(av, g.nv - 1), min(au, g.nu - 1));
+    {
+        const bool ne = R.j0 <= R.j1;
+        const int a = wave_min(ne ? R.j0 : 0x7fffffff), b = wave_max(ne ? R.j1 : -1);
+        const int c = wave_max(R.j0), d = wave_min(R.j1), e = wave_max(1 << R.ax) | wave_min(1 << R.ax);
+        if ((tid & 63) == 0) { s_wj[wv][0] = a; s_wj[wv][1] = b; s_wj[wv][2] = c; s_wj[wv][3] = d; s_wj[wv][4] = e; }
+    }
     if (active) {
-        R = ray_setup<true>(g, L, p, av, au);
-        atomicOr(&s_axes, 1 << R.ax);
-        if (R.j0 <= R.j1) { atomicMin(&s_jlo, R.j0); atomicMax(&s_jhi, R.j1); }
         // corner rays of the (possibly partial) tile
         const int ulast = min(au0 + kTU, g.nu) - 1 - au0, vlast = min(av0 + kTV, g.nv) - 1 - av0;
         for (int cy = 0; cy < 2; ++cy)
@@ -395,7 +413,18 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
                 }
     }
     __syncthreads();
-    const int axes = s_axes, jlo = s_jlo, jhi = s_jhi;
+    int axes = 0, jlo = 0x7fffffff, jhi = -1;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        jlo = min(jlo, s_wj[w][0]);
+        jhi = max(jhi, s_wj[w][1]);
+        axes |= s_wj[w][4];
+    }
+    // wavefront-uniform plane ranges: the union of the lanes' ranges (skip
+    // test) and their intersection (all lanes sample every plane of a chunk;
+    // a ray that misses the volume leaves it empty)
+    const int wlo = __builtin_amdgcn_readfirstlane(s_wj[wv][0]), whi = __builtin_amdgcn_readfirstlane(s_wj[wv][1]);
+    const int wilo = __builtin_amdgcn_readfirstlane(s_wj[wv][2]), wihi = __builtin_amdgcn_readfirstlane(s_wj[wv][3]);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol, (size_t)offy + L.nvy);
     const int nch = jhi >= jlo ? (jhi - jlo) / kPC + 1 : 0;
     if (axes == 3 || nch > kMaxChunks) {   // mixed dominant axes: direct path
@@ -409,7 +438,6 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     }
     const bool isx = axes != 2;
     const uint32_t S = isx ? L.sx : L.sy, Rw = isx ? L.rx : L.ry, base = isx ? 0u : offy;
-    const int Na = isx ? g.nx : g.ny;
     const int nrows = g.nz + 2 * L.pz;
     // box of every chunk
     for (int c = tid; c < nch; c += kTU * kTV) {
@@ -438,49 +466,52 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     // Staging: work-item t < kStage owns 16-byte column t % kNQ of box row
     // t / kNQ in every plane of a chunk, so its element offset within the
     // box is fixed; per chunk it issues one load and one LDS store per plane
-    // (rows outside the box skip both).
+    // (rows outside the box skip both).  All kPC planes are staged, also
+    // past the last plane of the volume: such planes feed only masked
+    // samples, and the range-checked buffer loads stay inside the copies or
+    // return zero.
     const bool stager = tid < kStage;
     const int r_t = tid / kNQ, c4_t = tid % kNQ;
     const uint32_t toff = __umul24((uint32_t)r_t, Rw) + 4u * (uint32_t)c4_t;
     float4 pre[kPC];
     auto fetch = [&](int c) {
-        const uint32_t bx = s_box[c];
+        const uint32_t bx = __builtin_amdgcn_readfirstlane(s_box[c]);
         if (bx == 0u) return;
         const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u), nr = (int)(bx & 63u);
         const int ja = jlo + c * kPC;
-        const int nplanes = min(kPC, Na - ja);
         if (stager && r_t < nr) {
             const uint32_t e0 = base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0 + toff;
 #pragma unroll
-            for (int pl = 0; pl < kPC; ++pl)
-                if (pl < nplanes) {
-                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((e0 + pl * S) * 4u), 0, 0);
-                    pre[pl] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]), __builtin_bit_cast(float, (uint32_t)w[1]),
-                                          __builtin_bit_cast(float, (uint32_t)w[2]), __builtin_bit_cast(float, (uint32_t)w[3]));
-                }
+            for (int pl = 0; pl < kPC; ++pl) {
+                const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((e0 + pl * S) * 4u), 0, 0);
+                pre[pl] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]), __builtin_bit_cast(float, (uint32_t)w[1]),
+                                      __builtin_bit_cast(float, (uint32_t)w[2]), __builtin_bit_cast(float, (uint32_t)w[3]));
+            }
         }
     };
     const float *tile = (const float *)tile4;
     __syncthreads();   // boxes visible
     if (nch > 0) fetch(0);
     double acc = 0.0;
+    // row slope plus the tile's plane stride in rows: plane pl of a chunk
+    // sits kSR rows below plane pl - 1
+    const float gcs = R.gc + (float)kSR;
     for (int c = 0; c < nch; ++c) {
         const int ja = jlo + c * kPC;
-        const uint32_t bx = s_box[c];
+        const uint32_t bx = __builtin_amdgcn_readfirstlane(s_box[c]);
         const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u);
         if (bx != 0u) {
-            const int nr = (int)(bx & 63u), nplanes = min(kPC, Na - ja);
+            const int nr = (int)(bx & 63u);
             __syncthreads();   // previous chunk's readers are done with the tile
             if (stager && r_t < nr) {
 #pragma unroll
-                for (int pl = 0; pl < kPC; ++pl)
-                    if (pl < nplanes) tile4[(pl * kSR + r_t) * (kSC / 4) + c4_t] = pre[pl];
+                for (int pl = 0; pl < kPC; ++pl) tile4[(pl * kSR + r_t) * (kSC / 4) + c4_t] = pre[pl];
             }
             __syncthreads();
         }
         if (c + 1 < nch) fetch(c + 1);
+        if (ja + kPC - 1 < wlo || ja > whi) continue;   // no lane of this wavefront samples the chunk
         const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
-        if (!__any(jf <= jb)) continue;   // no lane of this wavefront samples the chunk
         if (bx == 0u) {    // box too large: direct loads for this chunk
             if (jf <= jb) acc += direct_samples<true>(R, rs, base, S, Rw, jf, jb);
             continue;
@@ -489,24 +520,26 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
         // the integer box origin is exact, and the box keeps one cell of
         // margin, so inside the lane's plane range the coordinates are >= 0
         // and truncation is floor.
-        const float fb0c = active ? fmaf((float)ja, R.gb, R.fb0) - (float)b0 : 0.0f;
-        const float fc0c = active ? fmaf((float)ja, R.gc, R.fc0) - (float)c0 : 0.0f;
-        const bool full = !active || (R.j0 <= ja && R.j1 >= ja + kPC - 1);
-        float grp = 0.0f;
-        if (__all(full)) {
+        const float fb0c = fmaf((float)ja, R.gb, R.fb0) - (float)b0;
+        const float fc0c = fmaf((float)ja, R.gc, R.fc0) - (float)c0;
+        float grp;
+        if (wilo <= ja && wihi >= ja + kPC - 1) {
             // every lane samples all planes of the chunk: no masks
+            grp = 0.0f;
 #pragma unroll
             for (int pl = 0; pl < kPC; ++pl) {
                 const float fb = pl ? fmaf((float)pl, R.gb, fb0c) : fb0c;
-                const float fc = pl ? fmaf((float)pl, R.gc, fc0c) : fc0c;
+                const float fc = pl ? fmaf((float)pl, gcs, fc0c) : fc0c;
                 const float wb = __builtin_amdgcn_fractf(fb), wc = __builtin_amdgcn_fractf(fc);
-                const float *t = tile + pl * kSR * kSC + __umul24((uint32_t)(int)fc, (uint32_t)kSC) + (uint32_t)(int)fb;
+                const float *t = tile + __umul24((uint32_t)(int)fc, (uint32_t)kSC) + (uint32_t)(int)fb;
                 const float t00 = t[0], t01 = t[1], t10 = t[kSC], t11 = t[kSC + 1];
                 const float a0 = fmaf(wb, t01 - t00, t00);
                 const float a1 = fmaf(wb, t11 - t10, t10);
-                grp += fmaf(wc, a1 - a0, a0);
+                const float v = fmaf(wc, a1 - a0, a0);
+                grp = pl ? grp + v : v;
             }
         } else {
+            grp = 0.0f;
             // boundary chunk: planes outside a lane's range are dropped; their
             // coordinates may leave the box, so the tap indices are clamped
             // into the tile
