@@ -12,7 +12,9 @@
 //
 // Orthonormalisation is classical Gram-Schmidt applied twice (CGS2):
 //   pass 1: d1 = W^T z, ||z||^2                 (one sweep over W)
-//   pass 2: z1 = z - W h1,  d2 = W^T z1          (two sweeps)
+//   pass 2: z1 = z - W h1,  d2 = W^T z1          (one fused sweep; with more
+//           than one chunk of basis vectors, the earlier chunks are read a
+//           second time for their dots)
 //   pass 3: z2 = z1 - W h2, ||z2||^2             (one sweep)
 // Each sweep streams chunks of up to 16 basis vectors with 16-byte loads
 // and accumulates in FP64.  Per-block partial sums go to a column-major
@@ -88,6 +90,39 @@ __global__ __launch_bounds__(256) void k_maxpy(const float *__restrict__ W, size
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     block_partials<NV>(acc, 0, nacc, nrm != 0, vlo, ncol, partials, kMaxBlk, blockIdx.x);
+}
+
+// z' = zs z - sum_j coef[j] W[j] and partial d[j] = W[j] . z' for one chunk
+// in a single sweep (the second pass of CGS2 for the chunk that completes
+// z'; the dots of earlier chunks need the finished z' and take k_mdot).
+template <int NV>
+__global__ __launch_bounds__(256) void k_maxpy_dot(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
+                                                   const float *zin, float *zout, size_t n,
+                                                   const double *__restrict__ coef,
+                                                   const double *__restrict__ zscale, double *__restrict__ partials,
+                                                   const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    __shared__ double cf[NV];
+    for (int j = threadIdx.x; j < cnt; j += 256) cf[j] = coef[vlo + j];
+    __syncthreads();
+    const double zs = zscale ? *zscale : 1.0;
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    const float *Wc = W + (size_t)vlo * ldw;
+    const size_t n4 = n / 4;
+    maxpy_dot_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (size_t i = n4 * 4; i < n; ++i) {
+            double u = zs * (double)zin[i];
+            for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)Wc[(size_t)j * ldw + i];
+            const float o = (float)u;
+            zout[i] = o;
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                if (j < cnt) acc[j] += (double)Wc[(size_t)j * ldw + i] * (double)o;
+        }
+    block_partials<NV>(acc, cnt, 0.0, false, vlo, 0, partials, kMaxBlk, blockIdx.x);
 }
 
 __global__ void k_gmres_init(KState st, int nblk, double qscale_c) {
@@ -437,6 +472,23 @@ static int launch_maxpy(const GmresBufs &b, int vlo, int cnt, const float *zin, 
     return CT_OK;
 }
 
+static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *zin, float *zout, const double *coef,
+                            const double *zscale, hipStream_t s) {
+    ProfScope prof(PROF_CGS, s);
+    const int nblk = sweep_blocks(b.len / 4 + 1);
+    const int *stop = b.st.flags + F_STOP;
+#define CT_MAXPY_DOT(NVV) \
+    hipLaunchKernelGGL(k_maxpy_dot<NVV>, dim3(nblk), dim3(256), 0, s, b.W, b.ldw, vlo, cnt, zin, zout, b.len, coef, \
+                       zscale, b.st.partials, stop)
+    if (cnt <= 1) CT_MAXPY_DOT(1);
+    else if (cnt <= 4) CT_MAXPY_DOT(4);
+    else if (cnt <= 8) CT_MAXPY_DOT(8);
+    else CT_MAXPY_DOT(16);
+#undef CT_MAXPY_DOT
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
 // Partial sums for every block of a pass land in the same columns, so every
 // pass over a vector range uses the same number of blocks (sweep_blocks of
 // len/4 + 1) and the reduction kernels read that many.
@@ -457,14 +509,18 @@ int run_cgs(int mode, const GmresBufs &b, int nvec, const float *zin, float *zou
     for (int lo = 0; lo < nvec; lo += kCgsChunk) {
         const int cnt = nvec - lo < kCgsChunk ? nvec - lo : kCgsChunk;
         const bool last = lo + cnt >= nvec;
-        CT_TRY(launch_maxpy(b, lo, cnt, lo == 0 ? zin : zout, zout, coef, lo == 0 ? zscale : nullptr,
-                            mode == 2 && last, 0, s));
+        const float *src = lo == 0 ? zin : zout;
+        const double *zsc = lo == 0 ? zscale : nullptr;
+        if (mode == 1 && last) {
+            // the chunk that completes z1 also takes its own dots
+            CT_TRY(launch_maxpy_dot(b, lo, cnt, src, zout, coef, zsc, s));
+        } else {
+            CT_TRY(launch_maxpy(b, lo, cnt, src, zout, coef, zsc, mode == 2 && last, 0, s));
+        }
     }
     if (mode == 1)
-        for (int lo = 0; lo < nvec; lo += kCgsChunk) {
-            const int cnt = nvec - lo < kCgsChunk ? nvec - lo : kCgsChunk;
-            CT_TRY(launch_mdot(b, lo, cnt, zout, false, 0, s));
-        }
+        for (int lo = 0; lo + kCgsChunk < nvec; lo += kCgsChunk)   // every chunk but the last
+            CT_TRY(launch_mdot(b, lo, kCgsChunk, zout, false, 0, s));
     return CT_OK;
 }
 

@@ -105,6 +105,34 @@ __device__ __forceinline__ void maxpy_groups(const float *__restrict__ Wc, size_
     }
 }
 
+// Fused multi-axpy and multi-dot over float4 groups: z' = zs z - sum_j
+// cf[j] W[vlo+j] (FP64, rounded to FP32 and stored), then acc[j] +=
+// W[vlo+j] . z' with the same W values still in registers, so the chunk of
+// basis vectors is read once for both.
+template <int NV>
+__device__ __forceinline__ void maxpy_dot_groups(const float *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
+                                                 double zs, const float *zin, float *zout, size_t q0, size_t q1,
+                                                 size_t qstep, double (&acc)[NV]) {
+    for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
+        const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
+        double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
+        float4 w[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) {
+                w[j] = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                const double c = cf[j];
+                u0 -= c * (double)w[j].x; u1 -= c * (double)w[j].y; u2 -= c * (double)w[j].z; u3 -= c * (double)w[j].w;
+            }
+        const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
+        reinterpret_cast<float4 *>(zout)[q] = o;
+        const double o0 = o.x, o1 = o.y, o2 = o.z, o3 = o.w;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) acc[j] += (double)w[j].x * o0 + (double)w[j].y * o1 + (double)w[j].z * o2 + (double)w[j].w * o3;
+    }
+}
+
 // out[j] = sum over b < nblk of partials[j * cstride + b], j < count.  One
 // wavefront per column, lanes stride the blocks, a fixed shuffle tree
 // finishes: the order never changes, so the result is reproducible.
