@@ -802,7 +802,7 @@ __device__ __forceinline__ void project_point(const GeomK &g, double px, double 
 }
 
 template <typename InT>
-__global__ __launch_bounds__(256) void k_bp_cone_staged(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
+__global__ __launch_bounds__(256, 5) void k_bp_cone_staged(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
                                                         const float *__restrict__ in_scale,
                                                         const int *__restrict__ stop) {
     if (stop && *stop) return;
@@ -898,17 +898,32 @@ __global__ __launch_bounds__(256) void k_bp_cone_staged(GeomK g, const InT *__re
         const float dzf = (float)(g.vox * inv_dv), pz0f = (float)(pz0 * inv_dv), wcf = (float)wconst;
         // FP32 data with rows a multiple of four: 16-byte staging loads
         const bool vec4 = sizeof(InT) == 4 && (nu & 3) == 0 && ((uintptr_t)y & 15) == 0;
+        // Each work-item stages the same cells (view within the group, row,
+        // 16-byte column) of every view group, so their coordinates are
+        // computed once; a view's box is one LDS word (u0 low, v0 high).
+        constexpr int kCells = kVG * kSV * Q, kCPT = (kCells + 255) / 256;
+        uint32_t cell[kCPT];   // view in group | row << 8 | first column << 16
+#pragma unroll
+        for (int i = 0; i < kCPT; ++i) {
+            const int q = tid + 256 * i;
+            cell[i] = (uint32_t)(q / (kSV * Q)) | (uint32_t)((q / Q) % kSV) << 8 | (uint32_t)(4 * (q % Q)) << 16;
+        }
+        const uint32_t *boxw = reinterpret_cast<const uint32_t *>(&s_box[0][0]);
         for (int p0 = 0; p0 < P; p0 += kVG) {
             __syncthreads();
-            for (int q = tid; q < kVG * kSV * Q; q += 256) {
-                const int vv = q / (kSV * Q), r = (q / Q) % kSV, c4 = q % Q;
-                const int p = p0 + vv;
+#pragma unroll
+            for (int i = 0; i < kCPT; ++i) {
+                const int q = tid + 256 * i;
+                if (kCells % 256 != 0 && q >= kCells) break;
+                const int p = p0 + (int)(cell[i] & 0xffu);
                 float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (p < P) {
-                    const int v = s_box[p][1] + r, u = s_box[p][0] + 4 * c4;
-                    if (v >= 0 && v < nv) {
-                        const InT *row = y + ((size_t)p * nv + v) * nu;
-                        if (vec4 && u >= 0 && u + 3 < nu) {
+                    const uint32_t bx = boxw[p];
+                    const int v = (int)(short)(bx >> 16) + (int)((cell[i] >> 8) & 0xffu);
+                    const int u = (int)(short)(bx & 0xffffu) + (int)(cell[i] >> 16);
+                    if ((unsigned)v < (unsigned)nv) {
+                        const InT *row = y + (size_t)(uint32_t)(p * nv + v) * (uint32_t)nu;
+                        if (vec4 && (unsigned)u <= (unsigned)(nu - 4)) {
                             e = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(row) + u);
                         } else {
                             float t4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
