@@ -19,6 +19,7 @@
 //    The view's perspective set-up (U, M, u-taps, weight) is FP64 and shared
 //    by the whole chunk; the z loop is FP32 with FMA-from-index.
 //  * F convolves each detector row in LDS.
+#include <type_traits>
 #include <cmath>
 
 #include "ct_common.h"
@@ -937,7 +938,13 @@ __global__ __launch_bounds__(256, 5) void k_bp_cone_staged(GeomK g, const InT *_
                 tile4[q] = e;
             }
             __syncthreads();
-            if (active) {
+            // Rows: within a chunk whose kZC planes all lie in the volume the
+            // box bounds every voxel's row with a cell of margin (v is
+            // linear in z and linear-fractional across the columns, so its
+            // extremes are at the corner columns and the end planes), and
+            // the row index needs no clamp; the last, partial chunk keeps it.
+            auto views = [&](auto clamp_rows) {
+                constexpr bool kClampRows = decltype(clamp_rows)::value;
                 for (int vv = 0; vv < kVG && p0 + vv < P; ++vv) {
                     const int p = p0 + vv;
                     const float c = g.cs32[2 * p], s = g.cs32[2 * p + 1];
@@ -956,13 +963,17 @@ __global__ __launch_bounds__(256, 5) void k_bp_cone_staged(GeomK g, const InT *_
                     for (int z = 0; z < kZC; ++z) {
                         const float fv = fmaf((float)z, dfv, fv0r);
                         const float wv = __builtin_amdgcn_fractf(fv);
-                        const int lv = min(max((int)fv, 0), kSV - 2);
+                        const int lv = kClampRows ? min(max((int)fv, 0), kSV - 2) : (int)fv;
                         const float *t = tv + lv * kSU;
                         const float a = fmaf(wu, t[1] - t[0], t[0]);
                         const float b = fmaf(wu, t[kSU + 1] - t[kSU], t[kSU]);
                         grp[z] = fmaf(w, fmaf(wv, b - a, a), grp[z]);
                     }
                 }
+            };
+            if (active) {
+                if (iz0 + kZC <= g.nz) views(std::false_type{});
+                else views(std::true_type{});
 #pragma unroll
                 for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
             }
