@@ -1392,6 +1392,90 @@ __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, Ou
     }
 }
 
+// The same filter with whole rows staged: for rows short enough that 16 of
+// them (both parities) fit in LDS, a wavefront computes the even and the odd
+// outputs of a 16-output block back to back, adds the h0 terms from LDS, and
+// stores the 32 interleaved outputs of each row as contiguous 16-byte
+// vectors.  Input and output then move once, in full lines, where the
+// one-parity kernel reads each input twice and writes stride-2.
+template <typename InT, typename OutT>
+__global__ __launch_bounds__(256) void k_ramp_rows(const InT *__restrict__ q, OutT *__restrict__ out,
+                                                   const float *__restrict__ taps, int nu, size_t rows,
+                                                   int vec_out, const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    extern __shared__ float sm[];
+    const int ne = (nu + 1) / 2, no = nu / 2;
+    const int nep = (ne + 15) & ~15, nop = (no + 15) & ~15;
+    const int P2 = nep > nop ? nep : nop;      // outputs per parity, padded to 16
+    const int ss = 2 * P2 + 1;                 // odd row stride: rows start on different banks
+    const int lmax = 2 * P2 + 1;
+    float *Qs = sm, *hsym = sm + 16 * ss;
+    const size_t r0 = (size_t)blockIdx.x * 16;
+    const int tid = threadIdx.x;
+    for (int t = tid; t <= 2 * lmax; t += 256) {
+        const int L = t - lmax, aL = L < 0 ? -L : L;
+        hsym[t] = aL < nu ? taps[aL] : 0.0f;
+    }
+    for (int t = tid; t < 16 * ss; t += 256) {
+        const int r = t / ss, m = t - r * ss;
+        float v = 0.0f;
+        if (m < nu && r0 + r < rows) v = to_f(q[(r0 + r) * nu + m]);
+        Qs[t] = v;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const float h0 = hsym[lmax];
+    const size_t row = r0 + li;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    for (int task = wave; task < P2 / 16; task += 4) {
+        const int i0 = 16 * task;
+        // outputs 2i + par from the inputs of the other parity, q[2m + 1 - par];
+        // the two parities' chains are interleaved so that the matrix core
+        // has two independent accumulations in flight (nop <= nep <= nop + 16)
+        const float *ap0 = hsym + lmax + 2 * (i0 + li - lk) - 1, *ap1 = ap0 + 2;
+        const float *bp0 = Qs + li * ss + 2 * lk + 1, *bp1 = bp0 - 1;
+        f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+        for (int m0 = 0; m0 < nop; m0 += 4) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap0[-2 * m0], bp0[2 * m0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1[-2 * m0], bp1[2 * m0], acc1, 0, 0, 0);
+        }
+        for (int m0 = nop; m0 < nep; m0 += 4)
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1[-2 * m0], bp1[2 * m0], acc1, 0, 0, 0);
+        float o[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = li * ss + 2 * (i0 + 4 * lk + r);
+            o[2 * r] = acc0[r] + h0 * Qs[c];
+            o[2 * r + 1] = acc1[r] + h0 * Qs[c + 1];
+        }
+        if (row < rows) {
+            const int col0 = 2 * (i0 + 4 * lk);   // this lane's 8 consecutive outputs of the row
+            OutT *dst = out + row * nu + col0;
+            if (vec_out && col0 + 8 <= nu) {
+                if (sizeof(OutT) == 4) {
+                    reinterpret_cast<float4 *>(dst)[0] = make_float4(o[0], o[1], o[2], o[3]);
+                    reinterpret_cast<float4 *>(dst)[1] = make_float4(o[4], o[5], o[6], o[7]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) dst[k] = from_f<OutT>(o[k]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (col0 + k < nu) dst[k] = from_f<OutT>(o[k]);
+            }
+        }
+    }
+}
+
+static size_t ramp_rows_lds(int nu) {
+    const int ne = (nu + 1) / 2, no = nu / 2;
+    const int P2 = ((ne + 15) & ~15) > ((no + 15) & ~15) ? ((ne + 15) & ~15) : ((no + 15) & ~15);
+    return sizeof(float) * ((size_t)16 * (2 * P2 + 1) + 2 * (size_t)(2 * P2 + 1) + 1);
+}
+
 // LDS bytes of k_ramp_mfma for a row length and row-group count
 static size_t ramp_mfma_lds(int nu, int nrg) {
     const int ne = (nu + 1) / 2, no = nu / 2;
@@ -1565,6 +1649,23 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
     if (shm > 64 * 1024) {
         set_error("ramp filter: detector rows longer than 4096 are not supported");
         return CT_ERR_UNSUPPORTED;
+    }
+    if (ramp_rows_lds(nu) <= 64 * 1024) {
+        // whole rows staged (rows up to about 900 bins)
+        const size_t lds = ramp_rows_lds(nu);
+        dim3 rgrid((unsigned)((rows + 15) / 16)), rblock(256);
+        const size_t es = out_dtype == CT_F16 ? 2 : 4;
+        const int vec_out = (nu % 4 == 0) && ((uintptr_t)out % 16 == 0) && (es == 4 || nu % 8 == 0);
+#define CT_RAMP_ROWS(IT, OT) \
+    hipLaunchKernelGGL((k_ramp_rows<IT, OT>), rgrid, rblock, lds, s, (const IT *)q, (OT *)out, g->d_ramp, nu, rows, \
+                       vec_out, stop)
+        if (q_dtype == CT_F32 && out_dtype == CT_F32) CT_RAMP_ROWS(float, float);
+        else if (q_dtype == CT_F16 && out_dtype == CT_F16) CT_RAMP_ROWS(__half, __half);
+        else if (q_dtype == CT_F16 && out_dtype == CT_F32) CT_RAMP_ROWS(__half, float);
+        else CT_RAMP_ROWS(float, __half);
+#undef CT_RAMP_ROWS
+        CT_LAUNCH_CHECK();
+        return CT_OK;
     }
     {
         // matrix-core path, one 16-row group per workgroup: larger groups
