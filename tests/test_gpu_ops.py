@@ -77,12 +77,13 @@ def test_ramp_and_filtered_backprojection(geoms, name):
     assert rel(x, oracle.backproject_Bun(desc, oracle.ramp(desc, y))) <= TOL
 
 
-@pytest.mark.parametrize("nu", [1, 2, 15, 33, 96, 385, 768, 769, 1088, 1089, 1600, 1601, 2048, 4096])
+@pytest.mark.parametrize("nu", [1, 2, 15, 33, 96, 385, 768, 769, 896, 897, 1088, 1089, 1600, 1601, 2048, 4096])
 def test_ramp_row_lengths(nu):
     """Row lengths the filter accepts: odd and even (the two parities differ
-    in length), one 16-output task and many, the matrix-core path up to its
-    LDS budget (1600 bins) and the per-row FIR beyond it; 37 rows leave a
-    ragged last row group."""
+    in length), one 16-output block and many, the whole-row matrix-core
+    kernel up to its LDS budget (896 bins), the one-parity kernel up to 1600
+    bins and the per-row FIR beyond; 37 rows leave a ragged last row
+    group."""
     desc = GeometryDesc(PARALLEL_2D, 8, 8, 1, 1.0, 37, nu, 1, 0.8731, 1.0)
     g = ct.Geometry(desc)
     say("F row length", nu)
