@@ -140,7 +140,8 @@ int launch_fill(float *p, size_t n, float v, hipStream_t s);
 int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s);
 int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy,
                     const int *stop, hipStream_t s);
-int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y,
+// xs: the plain volume (read only by line-intersection tiles that walk it)
+int launch_project(const ct_geometry *g, const float *vx, const float *vy, const float *xs, void *y,
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
 int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx,
                      float *vy, const int *stop, hipStream_t s);
@@ -151,7 +152,8 @@ int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *
 int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out,
                 int out_dtype, size_t rows, const int *stop, hipStream_t s);
 // line-intersection projector and its transpose (x read / scattered in its
-// own layout, no padded copies; the transpose adds into x)
+// own layout, no padded copies; the transpose adds into x); cone geometries
+// project through launch_project's staged kernel instead
 int launch_siddon(const ct_geometry *g, const float *x, void *y, int y_dtype,
                   const float *out_scale, const int *stop, hipStream_t s);
 int launch_siddon_T(const ct_geometry *g, const void *y, int y_dtype, float *x,

@@ -41,6 +41,10 @@ __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
     return make_float2(__builtin_bit_cast(float, (uint32_t)v[0]), __builtin_bit_cast(float, (uint32_t)v[1]));
 }
 
+__device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
+    return __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)(elem * 4u), 0, 0));
+}
+
 __device__ __forceinline__ float to_f(float v) { return v; }
 __device__ __forceinline__ float to_f(__half v) { return __half2float(v); }
 template <typename T> __device__ __forceinline__ T from_f(float v);
@@ -313,6 +317,55 @@ __global__ __launch_bounds__(256) void k_project(GeomK g, PadLayout L, const flo
     store_ray(g, y, p, av, au, acc, R.step, out_scale);
 }
 
+// Line-intersection (Siddon) weights of one ray on the slabs of the dominant
+// axis.  Slab j spans plane coordinate j -+ 1/2 and advances the ray by
+// R.step in length; with the in-plane coordinates shifted by 1/2 (b' = b +
+// 1/2, c' = c + 1/2) a voxel index is floor(b').  Where |gb|, |gc| <= 1 the
+// ray crosses at most one b boundary and one c boundary inside a slab, at
+// slab fractions s_b and s_c, so the slab splits into three segments (some
+// of length 0): [0, s1] in voxel (b'_lo, c'_lo), [s1, s2] in the voxel that
+// the first crossing leads to, [s2, 1] in (b'_hi, c'_hi), with s1 =
+// min(s_b, s_c), s2 = max(s_b, s_c).  The ray sum is R.step times the
+// fraction-weighted voxel values.
+struct SlabSeg {
+    int b0, c0, b1, c1, bm, cm;   // first, last and middle voxel indices
+    float s1, s2;
+};
+__device__ __forceinline__ SlabSeg slab_segments(float blo, float bhi, float clo, float chi, float igb, float igc) {
+    SlabSeg q;
+    q.b0 = (int)floorf(blo); q.b1 = (int)floorf(bhi);
+    q.c0 = (int)floorf(clo); q.c1 = (int)floorf(chi);
+    const float sb = q.b0 == q.b1 ? 1.0f : ((float)max(q.b0, q.b1) - blo) * igb;
+    const float sc = q.c0 == q.c1 ? 1.0f : ((float)max(q.c0, q.c1) - clo) * igc;
+    q.s1 = fminf(sb, sc);
+    q.s2 = fmaxf(sb, sc);
+    const bool bfirst = sb < sc;
+    q.bm = bfirst ? q.b1 : q.b0;
+    q.cm = bfirst ? q.c0 : q.c1;
+    return q;
+}
+
+// Slabs [ja, jb] of one ray read straight from the padded copy (tiles or
+// chunks that are not staged).
+__device__ __forceinline__ double slab_sums_direct(const RaySetup &R, float igb, float igc,
+                                                   __amdgpu_buffer_rsrc_t rs, uint32_t base, uint32_t S,
+                                                   uint32_t Rw, int ja, int jb) {
+    double acc = 0.0;
+    for (int j = ja; j <= jb; ++j) {
+        const float fl = (float)j - 0.5f, fh = (float)j + 0.5f;
+        const SlabSeg q = slab_segments(fmaf(fl, R.gb, R.fb0) + 0.5f, fmaf(fh, R.gb, R.fb0) + 0.5f,
+                                        fmaf(fl, R.gc, R.fc0) + 0.5f, fmaf(fh, R.gc, R.fc0) + 0.5f, igb, igc);
+        const uint32_t pj = base + __umul24((uint32_t)j, S);
+        const float x0 = ld1(rs, pj + __umul24((uint32_t)q.c0, Rw) + (uint32_t)q.b0);
+        const float xm = ld1(rs, pj + __umul24((uint32_t)q.cm, Rw) + (uint32_t)q.bm);
+        const float x1 = ld1(rs, pj + __umul24((uint32_t)q.c1, Rw) + (uint32_t)q.b1);
+        acc += (double)fmaf(q.s1, x0, fmaf(q.s2 - q.s1, xm, (1.0f - q.s2) * x1));
+    }
+    return acc;
+}
+
+__device__ double siddon_ray_sum(const GeomK &g, const float *__restrict__ x, int p, int av, int au);
+
 // ---------------------------------------------------- staged 3D projector
 // A workgroup is a 16 (u) x 16 (v) tile of one view's detector.  At a given
 // plane its 256 rays sample a compact patch of about 18 x 18 voxels, and
@@ -375,10 +428,15 @@ __device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int &tu, int &
     return p < P;
 }
 
-template <typename OutT>
+// SID: the line-intersection model instead of Joseph's (same tiles, boxes
+// and staging; per plane a slab of three segments instead of a bilinear
+// sample; tiles with rays steeper than one voxel per plane in z walk the
+// plain volume xs with the generic line-intersection walk).
+template <typename OutT, bool SID>
 __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
                                                         uint32_t offy, OutT *__restrict__ y,
                                                         const float *__restrict__ out_scale,
+                                                        const float *__restrict__ xs,
                                                         const int *__restrict__ stop) {
     if (stop && *stop) return;
     int tu, tv, p;
@@ -398,7 +456,8 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     {
         const bool ne = R.j0 <= R.j1;
         const int a = wave_min(ne ? R.j0 : 0x7fffffff), b = wave_max(ne ? R.j1 : -1);
-        const int c = wave_max(R.j0), d = wave_min(R.j1), e = wave_max(1 << R.ax) | wave_min(1 << R.ax);
+        const int c = wave_max(R.j0), d = wave_min(R.j1);
+        const int e = (wave_max(1 << R.ax) | wave_min(1 << R.ax)) | (SID ? wave_max(fabsf(R.gc) > 1.0f ? 4 : 0) : 0);
         if ((tid & 63) == 0) { s_wj[wv][0] = a; s_wj[wv][1] = b; s_wj[wv][2] = c; s_wj[wv][3] = d; s_wj[wv][4] = e; }
     }
     if (active) {
@@ -428,11 +487,21 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     const int wilo = __builtin_amdgcn_readfirstlane(s_wj[wv][2]), wihi = __builtin_amdgcn_readfirstlane(s_wj[wv][3]);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol, (size_t)offy + L.nvy);
     const int nch = jhi >= jlo ? (jhi - jlo) / kPC + 1 : 0;
+    // per-ray reciprocal slopes of the line-intersection slabs
+    const float igb = SID ? 1.0f / R.gb : 0.0f, igc = SID ? 1.0f / R.gc : 0.0f;
+    if (SID && (axes & 4)) {   // steep rays: generic walk over the plain volume
+        if (active) {
+            const float val = (float)siddon_ray_sum(g, xs, p, av, au);
+            y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(out_scale ? val * *out_scale : val);
+        }
+        return;
+    }
     if (axes == 3 || nch > kMaxChunks) {   // mixed dominant axes: direct path
         if (active) {
             const bool isx = R.ax == 0;
-            const double acc = direct_samples<true>(R, rs, isx ? 0u : offy, isx ? L.sx : L.sy,
-                                                    isx ? L.rx : L.ry, R.j0, R.j1);
+            const uint32_t bs = isx ? 0u : offy, Ss = isx ? L.sx : L.sy, Rs = isx ? L.rx : L.ry;
+            const double acc = SID ? slab_sums_direct(R, igb, igc, rs, bs, Ss, Rs, R.j0, R.j1)
+                                   : direct_samples<true>(R, rs, bs, Ss, Rs, R.j0, R.j1);
             store_ray(g, y, p, av, au, acc, R.step, out_scale);
         }
         return;
@@ -514,7 +583,9 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
         if (ja + kPC - 1 < wlo || ja > whi) continue;   // no lane of this wavefront samples the chunk
         const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
         if (bx == 0u) {    // box too large: direct loads for this chunk
-            if (jf <= jb) acc += direct_samples<true>(R, rs, base, S, Rw, jf, jb);
+            if (jf <= jb)
+                acc += SID ? slab_sums_direct(R, igb, igc, rs, base, S, Rw, jf, jb)
+                           : direct_samples<true>(R, rs, base, S, Rw, jf, jb);
             continue;
         }
         // Box-relative coordinates at the chunk's first plane.  Subtracting
@@ -524,7 +595,33 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
         const float fb0c = fmaf((float)ja, R.gb, R.fb0) - (float)b0;
         const float fc0c = fmaf((float)ja, R.gc, R.fc0) - (float)c0;
         float grp;
-        if (wilo <= ja && wihi >= ja + kPC - 1) {
+        if (SID) {
+            // slab boundaries k = 0..kPC at plane coordinates ja + k - 1/2,
+            // shifted by 1/2 so that floor gives the voxel; unmasked where
+            // every lane samples every plane, else indices clamped into the
+            // tile and slabs outside a lane's range dropped
+            const bool all = wilo <= ja && wihi >= ja + kPC - 1;
+            float bq[kPC + 1], cq[kPC + 1];
+#pragma unroll
+            for (int k = 0; k <= kPC; ++k) {
+                bq[k] = fmaf((float)k - 0.5f, R.gb, fb0c) + 0.5f;
+                cq[k] = fmaf((float)k - 0.5f, R.gc, fc0c) + 0.5f;
+            }
+            grp = 0.0f;
+#pragma unroll
+            for (int pl = 0; pl < kPC; ++pl) {
+                SlabSeg q = slab_segments(bq[pl], bq[pl + 1], cq[pl], cq[pl + 1], igb, igc);
+                if (!all) {
+                    q.b0 = min(max(q.b0, 0), kSC - 1); q.b1 = min(max(q.b1, 0), kSC - 1); q.bm = min(max(q.bm, 0), kSC - 1);
+                    q.c0 = min(max(q.c0, 0), kSR - 1); q.c1 = min(max(q.c1, 0), kSR - 1); q.cm = min(max(q.cm, 0), kSR - 1);
+                }
+                const float *t = tile + pl * kSR * kSC;
+                const float x0 = t[q.c0 * kSC + q.b0], xm = t[q.cm * kSC + q.bm], x1 = t[q.c1 * kSC + q.b1];
+                const float v = fmaf(q.s1, x0, fmaf(q.s2 - q.s1, xm, (1.0f - q.s2) * x1));
+                const int j = ja + pl;
+                grp += (all || (j >= jf && j <= jb)) ? v : 0.0f;
+            }
+        } else if (wilo <= ja && wihi >= ja + kPC - 1) {
             // every lane samples all planes of the chunk: no masks
             grp = 0.0f;
 #pragma unroll
@@ -712,22 +809,16 @@ __device__ __forceinline__ double siddon_step(const GeomK &g, SiddonWalk &w, lon
     return len;
 }
 
-template <bool CONE, typename OutT>
-__global__ __launch_bounds__(256) void k_siddon(GeomK g, const float *__restrict__ x, OutT *__restrict__ y,
-                                                const float *__restrict__ out_scale,
-                                                const int *__restrict__ stop) {
-    if (stop && *stop) return;
-    const int au = blockIdx.x * blockDim.x + threadIdx.x;
-    const int av = blockIdx.y * blockDim.y + threadIdx.y;
-    const int p = blockIdx.z;
-    if (au >= g.nu || av >= g.nv) return;
+// Sum over the voxels one ray crosses of length x value, walking the plain
+// volume.  The walk does not depend on the data: it advances eight steps,
+// then issues their eight gathers together (a finished walk repeats its last
+// voxel with length 0); 8 beat 4 and 2 at 256^3 (12.8, 13.3, 17.2 ms).
+template <bool CONE>
+__device__ __forceinline__ double siddon_walk_sum(const GeomK &g, const float *__restrict__ x, int p, int av,
+                                                  int au) {
     SiddonWalk w = siddon_setup<CONE>(g, p, av, au);
     double acc = 0.0;
     if (w.hit) {
-        // the walk does not depend on the data: advance eight steps, then
-        // issue their eight gathers together (a finished walk repeats its
-        // last voxel with length 0); 8 beat 4 and 2 at 256^3 (12.8, 13.3,
-        // 17.2 ms)
         constexpr int U = 8;
         long idx = w.i0 + (long)w.i1 * g.nx + (long)w.i2 * g.nx * g.ny;
         const int steps = g.nx + g.ny + g.nz + 2;
@@ -753,7 +844,25 @@ __global__ __launch_bounds__(256) void k_siddon(GeomK g, const float *__restrict
             for (int u = 0; u < U; ++u) acc = fma(len[u], (double)v[u], acc);
         }
     }
-    float val = (float)acc;
+    return acc;
+}
+
+__device__ double siddon_ray_sum(const GeomK &g, const float *__restrict__ x, int p, int av, int au) {
+    return siddon_walk_sum<true>(g, x, p, av, au);
+}
+
+// One work-item per ray (2D, and cone geometries the staged kernel does not
+// take).
+template <bool CONE, typename OutT>
+__global__ __launch_bounds__(256) void k_siddon(GeomK g, const float *__restrict__ x, OutT *__restrict__ y,
+                                                const float *__restrict__ out_scale,
+                                                const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int au = blockIdx.x * blockDim.x + threadIdx.x;
+    const int av = blockIdx.y * blockDim.y + threadIdx.y;
+    const int p = blockIdx.z;
+    if (au >= g.nu || av >= g.nv) return;
+    float val = (float)siddon_walk_sum<CONE>(g, x, p, av, au);
     if (out_scale) val *= *out_scale;
     y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(val);
 }
@@ -1538,7 +1647,7 @@ static void ray_grid(const ct_geometry *g, dim3 &grid, dim3 &block) {
     grid = dim3((g->k.nu + block.x - 1) / block.x, (g->k.nv + block.y - 1) / block.y, g->k.P);
 }
 
-int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y, int y_dtype,
+int launch_project(const ct_geometry *g, const float *vx, const float *vy, const float *xs, void *y, int y_dtype,
                    const float *out_scale, const int *stop, hipStream_t s) {
     dim3 grid, block;
     ray_grid(g, grid, block);
@@ -1561,8 +1670,13 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
             return CT_ERR_UNSUPPORTED;
         }
         dim3 sgrid((unsigned)(8 * per)), sblock(kTU, kTV);
-        if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
-        else hipLaunchKernelGGL((k_project_staged<__half>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
+        if (g->k.proj == CT_SIDDON) {
+            if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float, true>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, xs, stop);
+            else hipLaunchKernelGGL((k_project_staged<__half, true>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, xs, stop);
+        } else {
+            if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float, false>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, xs, stop);
+            else hipLaunchKernelGGL((k_project_staged<__half, false>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, xs, stop);
+        }
     } else {
         if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
         else hipLaunchKernelGGL((k_project<false, __half>), grid, block, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
@@ -1815,10 +1929,11 @@ OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *w
 
 int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratch &sc, bool pad_ready,
             const float *out_scale, const int *stop, hipStream_t s) {
-    if (g->k.proj == CT_SIDDON) return launch_siddon(g, x, y, y_dtype, out_scale, stop, s);
+    if (g->k.proj == CT_SIDDON && g->k.kind != CT_CONE_CIRCULAR_3D)
+        return launch_siddon(g, x, y, y_dtype, out_scale, stop, s);
     if (!pad_ready) CT_TRY(launch_pad_zero(g, sc.vx, sc.vy, s));
     CT_TRY(launch_pad_copy(g, x, sc.vx, sc.vy, stop, s));
-    return launch_project(g, sc.vx, sc.vy, y, y_dtype, out_scale, stop, s);
+    return launch_project(g, sc.vx, sc.vy, x, y, y_dtype, out_scale, stop, s);
 }
 
 int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *x, OpScratch &sc,
