@@ -140,8 +140,7 @@ int launch_fill(float *p, size_t n, float v, hipStream_t s);
 int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s);
 int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy,
                     const int *stop, hipStream_t s);
-// xs: the plain volume (read only by line-intersection tiles that walk it)
-int launch_project(const ct_geometry *g, const float *vx, const float *vy, const float *xs, void *y,
+int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y,
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
 int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx,
                      float *vy, const int *stop, hipStream_t s);

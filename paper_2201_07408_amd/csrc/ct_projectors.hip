@@ -364,8 +364,6 @@ __device__ __forceinline__ double slab_sums_direct(const RaySetup &R, float igb,
     return acc;
 }
 
-__device__ double siddon_ray_sum(const GeomK &g, const float *__restrict__ x, int p, int av, int au);
-
 // ---------------------------------------------------- staged 3D projector
 // A workgroup is a 16 (u) x 16 (v) tile of one view's detector.  At a given
 // plane its 256 rays sample a compact patch of about 18 x 18 voxels, and
@@ -430,13 +428,13 @@ __device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int &tu, int &
 
 // SID: the line-intersection model instead of Joseph's (same tiles, boxes
 // and staging; per plane a slab of three segments instead of a bilinear
-// sample; tiles with rays steeper than one voxel per plane in z walk the
-// plain volume xs with the generic line-intersection walk).
+// sample).  Geometries admit no ray steeper than one voxel per plane in z
+// (ct_geometry_create rejects cone angles that allow z-dominant rays), as
+// the slab decomposition requires.
 template <typename OutT, bool SID>
 __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
                                                         uint32_t offy, OutT *__restrict__ y,
                                                         const float *__restrict__ out_scale,
-                                                        const float *__restrict__ xs,
                                                         const int *__restrict__ stop) {
     if (stop && *stop) return;
     int tu, tv, p;
@@ -457,7 +455,7 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
         const bool ne = R.j0 <= R.j1;
         const int a = wave_min(ne ? R.j0 : 0x7fffffff), b = wave_max(ne ? R.j1 : -1);
         const int c = wave_max(R.j0), d = wave_min(R.j1);
-        const int e = (wave_max(1 << R.ax) | wave_min(1 << R.ax)) | (SID ? wave_max(fabsf(R.gc) > 1.0f ? 4 : 0) : 0);
+        const int e = wave_max(1 << R.ax) | wave_min(1 << R.ax);
         if ((tid & 63) == 0) { s_wj[wv][0] = a; s_wj[wv][1] = b; s_wj[wv][2] = c; s_wj[wv][3] = d; s_wj[wv][4] = e; }
     }
     if (active) {
@@ -489,13 +487,6 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     const int nch = jhi >= jlo ? (jhi - jlo) / kPC + 1 : 0;
     // per-ray reciprocal slopes of the line-intersection slabs
     const float igb = SID ? 1.0f / R.gb : 0.0f, igc = SID ? 1.0f / R.gc : 0.0f;
-    if (SID && (axes & 4)) {   // steep rays: generic walk over the plain volume
-        if (active) {
-            const float val = (float)siddon_ray_sum(g, xs, p, av, au);
-            y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(out_scale ? val * *out_scale : val);
-        }
-        return;
-    }
     if (axes == 3 || nch > kMaxChunks) {   // mixed dominant axes: direct path
         if (active) {
             const bool isx = R.ax == 0;
@@ -847,12 +838,8 @@ __device__ __forceinline__ double siddon_walk_sum(const GeomK &g, const float *_
     return acc;
 }
 
-__device__ double siddon_ray_sum(const GeomK &g, const float *__restrict__ x, int p, int av, int au) {
-    return siddon_walk_sum<true>(g, x, p, av, au);
-}
-
-// One work-item per ray (2D, and cone geometries the staged kernel does not
-// take).
+// One work-item per ray (2D geometries; cone geometries take the staged
+// kernel).
 template <bool CONE, typename OutT>
 __global__ __launch_bounds__(256) void k_siddon(GeomK g, const float *__restrict__ x, OutT *__restrict__ y,
                                                 const float *__restrict__ out_scale,
@@ -1647,7 +1634,7 @@ static void ray_grid(const ct_geometry *g, dim3 &grid, dim3 &block) {
     grid = dim3((g->k.nu + block.x - 1) / block.x, (g->k.nv + block.y - 1) / block.y, g->k.P);
 }
 
-int launch_project(const ct_geometry *g, const float *vx, const float *vy, const float *xs, void *y, int y_dtype,
+int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y, int y_dtype,
                    const float *out_scale, const int *stop, hipStream_t s) {
     dim3 grid, block;
     ray_grid(g, grid, block);
@@ -1671,11 +1658,11 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, const
         }
         dim3 sgrid((unsigned)(8 * per)), sblock(kTU, kTV);
         if (g->k.proj == CT_SIDDON) {
-            if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float, true>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, xs, stop);
-            else hipLaunchKernelGGL((k_project_staged<__half, true>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, xs, stop);
+            if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float, true>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
+            else hipLaunchKernelGGL((k_project_staged<__half, true>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
         } else {
-            if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float, false>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, xs, stop);
-            else hipLaunchKernelGGL((k_project_staged<__half, false>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, xs, stop);
+            if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project_staged<float, false>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
+            else hipLaunchKernelGGL((k_project_staged<__half, false>), sgrid, sblock, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
         }
     } else {
         if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
@@ -1933,7 +1920,7 @@ int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratc
         return launch_siddon(g, x, y, y_dtype, out_scale, stop, s);
     if (!pad_ready) CT_TRY(launch_pad_zero(g, sc.vx, sc.vy, s));
     CT_TRY(launch_pad_copy(g, x, sc.vx, sc.vy, stop, s));
-    return launch_project(g, sc.vx, sc.vy, x, y, y_dtype, out_scale, stop, s);
+    return launch_project(g, sc.vx, sc.vy, y, y_dtype, out_scale, stop, s);
 }
 
 int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *x, OpScratch &sc,
