@@ -389,7 +389,10 @@ constexpr int kNQ = 8;                // staged 16-byte columns per row (32 floa
 constexpr int kStage = kSR * kNQ;     // work-items that stage (one cell per plane each)
 static_assert(kStage <= kTU * kTV && kNQ * 4 <= kSC, "staging layout");
 constexpr int kMaxChunks = 512;       // planes up to 2048 (longer: direct path)
-constexpr int kVGrp = 16;             // consecutive views kept on one XCD (4: 4.90 ms, 8: 4.71, 16: 4.64, 32: 4.74 at 256^3)
+// consecutive views kept on one XCD; measured ms per launch at 256^3 with
+// 360 views / at 1024 x 1024 x 300 with 180 views: 6: 4.58 / 76.7,
+// 8: 4.72 / 78.7, 10: 4.51 / 77.2, 16: 4.64 / 88.6, 20: 4.66 / 91.5
+constexpr int kVGrp = 10;
 constexpr int kWaves = kTU * kTV / 64;
 
 __device__ __forceinline__ int wave_min(int v) {
