@@ -144,6 +144,9 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
 int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx,
                      float *vy, const int *stop, hipStream_t s);
+// cone-beam A^T gathered per voxel straight into x (times *scale if given)
+int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, float *x,
+                            const float *scale, const int *stop, hipStream_t s);
 int launch_unpad_sum(const ct_geometry *g, const float *vx, const float *vy, float *x,
                      const float *scale, const int *stop, hipStream_t s);
 int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *x,

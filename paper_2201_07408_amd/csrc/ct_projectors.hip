@@ -159,17 +159,24 @@ struct RaySetup {
     float step;        // vox * |r| / |r_a|
 };
 
+// In-plane direction of the cone-beam ray through detector column au at
+// view (c, s) = (cos, sin): the projector's dominant-axis decision and the
+// voxel-driven transpose both take it from here, so they agree bit for bit.
+__device__ __forceinline__ void cone_ray_xy(const GeomK &g, double c, double s, int au, double &rx, double &ry) {
+    const double u = (au - 0.5 * (g.nu - 1)) * g.du;
+    rx = -g.sdd * c - u * s;
+    ry = -g.sdd * s + u * c;
+}
+
 template <bool CONE>
 __device__ __forceinline__ RaySetup ray_setup(const GeomK &g, const PadLayout &L, int p, int av, int au) {
     const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
     double ox, oy, rx, ry, rz;
     if (CONE) {
-        const double u = (au - 0.5 * (g.nu - 1)) * g.du;
         const double v = (av - 0.5 * (g.nv - 1)) * g.dv;
         ox = g.sod * c;
         oy = g.sod * s;
-        rx = -g.sdd * c - u * s;
-        ry = -g.sdd * s + u * c;
+        cone_ray_xy(g, c, s, au, rx, ry);
         rz = v;
     } else {
         const double sa = (au - 0.5 * (g.nu - 1)) * g.du;
@@ -701,8 +708,105 @@ __global__ __launch_bounds__(256) void k_project_T(GeomK g, PadLayout L, const I
     }
 }
 
+constexpr int kZC = 16;   // z voxels per work-item in the voxel-driven cone kernels
+
+// Exact transpose of the cone-beam Joseph projector, gathered per voxel
+// instead of scattered per sample.  Voxel (ix, iy, iz) receives, from every
+// ray that samples its plane (x = ix for x-dominant rays, y = iy for
+// y-dominant ones) within one voxel of it in both in-plane coordinates, the
+// ray's value times the bilinear weight tent(f_b - i_b) tent(f_c - iz) and
+// the ray's step length: the A_ij of the forward model, summed over i.
+// Along a plane a ray's b coordinate depends on its detector column only,
+// f_b = (o_b + D t(u)) / vox + C_b with D the plane's distance from the
+// source along the dominant axis and t = r_b / r_a a linear-fractional
+// function of u; inverting it at f_b = i_b -+ 1 gives the few candidate
+// columns (all columns where the inverse interval wraps through infinity),
+// each of which is tested exactly, dominant axis included.  Its c
+// coordinate is linear in the detector row, which gives the rows per voxel.
+// Views are summed in FP32 in groups of four and added to FP64, as in B_un;
+// no atomics, so the result is deterministic.
+template <typename InT>
+__global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
+                                                          const float *__restrict__ scale,
+                                                          const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int ix = blockIdx.x * 16 + threadIdx.x, iy = blockIdx.y * 16 + threadIdx.y, iz0 = blockIdx.z * kZC;
+    if (ix >= g.nx || iy >= g.ny) return;   // no barriers below
+    const int nu = g.nu, nv = g.nv, P = g.P;
+    const double vox = g.vox;
+    const double Cx = 0.5 * (g.nx - 1), Cy = 0.5 * (g.ny - 1), Cu = 0.5 * (nu - 1);
+    const float Czf = (float)(0.5 * (g.nz - 1)), Cvf = (float)(0.5 * (nv - 1)), dvf = (float)g.dv;
+    const double xc = (ix - Cx) * vox, yc = (iy - Cy) * vox;
+    double acc[kZC];
+    float grp[kZC];
+#pragma unroll
+    for (int z = 0; z < kZC; ++z) { acc[z] = 0.0; grp[z] = 0.0f; }
+    for (int p = 0; p < P; ++p) {
+        const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+        const double ox = g.sod * c, oy = g.sod * s;
+        const InT *yp = y + (size_t)p * nv * nu;
+#pragma unroll 1
+        for (int axis = 0; axis < 2; ++axis) {
+            // axis 0: x-dominant rays on the plane x = xc (b = y); axis 1:
+            // y-dominant rays on the plane y = yc (b = x)
+            const double D = axis ? yc - oy : xc - ox;
+            const double ob = axis ? ox : oy, Cb = axis ? Cx : Cy;
+            const int ib = axis ? ix : iy;
+            // t(u) = (al u + be) / (ga u + de)
+            const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
+            const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
+            const double tm = ((ib - 1 - Cb) * vox - ob) / D, tp = ((ib + 1 - Cb) * vox - ob) / D;
+            const double dm = ga * tm - al, dp = ga * tp - al;
+            int a_lo = 0, a_hi = nu - 1;
+            if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
+                const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
+                const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
+                a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
+                a_hi = ahi < (double)nu ? min((int)ceil(ahi), nu - 1) : nu - 1;
+                if (alo >= (double)nu || ahi <= -1.0) a_hi = -1;   // interval off the detector
+            }
+            for (int au = a_lo; au <= a_hi; ++au) {
+                double rx, ry;
+                cone_ray_xy(g, c, s, au, rx, ry);
+                if ((fabs(rx) >= fabs(ry)) != (axis == 0)) continue;   // the projector's dominant axis
+                const double ra = axis ? ry : rx, rb = axis ? rx : ry;
+                const float wb = 1.0f - fabsf((float)((ob + D * rb / ra) / vox + Cb - ib));
+                if (!(wb > 0.0f)) continue;
+                // f_c(av) = Cz + a1 (av - Cv), a1 = D dv / (ra vox)
+                const float a1 = (float)(D * g.dv / (ra * vox)), ia1 = 1.0f / a1;
+                const float sxy = (float)(rx * rx + ry * ry), istep = (float)(vox / fabs(ra));
+                const InT *col = yp + au;
+#pragma unroll
+                for (int z = 0; z < kZC; ++z) {
+                    const float dz = (float)(iz0 + z) - Czf;    // iz - Cz
+                    const float l1 = fmaf(dz - 1.0f, ia1, Cvf), l2 = fmaf(dz + 1.0f, ia1, Cvf);
+                    const int v0 = max((int)ceilf(fminf(l1, l2)), 0), v1 = min((int)floorf(fmaxf(l1, l2)), nv - 1);
+                    float sum = 0.0f;
+                    for (int av = v0; av <= v1; ++av) {
+                        const float dv = (float)av - Cvf;
+                        const float wc = 1.0f - fabsf(fmaf(a1, dv, -dz));
+                        const float vv = dv * dvf;
+                        const float w = fmaxf(wc, 0.0f) * istep * sqrtf(fmaf(vv, vv, sxy));
+                        sum = fmaf(w, to_f(col[(size_t)av * nu]), sum);
+                    }
+                    grp[z] = fmaf(wb, sum, grp[z]);
+                }
+            }
+        }
+        if ((p & 3) == 3 || p == P - 1) {
+#pragma unroll
+            for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
+        }
+    }
+    const double sc = scale ? (double)*scale : 1.0;
+#pragma unroll
+    for (int z = 0; z < kZC; ++z) {
+        const int iz = iz0 + z;
+        if (iz < g.nz) x[((size_t)iz * g.ny + iy) * g.nx + ix] = (float)(acc[z] * sc);
+    }
+}
+
 // --------------------------------------------------------------- B_un
-constexpr int kZC = 16;   // z voxels per work-item in the cone back-projector
 
 // ------------------------------------------- line-intersection projector
 // A_ij = length of ray i inside voxel j (the forward model the paper uses,
@@ -1675,6 +1779,18 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
     return CT_OK;
 }
 
+int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, float *x, const float *scale,
+                            const int *stop, hipStream_t s) {
+    ProfScope prof(PROF_AT, s);
+    dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC), block(16, 16);
+    if (y_dtype == CT_F32)
+        hipLaunchKernelGGL((k_project_T_gather<float>), grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
+    else
+        hipLaunchKernelGGL((k_project_T_gather<__half>), grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
+    CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
 int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx, float *vy,
                      const int *stop, hipStream_t s) {
     ProfScope prof(PROF_AT, s);
@@ -1938,8 +2054,10 @@ int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *
         CT_TRY(launch_fill(x, g->n_vox, 0.0f, s));
         return launch_siddon_T(g, y, y_dtype, x, in_scale, stop, s);
     }
-    // A^T: scatter into zeroed padded copies, then fold back.  The scatter
-    // also writes border cells, so a following A must re-zero the border.
+    if (g->k.kind == CT_CONE_CIRCULAR_3D) return launch_project_T_gather(g, y, y_dtype, x, in_scale, stop, s);
+    // 2D A^T: scatter into zeroed padded copies, then fold back.  The
+    // scatter also writes border cells, so a following A must re-zero the
+    // border.
     CT_TRY(launch_fill(sc.vx, g->pad.nvx, 0.0f, s));
     CT_TRY(launch_fill(sc.vy, g->pad.nvy, 0.0f, s));
     CT_TRY(launch_project_T(g, y, y_dtype, sc.vx, sc.vy, stop, s));
