@@ -56,6 +56,15 @@ inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a
 
 // ---------------------------------------------------------- kernel geometry
 // Plain-old-data copy of the geometry passed by value to kernels.
+// Per (view, detector column) quantities of a cone-beam ray that do not
+// depend on the detector row, for the voxel-driven transpose: the in-plane
+// slope t = r_b / r_a along the dominant axis a, dv / (r_a vox), the step
+// factor vox / |r_a| (negative for y-dominant columns) and r_x^2 + r_y^2.
+struct ColT {
+    double t;
+    float ar, is, sxy, pad;
+};
+
 struct GeomK {
     int kind;          // 0 = 2D parallel, 1 = 3D cone
     int proj;          // CT_JOSEPH or CT_SIDDON
@@ -65,6 +74,8 @@ struct GeomK {
     const double *cs;  // device: cos, sin per view (2*P)
     const float *cs32; // device: the same table rounded to FP32
     const int *axis;   // device: per-view dominant axis for 2D (0 = x, 1 = y)
+    const ColT *colT;  // device: per (view, column) table of cone-beam rays, P x nu
+    const int *vdom;   // device: per view, bit 0 / bit 1 set if any column is x- / y-dominant
 };
 
 // Padded, axis-permuted volume copies read by the forward projector and
@@ -103,6 +114,8 @@ struct ct_geometry {
     std::vector<int> h_axis;       // 2D dominant axis per view
     double *d_cs = nullptr;
     float *d_cs32 = nullptr;
+    ct::ColT *d_colT = nullptr;
+    int *d_vdom = nullptr;
     int *d_axis = nullptr;
     float *d_ramp = nullptr;       // du * h[j], j = 0..nu-1 (FP32)
     size_t n_vox = 0, n_rays = 0;
@@ -142,6 +155,8 @@ int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy,
                     const int *stop, hipStream_t s);
 int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y,
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
+// fills g->d_colT (cone geometries) from the kernel view; synchronous
+int launch_col_table(ct_geometry *g);
 int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx,
                      float *vy, const int *stop, hipStream_t s);
 // cone-beam A^T gathered per voxel straight into x (times *scale if given)

@@ -238,7 +238,24 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     k.cs = g->d_cs;
     k.cs32 = g->d_cs32;
     k.axis = g->d_axis;
+    k.colT = nullptr;
+    k.vdom = nullptr;
     g->pad = pad_layout(k);
+    if (d.kind == CT_CONE_CIRCULAR_3D) {
+        if (hipMalloc(&g->d_colT, sizeof(ColT) * (size_t)P * d.nu) != hipSuccess ||
+            hipMalloc(&g->d_vdom, sizeof(int) * (size_t)P) != hipSuccess) {
+            ct_geometry_destroy(g);
+            set_error("ct_geometry_create: hipMalloc failed");
+            return CT_ERR_ALLOC;
+        }
+        k.colT = g->d_colT;
+        k.vdom = g->d_vdom;
+        const int st = launch_col_table(g);
+        if (st != CT_OK) {
+            ct_geometry_destroy(g);
+            return st;
+        }
+    }
     *out = g;
     return CT_OK;
 }
@@ -247,6 +264,8 @@ extern "C" void ct_geometry_destroy(ct_geometry *g) {
     if (!g) return;
     if (g->d_cs) (void)hipFree(g->d_cs);
     if (g->d_cs32) (void)hipFree(g->d_cs32);
+    if (g->d_colT) (void)hipFree(g->d_colT);
+    if (g->d_vdom) (void)hipFree(g->d_vdom);
     if (g->d_axis) (void)hipFree(g->d_axis);
     if (g->d_ramp) (void)hipFree(g->d_ramp);
     delete g;

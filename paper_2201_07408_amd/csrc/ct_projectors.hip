@@ -710,6 +710,35 @@ __global__ __launch_bounds__(256) void k_project_T(GeomK g, PadLayout L, const I
 
 constexpr int kZC = 16;   // z voxels per work-item in the voxel-driven cone kernels
 
+// Per (view, column) ray table of a cone geometry (ColT), from the same
+// direction helper as the projector, so the dominant axis matches bit for
+// bit.
+__global__ void k_col_table(GeomK g, ColT *__restrict__ T) {
+    const int au = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y;
+    if (au >= g.nu) return;
+    const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+    double rx, ry;
+    cone_ray_xy(g, c, s, au, rx, ry);
+    const bool xdom = fabs(rx) >= fabs(ry);
+    const double ra = xdom ? rx : ry, rb = xdom ? ry : rx;
+    ColT e;
+    e.t = rb / ra;
+    e.ar = (float)(g.dv / (ra * g.vox));
+    e.is = (float)((xdom ? 1.0 : -1.0) * g.vox / fabs(ra));
+    e.sxy = (float)(rx * rx + ry * ry);
+    e.pad = 0.0f;
+    T[(size_t)p * g.nu + au] = e;
+}
+
+// Per view: which dominant axes occur among its columns.
+__global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict__ vdom) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.P) return;
+    int f = 0;
+    for (int au = 0; au < g.nu; ++au) f |= T[(size_t)p * g.nu + au].is > 0.0f ? 1 : 2;
+    vdom[p] = f;
+}
+
 // Exact transpose of the cone-beam Joseph projector, gathered per voxel
 // instead of scattered per sample.  Voxel (ix, iy, iz) receives, from every
 // ray that samples its plane (x = ix for x-dominant rays, y = iy for
@@ -721,41 +750,53 @@ constexpr int kZC = 16;   // z voxels per work-item in the voxel-driven cone ker
 // source along the dominant axis and t = r_b / r_a a linear-fractional
 // function of u; inverting it at f_b = i_b -+ 1 gives the few candidate
 // columns (all columns where the inverse interval wraps through infinity),
-// each of which is tested exactly, dominant axis included.  Its c
-// coordinate is linear in the detector row, which gives the rows per voxel.
-// Views are summed in FP32 in groups of four and added to FP64, as in B_un;
-// no atomics, so the result is deterministic.
+// each of which is tested exactly with the projector's dominant axis from
+// the column table.  Its c coordinate is linear in the detector row: each
+// row of a candidate column feeds the two voxels of the work-item's z
+// chunk around its f_c, accumulated in per-work-item LDS slots.  Views are
+// summed in FP32 in groups of four and added to FP64, as in B_un; no
+// atomics, so the result is deterministic.
+constexpr int kATS = kZC + 1;   // LDS slots per work-item (odd stride across banks)
+
 template <typename InT>
 __global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ stop) {
     if (stop && *stop) return;
+    __shared__ float s_acc[256 * kATS];
+    const int tid = threadIdx.y * 16 + threadIdx.x;
     const int ix = blockIdx.x * 16 + threadIdx.x, iy = blockIdx.y * 16 + threadIdx.y, iz0 = blockIdx.z * kZC;
-    if (ix >= g.nx || iy >= g.ny) return;   // no barriers below
+    if (ix >= g.nx || iy >= g.ny) return;   // no barriers below: the slots are private
+    float *slot = s_acc + tid * kATS;
+#pragma unroll
+    for (int z = 0; z < kZC; ++z) slot[z] = 0.0f;
     const int nu = g.nu, nv = g.nv, P = g.P;
-    const double vox = g.vox;
+    const double vox = g.vox, ivox = 1.0 / vox;
     const double Cx = 0.5 * (g.nx - 1), Cy = 0.5 * (g.ny - 1), Cu = 0.5 * (nu - 1);
-    const float Czf = (float)(0.5 * (g.nz - 1)), Cvf = (float)(0.5 * (nv - 1)), dvf = (float)g.dv;
+    const float Cvf = (float)(0.5 * (nv - 1)), dvf = (float)g.dv;
+    const float zoff = (float)(0.5 * (g.nz - 1) - iz0);   // f_c - iz0 = zoff + a1 (av - Cv)
     const double xc = (ix - Cx) * vox, yc = (iy - Cy) * vox;
     double acc[kZC];
-    float grp[kZC];
 #pragma unroll
-    for (int z = 0; z < kZC; ++z) { acc[z] = 0.0; grp[z] = 0.0f; }
+    for (int z = 0; z < kZC; ++z) acc[z] = 0.0;
     for (int p = 0; p < P; ++p) {
         const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
         const double ox = g.sod * c, oy = g.sod * s;
         const InT *yp = y + (size_t)p * nv * nu;
+        const ColT *Tp = g.colT + (size_t)p * nu;
+        const int vd = g.vdom[p];
 #pragma unroll 1
         for (int axis = 0; axis < 2; ++axis) {
+            if (!(vd & (1 << axis))) continue;   // no column of this view has this dominant axis
             // axis 0: x-dominant rays on the plane x = xc (b = y); axis 1:
             // y-dominant rays on the plane y = yc (b = x)
             const double D = axis ? yc - oy : xc - ox;
-            const double ob = axis ? ox : oy, Cb = axis ? Cx : Cy;
             const int ib = axis ? ix : iy;
-            // t(u) = (al u + be) / (ga u + de)
+            const double e0 = (axis ? ox : oy) - (ib - (axis ? Cx : Cy)) * vox;   // f_b - ib = (e0 + D t) / vox
+            // t(u) = (al u + be) / (ga u + de), inverted at f_b - ib = -+1
             const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
             const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
-            const double tm = ((ib - 1 - Cb) * vox - ob) / D, tp = ((ib + 1 - Cb) * vox - ob) / D;
+            const double iD = 1.0 / D, tm = (-vox - e0) * iD, tp = (vox - e0) * iD;
             const double dm = ga * tm - al, dp = ga * tp - al;
             int a_lo = 0, a_hi = nu - 1;
             if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
@@ -765,37 +806,34 @@ __global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__
                 a_hi = ahi < (double)nu ? min((int)ceil(ahi), nu - 1) : nu - 1;
                 if (alo >= (double)nu || ahi <= -1.0) a_hi = -1;   // interval off the detector
             }
+            const float Df = (float)D;
             for (int au = a_lo; au <= a_hi; ++au) {
-                double rx, ry;
-                cone_ray_xy(g, c, s, au, rx, ry);
-                if ((fabs(rx) >= fabs(ry)) != (axis == 0)) continue;   // the projector's dominant axis
-                const double ra = axis ? ry : rx, rb = axis ? rx : ry;
-                const float wb = 1.0f - fabsf((float)((ob + D * rb / ra) / vox + Cb - ib));
+                const ColT T = Tp[au];
+                if ((T.is > 0.0f) != (axis == 0)) continue;   // the projector's dominant axis
+                const float wb = 1.0f - fabsf((float)((e0 + D * T.t) * ivox));
                 if (!(wb > 0.0f)) continue;
-                // f_c(av) = Cz + a1 (av - Cv), a1 = D dv / (ra vox)
-                const float a1 = (float)(D * g.dv / (ra * vox)), ia1 = 1.0f / a1;
-                const float sxy = (float)(rx * rx + ry * ry), istep = (float)(vox / fabs(ra));
+                // f_c(av) - iz0 = zoff + a1 (av - Cv): rows feeding the chunk
+                // [iz0 - 1, iz0 + kZC]
+                const float a1 = Df * T.ar, ia1 = 1.0f / a1;
+                const float r1 = fmaf(-1.0f - zoff, ia1, Cvf), r2 = fmaf((float)kZC - zoff, ia1, Cvf);
+                const int v0 = max((int)ceilf(fminf(r1, r2)), 0), v1 = min((int)floorf(fmaxf(r1, r2)), nv - 1);
+                const float wis = wb * fabsf(T.is);
                 const InT *col = yp + au;
-#pragma unroll
-                for (int z = 0; z < kZC; ++z) {
-                    const float dz = (float)(iz0 + z) - Czf;    // iz - Cz
-                    const float l1 = fmaf(dz - 1.0f, ia1, Cvf), l2 = fmaf(dz + 1.0f, ia1, Cvf);
-                    const int v0 = max((int)ceilf(fminf(l1, l2)), 0), v1 = min((int)floorf(fmaxf(l1, l2)), nv - 1);
-                    float sum = 0.0f;
-                    for (int av = v0; av <= v1; ++av) {
-                        const float dv = (float)av - Cvf;
-                        const float wc = 1.0f - fabsf(fmaf(a1, dv, -dz));
-                        const float vv = dv * dvf;
-                        const float w = fmaxf(wc, 0.0f) * istep * sqrtf(fmaf(vv, vv, sxy));
-                        sum = fmaf(w, to_f(col[(size_t)av * nu]), sum);
-                    }
-                    grp[z] = fmaf(wb, sum, grp[z]);
+                for (int av = v0; av <= v1; ++av) {
+                    const float dv = (float)av - Cvf;
+                    const float zf = fmaf(a1, dv, zoff);
+                    const float zl = floorf(zf), w1 = zf - zl;
+                    const int zi = (int)zl;
+                    const float vv = dv * dvf;
+                    const float val = wis * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(col[(size_t)av * nu]);
+                    if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
+                    if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
                 }
             }
         }
         if ((p & 3) == 3 || p == P - 1) {
 #pragma unroll
-            for (int z = 0; z < kZC; ++z) { acc[z] += (double)grp[z]; grp[z] = 0.0f; }
+            for (int z = 0; z < kZC; ++z) { acc[z] += (double)slot[z]; slot[z] = 0.0f; }
         }
     }
     const double sc = scale ? (double)*scale : 1.0;
@@ -1776,6 +1814,19 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
         else hipLaunchKernelGGL((k_project<false, __half>), grid, block, 0, s, g->k, g->pad, vx, offy, (__half *)y, out_scale, stop);
     }
     CT_LAUNCH_CHECK();
+    return CT_OK;
+}
+
+int launch_col_table(ct_geometry *g) {
+    dim3 grid((g->k.nu + 255) / 256, g->k.P), block(256);
+    hipLaunchKernelGGL(k_col_table, grid, block, 0, 0, g->k, g->d_colT);
+    CT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_view_dom, dim3((g->k.P + 255) / 256), dim3(256), 0, 0, g->k, g->d_colT, g->d_vdom);
+    CT_LAUNCH_CHECK();
+    if (hipStreamSynchronize(0) != hipSuccess) {
+        set_error("ct_geometry_create: column table kernel failed");
+        return CT_ERR_HIP;
+    }
     return CT_OK;
 }
 
