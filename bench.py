@@ -390,6 +390,20 @@ def main():
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
     }
+    # the matched transpose (CGLS with A^T, autograd backward), outside the
+    # timed solves: three launches on the same data
+    log("bench: matched transpose")
+    yat = ct.ct_project_A(g, torch.ones(desc.vol_shape, device=b.device))
+    xat = ct.ct_backproject_AT(g, yat)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        xat = ct.ct_backproject_AT(g, yat, out=xat)
+    e1.record()
+    torch.cuda.synchronize()
+    line["AT_ms_per_launch"] = e0.elapsed_time(e1) / 3
+    del yat, xat
     if not args.no_monitor:
         log("bench: monitored solves")
         line["monitor"] = bench_monitor(ct, torch, b, x_phantom, ms_per_step)

@@ -825,7 +825,7 @@ __global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__
                     const float zl = floorf(zf), w1 = zf - zl;
                     const int zi = (int)zl;
                     const float vv = dv * dvf;
-                    const float val = wis * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(col[(size_t)av * nu]);
+                    const float val = wis * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(col[av * nu]);
                     if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
                     if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
                 }
