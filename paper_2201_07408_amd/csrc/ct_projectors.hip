@@ -756,9 +756,32 @@ __global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict_
 // chunk around its f_c, accumulated in per-work-item LDS slots.  Views are
 // summed in FP32 in groups of four and added to FP64, as in B_un; no
 // atomics, so the result is deterministic.
+// SID: the transpose of the line-intersection model instead.  The weight of
+// a voxel is then the fraction of the ray's slab (plane coordinate ix -+ 1/2,
+// or iy -+ 1/2) spent inside it: with the slab parameter s in [0, 1], the
+// ray is inside the voxel's b range on one interval of s and inside its c
+// range on another (the coordinates are linear in s), and the weight is the
+// length of their intersection.  Such rays have |f_b - i_b| < 1 and
+// |f_c - iz| < 1 at the plane, so the candidates are the same.
 constexpr int kATS = kZC + 1;   // LDS slots per work-item (odd stride across banks)
 
-template <typename InT>
+// The s in [0, 1] on which lo <= d + (s - 1/2) g < lo + 1: the slab
+// parameters where a coordinate with centre offset d and slope g per slab
+// lies in one voxel (lo = -1/2 for the voxel at offset 0).
+__device__ __forceinline__ void slab_interval(float d, float g, float &s0, float &s1) {
+    if (g == 0.0f) {
+        const bool in = d >= -0.5f && d < 0.5f;
+        s0 = in ? 0.0f : 1.0f;
+        s1 = in ? 1.0f : 0.0f;
+        return;
+    }
+    const float ig = 1.0f / g;
+    const float a = fmaf(-0.5f - d, ig, 0.5f), b = fmaf(0.5f - d, ig, 0.5f);
+    s0 = fmaxf(fminf(a, b), 0.0f);
+    s1 = fminf(fmaxf(a, b), 1.0f);
+}
+
+template <typename InT, bool SID>
 __global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ stop) {
@@ -810,7 +833,14 @@ __global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__
             for (int au = a_lo; au <= a_hi; ++au) {
                 const ColT T = Tp[au];
                 if ((T.is > 0.0f) != (axis == 0)) continue;   // the projector's dominant axis
-                const float wb = 1.0f - fabsf((float)((e0 + D * T.t) * ivox));
+                const float db = (float)((e0 + D * T.t) * ivox);   // f_b - ib at the plane
+                float wb, lb = 0.0f, hb = 0.0f;
+                if (SID) {
+                    slab_interval(db, (float)T.t, lb, hb);   // slab part inside the voxel's b range
+                    wb = hb > lb ? 1.0f : 0.0f;
+                } else {
+                    wb = 1.0f - fabsf(db);
+                }
                 if (!(wb > 0.0f)) continue;
                 // f_c(av) - iz0 = zoff + a1 (av - Cv): rows feeding the chunk
                 // [iz0 - 1, iz0 + kZC]
@@ -826,8 +856,22 @@ __global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__
                     const int zi = (int)zl;
                     const float vv = dv * dvf;
                     const float val = wis * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(col[av * nu]);
-                    if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
-                    if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
+                    if (SID) {
+                        // c slope per slab r_z / r_a; the slab's c range covers
+                        // voxels floor(zf + 1/2 -+ gc / 2) of the chunk
+                        const float gc = T.ar * (float)vox * dv;
+                        const float c0 = fmaf(-0.5f, gc, zf + 0.5f), c1 = fmaf(0.5f, gc, zf + 0.5f);
+                        const float k0f = floorf(c0), k1f = floorf(c1);
+                        const float sc = k0f == k1f ? 1.0f : (fmaxf(k0f, k1f) - c0) / gc;
+                        const float f0 = fmaxf(fminf(sc, hb) - lb, 0.0f);
+                        const float f1 = k0f == k1f ? 0.0f : fmaxf(hb - fmaxf(sc, lb), 0.0f);
+                        const int k0 = (int)k0f, k1 = (int)k1f;
+                        if ((unsigned)k0 < (unsigned)kZC) slot[k0] = fmaf(f0, val, slot[k0]);
+                        if ((unsigned)k1 < (unsigned)kZC && k1 != k0) slot[k1] = fmaf(f1, val, slot[k1]);
+                    } else {
+                        if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
+                        if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
+                    }
                 }
             }
         }
@@ -1834,10 +1878,17 @@ int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, fl
                             const int *stop, hipStream_t s) {
     ProfScope prof(PROF_AT, s);
     dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC), block(16, 16);
-    if (y_dtype == CT_F32)
-        hipLaunchKernelGGL((k_project_T_gather<float>), grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
-    else
-        hipLaunchKernelGGL((k_project_T_gather<__half>), grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
+    if (g->k.proj == CT_SIDDON) {
+        if (y_dtype == CT_F32)
+            hipLaunchKernelGGL((k_project_T_gather<float, true>), grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
+        else
+            hipLaunchKernelGGL((k_project_T_gather<__half, true>), grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
+    } else {
+        if (y_dtype == CT_F32)
+            hipLaunchKernelGGL((k_project_T_gather<float, false>), grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
+        else
+            hipLaunchKernelGGL((k_project_T_gather<__half, false>), grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
+    }
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
@@ -2100,12 +2151,12 @@ int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *
         CT_TRY(launch_ramp(g, y, y_dtype, sc.filt, y_dtype, (size_t)g->k.P * g->k.nv, stop, s));
         return launch_backproject(g, sc.filt, y_dtype, x, in_scale, stop, s);
     }
+    if (g->k.kind == CT_CONE_CIRCULAR_3D) return launch_project_T_gather(g, y, y_dtype, x, in_scale, stop, s);
     if (g->k.proj == CT_SIDDON) {
-        // the line-intersection transpose scatters straight into x
+        // the 2D line-intersection transpose scatters straight into x
         CT_TRY(launch_fill(x, g->n_vox, 0.0f, s));
         return launch_siddon_T(g, y, y_dtype, x, in_scale, stop, s);
     }
-    if (g->k.kind == CT_CONE_CIRCULAR_3D) return launch_project_T_gather(g, y, y_dtype, x, in_scale, stop, s);
     // 2D A^T: scatter into zeroed padded copies, then fold back.  The
     // scatter also writes border cells, so a following A must re-zero the
     // border.
