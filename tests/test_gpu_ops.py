@@ -91,7 +91,7 @@ def test_ramp_row_lengths(nu):
     assert rel(host(ct.ct_ramp_filter(g, dev(y))), oracle.ramp(desc, y)) <= TOL
 
 
-@pytest.mark.parametrize("name", ["w1_2d_64", "cone_24"])
+@pytest.mark.parametrize("name", ["w1_2d_64", "cone_24", "ragged_cone"])
 def test_fp16_storage(geoms, name):
     desc, g = geoms[name]
     say("FP16 storage", name)
@@ -103,6 +103,8 @@ def test_fp16_storage(geoms, name):
     xb = host(ct.ct_backproject_B(g, y16))
     ref_b = oracle.backproject_Bun(desc, host(y16))   # same FP16-rounded data
     assert rel(xb, ref_b) <= TOL
+    xt = host(ct.ct_backproject_AT(g, y16))
+    assert rel(xt, oracle.backproject_AT(desc, host(y16))) <= TOL
 
 
 def test_batch_equals_single_calls(geoms):
