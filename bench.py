@@ -209,6 +209,43 @@ def bench_monitor(ct, torch, b, x_phantom, plain_ms):
     return out
 
 
+def bench_basis16(ct, torch, lib, g, b, x_phantom, x32):
+    """The Krylov basis stored in FP16 on the headline workload: the full
+    30-iteration solve (time, orthogonalisation time, distance from the
+    FP32-basis iterate, image RMSE) and restarted BA-GMRES(10) x 3 cycles
+    with FP16 and FP32 bases (image RMSE, basis bytes)."""
+    import ctypes as C
+    x_ref = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
+    rmse = lambda x: float(torch.sqrt(torch.mean((x.double() - x_ref.double()) ** 2)))
+    n = x_ref.numel()
+    out = {"basis_bytes_full_fp32": 4 * n * (ITERS + 1), "basis_bytes_full_fp16": 2 * n * (ITERS + 1),
+           "basis_bytes_restart10_fp16": 2 * n * 11}
+    ct.ct_ba_gmres(g, b, ITERS, B="ramp", basis_dtype=torch.float16)
+    torch.cuda.synchronize()
+    lib.ct_profile_reset()
+    lib.ct_profile_enable(1)
+    t0 = time.perf_counter()
+    r = ct.ct_ba_gmres(g, b, ITERS, B="ramp", basis_dtype=torch.float16)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lib.ct_profile_enable(0)
+    n_l, t_l = C.c_long(), C.c_double()
+    lib.ct_profile_read(b"CGS", C.byref(n_l), C.byref(t_l))
+    out["full_fp16"] = {"iters_per_s": r.iters_done / dt, "CGS_ms_per_iteration": t_l.value / max(r.iters_done, 1),
+                        "rel_diff_vs_fp32_basis": float(torch.linalg.vector_norm(r.x - x32) /
+                                                        torch.linalg.vector_norm(x32)),
+                        "image_rmse": rmse(r.x), "image_rmse_fp32_basis": rmse(x32),
+                        "residual_at_30": r.res[-1], "residual_at_0": r.res[0]}
+    for name, bd in (("restart10x3_fp16", torch.float16), ("restart10x3_fp32", torch.float32)):
+        ct.ct_ba_gmres_restarted(g, b, 10, 3, B="ramp", basis_dtype=bd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rr = ct.ct_ba_gmres_restarted(g, b, 10, 3, B="ramp", basis_dtype=bd)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_solve": (time.perf_counter() - t0) * 1e3, "image_rmse": rmse(rr.x)}
+    return out
+
+
 def bench_paper_scale(ct, torch, lib):
     """BA-GMRES (B = B_un F) at the paper's data size: 1024 x 1024 x 300
     volume, 180 views of a 1088 x 896 detector (synthetic geometry, see
@@ -305,6 +342,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-siddon", action="store_true")
     ap.add_argument("--no-monitor", action="store_true")
+    ap.add_argument("--no-basis16", action="store_true")
     ap.add_argument("--paper-scale", action="store_true",
                     help="also solve at the paper's data size (1024x1024x300, 180 x 1088x896)")
     args = ap.parse_args()
@@ -407,6 +445,9 @@ def main():
     if not args.no_monitor:
         log("bench: monitored solves")
         line["monitor"] = bench_monitor(ct, torch, b, x_phantom, ms_per_step)
+    if not args.no_basis16 and sdt == torch.float32:
+        log("bench: FP16 Krylov basis")
+        line["basis_fp16"] = bench_basis16(ct, torch, lib, g, b, x_phantom, r.x.clone())
     if not args.no_siddon:
         log("bench: line-intersection forward model")
         line["siddon_A"] = bench_siddon(ct, torch, lib)

@@ -114,6 +114,19 @@ typedef struct {
     double breakdown_tol;     /* GMRES: stop when the new vector's norm after
                                  orthogonalisation is <= tol times its norm
                                  before; 0 -> 64 * 2^-24                    */
+    int basis_dtype;          /* BA-GMRES (plain and restarted): CT_F32, or
+                                 CT_F16 storage of the Krylov basis, whose
+                                 size is the method's memory burden (Sec. II).
+                                 Each new vector v is stored as FP16 of t v,
+                                 t a power of two with t ||v|| in
+                                 (sqrt(len)/2, sqrt(len)] (values near 1, no
+                                 overflow); orthogonalisation, dots and
+                                 norms stay FP32/FP64, and the rounding to
+                                 FP16 applies to the FP32 vector.  Halves the
+                                 basis memory and the orthogonalisation
+                                 traffic.  CT_ERR_UNSUPPORTED for the other
+                                 solvers and with the 2D line-intersection
+                                 projector.  0 (= CT_F32) keeps FP32.       */
 } ct_solver_opts;
 
 /* Validate the descriptor, build per-view tables (FP64 cos/sin, 2D

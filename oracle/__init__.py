@@ -251,19 +251,49 @@ class GmresResult:
     coeff: Optional[np.ndarray] = None  # y with x = W^T y (BA) / x = B W^T y (AB)
 
 
+def _round16(v: np.ndarray) -> np.ndarray:
+    """Values of v as stored in FP16: rounded to FP32 first (the precision
+    the stored vector is computed in), then to the nearest FP16 (ties to
+    even), returned as FP64."""
+    return np.asarray(v, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def _pow2_below(norm: float, n: int) -> float:
+    """The power of two t with t * norm in (sqrt(n)/2, sqrt(n)]."""
+    return float(2.0 ** math.floor(math.log2(math.sqrt(n) / norm)))
+
+
 def gmres(apply_S: Callable[[np.ndarray], np.ndarray], r0: np.ndarray, iters: int,
-          tau: float = 64 * EPS64, keep_basis: bool = False):
+          tau: float = 64 * EPS64, keep_basis: bool = False, basis: str = "f64"):
     """GMRES with x0 = 0 on S x = r0.  Returns (coeff, W, res, iters_done, R).
 
     Breakdown: the step stops after column k when the new vector's norm
-    after orthogonalisation is at most tau times its norm before."""
+    after orthogonalisation is at most tau times its norm before.
+
+    basis = "f16": the basis is kept as FP16 values (a storage choice of this
+    implementation, not of the paper).  The first vector is stored as
+    FP16(t0 r0) with t0 the power of two that puts t0 ||r0|| in
+    (sqrt(n)/2, sqrt(n)]; each later vector as FP16(t z2), z2 the vector
+    after both Gram-Schmidt passes and t chosen from the norm of the vector
+    after the first pass.  The basis vector used from then on is the stored
+    values divided by t times the unrounded norm, so H and the residual
+    recurrence are those of the unrounded vectors, and the rounding is the
+    only change."""
     r0 = np.asarray(r0, dtype=np.float64)
     beta = float(np.linalg.norm(r0))
     res = [beta]
     if beta == 0.0 or iters <= 0:
         return np.zeros(0), np.zeros((0, r0.size)), res, 0, np.zeros((0, 0))
+    if basis not in ("f64", "f16"):
+        raise ValueError("basis must be 'f64' or 'f16'")
+    f16 = basis == "f16"
+    n = r0.size
     W = np.zeros((iters + 1, r0.size), dtype=np.float64)
-    W[0] = r0 / beta
+    if f16:
+        t0 = _pow2_below(beta, n)
+        W[0] = _round16(t0 * r0) / (t0 * beta)
+    else:
+        W[0] = r0 / beta
     H = np.zeros((iters + 1, iters), dtype=np.float64)
     cs = np.zeros(iters)
     sn = np.zeros(iters)
@@ -277,6 +307,9 @@ def gmres(apply_S: Callable[[np.ndarray], np.ndarray], r0: np.ndarray, iters: in
         # classical Gram-Schmidt, twice
         h1 = Wk @ z
         z = z - Wk.T @ h1
+        if f16:
+            z1n = float(np.linalg.norm(z))
+            t = _pow2_below(z1n, n) if z1n > 0.0 else 1.0
         h2 = Wk @ z
         z = z - Wk.T @ h2
         hnext = float(np.linalg.norm(z))
@@ -298,7 +331,7 @@ def gmres(apply_S: Callable[[np.ndarray], np.ndarray], r0: np.ndarray, iters: in
         done = k + 1
         if hnext <= tau * znorm0:
             break
-        W[k + 1] = z / hnext
+        W[k + 1] = _round16(t * z) / (t * hnext) if f16 else z / hnext
     R = H[:done, :done]
     coeff = np.zeros(done)
     for i in range(done - 1, -1, -1):   # back substitution
@@ -307,12 +340,12 @@ def gmres(apply_S: Callable[[np.ndarray], np.ndarray], r0: np.ndarray, iters: in
 
 
 def ba_gmres(g, b, iters: int, B: str = "un", tau: float = 64 * EPS64,
-             keep_basis: bool = False) -> GmresResult:
+             keep_basis: bool = False, basis: str = "f64") -> GmresResult:
     """BA-GMRES (Eq. 5): GMRES on B A x = B b; x_k = W_k y_k."""
     g = _geom(g)
     Bop = back_projector(g, B)
     r0 = Bop(_f64(b).reshape(-1))
-    coeff, W, res, k, R = gmres(lambda v: Bop(project_A(g, v)), r0, iters, tau)
+    coeff, W, res, k, R = gmres(lambda v: Bop(project_A(g, v)), r0, iters, tau, basis=basis)
     x = W.T @ coeff if k > 0 else np.zeros(g.n)
     return GmresResult(x, res, k, W if keep_basis else None, R, coeff)
 
@@ -366,7 +399,7 @@ def cgls(g, b, iters: int, B: str = "AT") -> CglsResult:
     return CglsResult(x, res, done)
 
 
-def ba_gmres_restarted(g, b, m: int, cycles: int, B: str = "un"):
+def ba_gmres_restarted(g, b, m: int, cycles: int, B: str = "un", basis: str = "f64"):
     """Restarted BA-GMRES(m): each cycle runs m steps of BA-GMRES on the
     data residual of the current iterate and adds the correction
     (x <- x + d, d from K_m(BA, B(b - A x))).  Returns (x, list of the
@@ -377,7 +410,7 @@ def ba_gmres_restarted(g, b, m: int, cycles: int, B: str = "un"):
     hist = []
     for _ in range(cycles):
         r = b - np.asarray(project_A(g, x.reshape(g.vol_shape))).reshape(-1)
-        res = ba_gmres(g, r, m, B=B)
+        res = ba_gmres(g, r, m, B=B, basis=basis)
         x = x + np.asarray(res.x).reshape(-1)
         hist.append(list(res.res))
     return x, hist

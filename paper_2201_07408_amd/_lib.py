@@ -47,6 +47,7 @@ class SolverOpts(ctypes.Structure):
         ("B", ctypes.c_int),
         ("sino_dtype", ctypes.c_int),
         ("breakdown_tol", ctypes.c_double),
+        ("basis_dtype", ctypes.c_int),
     ]
 
 

@@ -196,12 +196,13 @@ class SolveResult:
 
 
 def _solve(fn_name: str, solver: int, g: Geometry, b: torch.Tensor, iters: int, B: str,
-           sino_dtype, breakdown_tol: float, out: Optional[torch.Tensor]) -> SolveResult:
+           sino_dtype, breakdown_tol: float, out: Optional[torch.Tensor],
+           basis_dtype=torch.float32) -> SolveResult:
     _need_device(b, "b", torch.float32)
     if b.numel() != g.n_rays:
         raise ValueError("b must have %d elements" % g.n_rays)
     lib = L.load()
-    opts = L.SolverOpts(int(iters), _B[B], _DT[sino_dtype], float(breakdown_tol))
+    opts = L.SolverOpts(int(iters), _B[B], _DT[sino_dtype], float(breakdown_tol), _DT[basis_dtype])
     n = ctypes.c_size_t()
     _check(lib.ct_solver_workspace_bytes(g.handle, solver, ctypes.byref(opts), ctypes.byref(n)),
            "ct_solver_workspace_bytes")
@@ -218,9 +219,11 @@ def _solve(fn_name: str, solver: int, g: Geometry, b: torch.Tensor, iters: int, 
 
 
 def ct_ba_gmres(g: Geometry, b: torch.Tensor, iters: int, B: str = "un", sino_dtype=torch.float32,
-                breakdown_tol: float = 0.0, out: Optional[torch.Tensor] = None) -> SolveResult:
-    """BA-GMRES (Eq. 5): GMRES on B A x = B b, x0 = 0."""
-    return _solve("ct_ba_gmres", L.CT_SOLVER_BA, g, b, iters, B, sino_dtype, breakdown_tol, out)
+                breakdown_tol: float = 0.0, out: Optional[torch.Tensor] = None,
+                basis_dtype=torch.float32) -> SolveResult:
+    """BA-GMRES (Eq. 5): GMRES on B A x = B b, x0 = 0.  basis_dtype =
+    torch.float16 stores the Krylov basis in FP16 (power-of-two scaled)."""
+    return _solve("ct_ba_gmres", L.CT_SOLVER_BA, g, b, iters, B, sino_dtype, breakdown_tol, out, basis_dtype)
 
 
 @dataclass
@@ -231,13 +234,14 @@ class RestartResult:
 
 
 def ct_ba_gmres_restarted(g: Geometry, b: torch.Tensor, m: int, cycles: int, B: str = "un",
-                          breakdown_tol: float = 0.0, out: Optional[torch.Tensor] = None) -> RestartResult:
+                          breakdown_tol: float = 0.0, out: Optional[torch.Tensor] = None,
+                          basis_dtype=torch.float32) -> RestartResult:
     """Restarted BA-GMRES(m): `cycles` cycles of m steps on the data residual."""
     _need_device(b, "b", torch.float32)
     if b.numel() != g.n_rays:
         raise ValueError("b must have %d elements" % g.n_rays)
     lib = L.load()
-    opts = L.SolverOpts(int(m), _B[B], L.CT_F32, float(breakdown_tol))
+    opts = L.SolverOpts(int(m), _B[B], L.CT_F32, float(breakdown_tol), _DT[basis_dtype])
     n = ctypes.c_size_t()
     _check(lib.ct_solver_workspace_bytes(g.handle, L.CT_SOLVER_BA_RESTARTED, ctypes.byref(opts), ctypes.byref(n)),
            "ct_solver_workspace_bytes")

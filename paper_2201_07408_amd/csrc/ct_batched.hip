@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_bmaxpy(const float *__restrict__ W, siz
     const double zs = use_zs ? st.misc[M_ZS] : 1.0;
     double nacc = 0.0;
     const size_t q0 = (size_t)vb * kQ;
-    maxpy_groups<NV>(W + (size_t)vlo * ldw, ldw, cnt, cf, zs, zin, zout, q0, q0 + kQ, 256, nacc);
+    maxpy_groups<NV>(W + (size_t)vlo * ldw, ldw, cnt, cf, zs, zin, zout, 1.0f, q0, q0 + kQ, 256, nacc);
     double acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
@@ -602,6 +602,11 @@ int check_batched(const ct_geometry *const *g, int count, const ct_solver_opts *
     CT_ARG_CHECK(o->sino_dtype == CT_F32 || o->sino_dtype == CT_F16, "ct_ba_gmres_batched: bad sino_dtype");
     if (o->sino_dtype != CT_F32) {
         set_error("ct_ba_gmres_batched: FP16 data storage is not batched");
+        return CT_ERR_UNSUPPORTED;
+    }
+    CT_ARG_CHECK(o->basis_dtype == CT_F32 || o->basis_dtype == CT_F16, "ct_ba_gmres_batched: bad basis_dtype");
+    if (o->basis_dtype != CT_F32) {
+        set_error("ct_ba_gmres_batched: FP16 basis storage is not batched");
         return CT_ERR_UNSUPPORTED;
     }
     CT_ARG_CHECK(o->breakdown_tol >= 0.0 && std::isfinite(o->breakdown_tol), "ct_ba_gmres_batched: bad breakdown_tol");

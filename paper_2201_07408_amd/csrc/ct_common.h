@@ -151,7 +151,7 @@ class ProfScope {
 
 int launch_fill(float *p, size_t n, float v, hipStream_t s);
 int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s);
-int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy,
+int launch_pad_copy(const ct_geometry *g, const void *x, int x_dtype, float *vx, float *vy,
                     const int *stop, hipStream_t s);
 int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y,
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
@@ -223,8 +223,10 @@ int launch_bramp(const BSlice *sl, int count, const int *pfx, int nblk, int max_
                  hipStream_t s);
 
 // y = A x.  Padding of vx/vy must already be zero (pad_ready) or is zeroed here.
-int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratch &sc,
-            bool pad_ready, const float *out_scale, const int *stop, hipStream_t s);
+// x is FP32, or FP16 (x_dtype) where A reads the padded copies (not the 2D
+// line-intersection projector).
+int apply_A(const ct_geometry *g, const void *x, void *y, int y_dtype, OpScratch &sc,
+            bool pad_ready, const float *out_scale, const int *stop, hipStream_t s, int x_dtype = CT_F32);
 // x = B y with B in {B_un, B_un F, A^T}.
 int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *x,
             OpScratch &sc, const float *in_scale, const int *stop, hipStream_t s);

@@ -22,6 +22,7 @@
 // (deterministic, no float atomics) before running the scalar step.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "ct_krylov_dev.h"
 
@@ -41,15 +42,15 @@ constexpr int kTile = 256;       // float4 groups per block per grid-stride step
 // Work-items stride over 16-byte groups of four elements (the last partial
 // group goes element by element), every basis vector of the chunk is read
 // once per pass with 16-byte loads, and all sums accumulate in FP64.
-template <int NV>
-__global__ __launch_bounds__(256) void k_mdot(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
+template <int NV, typename WT>
+__global__ __launch_bounds__(256) void k_mdot(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
                                               const float *__restrict__ z, size_t n, int nrm, int ncol,
                                               double *__restrict__ partials, const int *__restrict__ stop) {
     if (stop && *stop) return;
     double acc[NV], nacc = 0.0;
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-    const float *Wc = W + (size_t)vlo * ldw;
+    const WT *Wc = W + (size_t)vlo * ldw;
     const size_t n4 = n / 4;
     mdot_groups<NV>(Wc, ldw, cnt, z, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)   // tail of fewer than four elements
@@ -58,32 +59,36 @@ __global__ __launch_bounds__(256) void k_mdot(const float *__restrict__ W, size_
             nacc += zd * zd;
 #pragma unroll
             for (int j = 0; j < NV; ++j)
-                if (j < cnt) acc[j] += (double)Wc[(size_t)j * ldw + i] * zd;
+                if (j < cnt) acc[j] += (double)ld_elem(Wc + (size_t)j * ldw, i) * zd;
         }
     block_partials<NV>(acc, cnt, nacc, nrm != 0, vlo, ncol, partials, kMaxBlk, blockIdx.x);
 }
 
-template <int NV>
-__global__ __launch_bounds__(256) void k_maxpy(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
-                                               const float *zin, float *zout, size_t n,
+// OT = __half stores the result as FP16 of oscale[0] * z' (the last pass of
+// an FP16-basis CGS2 step writing the new basis vector).
+template <int NV, typename WT, typename OT>
+__global__ __launch_bounds__(256) void k_maxpy(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
+                                               const float *zin, OT *zout, size_t n,
                                                const double *__restrict__ coef, const double *__restrict__ zscale,
-                                               int nrm, int ncol, double *__restrict__ partials,
-                                               const int *__restrict__ stop) {
+                                               const double *__restrict__ oscale, int nrm, int ncol,
+                                               double *__restrict__ partials, const int *__restrict__ stop) {
     if (stop && *stop) return;
     __shared__ double cf[NV];
     for (int j = threadIdx.x; j < cnt; j += 256) cf[j] = coef[vlo + j];
     __syncthreads();
     const double zs = zscale ? *zscale : 1.0;
+    const float os = oscale ? (float)*oscale : 1.0f;
     double nacc = 0.0;
-    const float *Wc = W + (size_t)vlo * ldw;
+    const WT *Wc = W + (size_t)vlo * ldw;
     const size_t n4 = n / 4;
-    maxpy_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, nacc);
+    maxpy_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, os, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
+                     nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (size_t i = n4 * 4; i < n; ++i) {
             double u = zs * (double)zin[i];
-            for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)Wc[(size_t)j * ldw + i];
+            for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)ld_elem(Wc + (size_t)j * ldw, i);
             const float o = (float)u;
-            zout[i] = o;
+            st_elem(zout, i, o, os);
             nacc += (double)o * o;
         }
     double acc[NV];
@@ -95,39 +100,43 @@ __global__ __launch_bounds__(256) void k_maxpy(const float *__restrict__ W, size
 // z' = zs z - sum_j coef[j] W[j] and partial d[j] = W[j] . z' for one chunk
 // in a single sweep (the second pass of CGS2 for the chunk that completes
 // z'; the dots of earlier chunks need the finished z' and take k_mdot).
-template <int NV>
-__global__ __launch_bounds__(256) void k_maxpy_dot(const float *__restrict__ W, size_t ldw, int vlo, int cnt,
+// With an FP16 basis it also sums ||z'||^2 into column ncol.
+template <int NV, typename WT>
+__global__ __launch_bounds__(256) void k_maxpy_dot(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
                                                    const float *zin, float *zout, size_t n,
                                                    const double *__restrict__ coef,
-                                                   const double *__restrict__ zscale, double *__restrict__ partials,
-                                                   const int *__restrict__ stop) {
+                                                   const double *__restrict__ zscale, int ncol,
+                                                   double *__restrict__ partials, const int *__restrict__ stop) {
+    constexpr bool kNrm = std::is_same<WT, __half>::value;
     if (stop && *stop) return;
     __shared__ double cf[NV];
     for (int j = threadIdx.x; j < cnt; j += 256) cf[j] = coef[vlo + j];
     __syncthreads();
     const double zs = zscale ? *zscale : 1.0;
-    double acc[NV];
+    double acc[NV], nacc = 0.0;
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-    const float *Wc = W + (size_t)vlo * ldw;
+    const WT *Wc = W + (size_t)vlo * ldw;
     const size_t n4 = n / 4;
-    maxpy_dot_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc);
+    maxpy_dot_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
+                         acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (size_t i = n4 * 4; i < n; ++i) {
             double u = zs * (double)zin[i];
-            for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)Wc[(size_t)j * ldw + i];
+            for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)ld_elem(Wc + (size_t)j * ldw, i);
             const float o = (float)u;
             zout[i] = o;
+            nacc += (double)o * o;
 #pragma unroll
             for (int j = 0; j < NV; ++j)
-                if (j < cnt) acc[j] += (double)Wc[(size_t)j * ldw + i] * (double)o;
+                if (j < cnt) acc[j] += (double)ld_elem(Wc + (size_t)j * ldw, i) * (double)o;
         }
-    block_partials<NV>(acc, cnt, 0.0, false, vlo, 0, partials, kMaxBlk, blockIdx.x);
+    block_partials<NV>(acc, cnt, nacc, kNrm, vlo, ncol, partials, kMaxBlk, blockIdx.x);
 }
 
-__global__ void k_gmres_init(KState st, int nblk, double qscale_c) {
+__global__ void k_gmres_init(KState st, int nblk, double qscale_c, double blen) {
     __shared__ double d[1];
-    gmres_init(st, nblk, qscale_c, d);
+    gmres_init(st, nblk, qscale_c, d, blen);
 }
 
 __global__ void k_gmres_red1(KState st, int nblk, int k) {
@@ -136,10 +145,10 @@ __global__ void k_gmres_red1(KState st, int nblk, int k) {
     gmres_red1(st, nblk, k, d);
 }
 
-__global__ void k_gmres_red2(KState st, int nblk, int k) {
+__global__ void k_gmres_red2(KState st, int nblk, int k, double blen) {
     extern __shared__ double d[];
     if (st.flags[F_STOP]) return;
-    gmres_red2(st, nblk, k, d);
+    gmres_red2(st, nblk, k, d, blen);
 }
 
 __global__ void k_gmres_red3(KState st, int nblk, int k, double tol, double qscale_c) {
@@ -151,7 +160,8 @@ __global__ void k_gmres_red3(KState st, int nblk, int k, double tol, double qsca
 __global__ void k_gmres_trsv(KState st) { gmres_trsv(st); }
 
 // out = sum_{j < k_done} coef[j] W[j] (or out + that sum), FP64 accumulation
-__global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, size_t ldw, size_t n,
+template <typename WT>
+__global__ __launch_bounds__(256) void k_combine(const WT *__restrict__ W, size_t ldw, size_t n,
                                                  KState st, float *__restrict__ out, int accumulate) {
     __shared__ double cf[kMaxVec + 1];
     const int kd = st.flags[F_KDONE];
@@ -160,7 +170,7 @@ __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ W, si
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         double a = accumulate ? (double)out[i] : 0.0;
-        for (int j = 0; j < kd; ++j) a += cf[j] * (double)W[(size_t)j * ldw + i];
+        for (int j = 0; j < kd; ++j) a += cf[j] * (double)ld_elem(W + (size_t)j * ldw, i);
         out[i] = (float)a;
     }
 }
@@ -375,8 +385,11 @@ struct Carver {
 };
 
 struct GmresBufs {
-    float *W = nullptr;     // (K+1) basis vectors of length len, stride ldw
+    void *W = nullptr;      // (K+1) basis vectors of length len, stride ldw (FP32, or FP16 if w16)
     size_t ldw = 0, len = 0;
+    bool w16 = false;
+    float *wf(int j) const { return (float *)W + (size_t)j * ldw; }
+    __half *wh(int j) const { return (__half *)W + (size_t)j * ldw; }
     OpScratch opA;          // padded copies
     void *q = nullptr;      // projections (BA) / image (AB)
     void *filt = nullptr;   // ramp-filtered data
@@ -396,7 +409,8 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
     const bool ba = solver == CT_SOLVER_BA;
     b.len = ba ? g->n_vox : g->n_rays;
     b.ldw = align_up(b.len, 64);
-    b.W = c.take<float>(b.ldw * (size_t)(K + 1));
+    b.w16 = o.basis_dtype == CT_F16;
+    b.W = b.w16 ? (void *)c.take<__half>(b.ldw * (size_t)(K + 1)) : (void *)c.take<float>(b.ldw * (size_t)(K + 1));
     b.opA.vx = c.take<float>(g->pad.nvx);
     b.opA.vy = c.take<float>(g->pad.nvy);
     const size_t es = o.sino_dtype == CT_F16 ? 2 : 4;
@@ -444,46 +458,61 @@ static int launch_mdot(const GmresBufs &b, int vlo, int cnt, const float *z, boo
     ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
-#define CT_MDOT(NVV) \
-    hipLaunchKernelGGL(k_mdot<NVV>, dim3(nblk), dim3(256), 0, s, b.W, b.ldw, vlo, cnt, z, b.len, (int)nrm, ncol, b.st.partials, stop)
-    if (cnt <= 1) CT_MDOT(1);
-    else if (cnt <= 4) CT_MDOT(4);
-    else if (cnt <= 8) CT_MDOT(8);
-    else CT_MDOT(16);
+#define CT_MDOT(NVV, WT, WP) \
+    hipLaunchKernelGGL((k_mdot<NVV, WT>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, z, b.len, (int)nrm, ncol, \
+                       b.st.partials, stop)
+#define CT_MDOT_NV(WT, WP) \
+    if (cnt <= 1) CT_MDOT(1, WT, WP); \
+    else if (cnt <= 4) CT_MDOT(4, WT, WP); \
+    else if (cnt <= 8) CT_MDOT(8, WT, WP); \
+    else CT_MDOT(16, WT, WP);
+    if (b.w16) { CT_MDOT_NV(__half, b.wh(0)) } else { CT_MDOT_NV(float, b.wf(0)) }
+#undef CT_MDOT_NV
 #undef CT_MDOT
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
 
+// zout16 != nullptr: store the result as FP16 (scale st.misc[M_BT]) there
+// instead of zout.
 static int launch_maxpy(const GmresBufs &b, int vlo, int cnt, const float *zin, float *zout, const double *coef,
-                        const double *zscale, bool nrm, int ncol, hipStream_t s) {
+                        const double *zscale, bool nrm, int ncol, hipStream_t s, __half *zout16 = nullptr) {
     ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
-#define CT_MAXPY(NVV) \
-    hipLaunchKernelGGL(k_maxpy<NVV>, dim3(nblk), dim3(256), 0, s, b.W, b.ldw, vlo, cnt, zin, zout, b.len, coef, zscale, \
-                       (int)nrm, ncol, b.st.partials, stop)
-    if (cnt <= 1) CT_MAXPY(1);
-    else if (cnt <= 4) CT_MAXPY(4);
-    else if (cnt <= 8) CT_MAXPY(8);
-    else CT_MAXPY(16);
+    const double *os = b.st.misc + M_BT;
+#define CT_MAXPY(NVV, WT, OT, WP, ZO) \
+    hipLaunchKernelGGL((k_maxpy<NVV, WT, OT>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, ZO, b.len, \
+                       coef, zscale, os, (int)nrm, ncol, b.st.partials, stop)
+#define CT_MAXPY_NV(WT, OT, WP, ZO) \
+    if (cnt <= 1) CT_MAXPY(1, WT, OT, WP, ZO); \
+    else if (cnt <= 4) CT_MAXPY(4, WT, OT, WP, ZO); \
+    else if (cnt <= 8) CT_MAXPY(8, WT, OT, WP, ZO); \
+    else CT_MAXPY(16, WT, OT, WP, ZO);
+    if (!b.w16) { CT_MAXPY_NV(float, float, b.wf(0), zout) }
+    else if (zout16) { CT_MAXPY_NV(__half, __half, b.wh(0), zout16) }
+    else { CT_MAXPY_NV(__half, float, b.wh(0), zout) }
+#undef CT_MAXPY_NV
 #undef CT_MAXPY
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
 
 static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *zin, float *zout, const double *coef,
-                            const double *zscale, hipStream_t s) {
+                            const double *zscale, int ncol, hipStream_t s) {
     ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
-#define CT_MAXPY_DOT(NVV) \
-    hipLaunchKernelGGL(k_maxpy_dot<NVV>, dim3(nblk), dim3(256), 0, s, b.W, b.ldw, vlo, cnt, zin, zout, b.len, coef, \
-                       zscale, b.st.partials, stop)
-    if (cnt <= 1) CT_MAXPY_DOT(1);
-    else if (cnt <= 4) CT_MAXPY_DOT(4);
-    else if (cnt <= 8) CT_MAXPY_DOT(8);
-    else CT_MAXPY_DOT(16);
+#define CT_MAXPY_DOT(NVV, WT, WP) \
+    hipLaunchKernelGGL((k_maxpy_dot<NVV, WT>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, zout, b.len, \
+                       coef, zscale, ncol, b.st.partials, stop)
+#define CT_MAXPY_DOT_NV(WT, WP) \
+    if (cnt <= 1) CT_MAXPY_DOT(1, WT, WP); \
+    else if (cnt <= 4) CT_MAXPY_DOT(4, WT, WP); \
+    else if (cnt <= 8) CT_MAXPY_DOT(8, WT, WP); \
+    else CT_MAXPY_DOT(16, WT, WP);
+    if (b.w16) { CT_MAXPY_DOT_NV(__half, b.wh(0)) } else { CT_MAXPY_DOT_NV(float, b.wf(0)) }
+#undef CT_MAXPY_DOT_NV
 #undef CT_MAXPY_DOT
     CT_LAUNCH_CHECK();
     return CT_OK;
@@ -493,10 +522,12 @@ static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *z
 // pass over a vector range uses the same number of blocks (sweep_blocks of
 // len/4 + 1) and the reduction kernels read that many.
 //   mode 0: d[j] = W[j].z (j < nvec) and ||z||^2 in column nvec
-//   mode 1: z1 = zs z - sum coef W (to zout), then d[j] = W[j].z1
-//   mode 2: z2 = z - sum coef W (to zout) and ||z2||^2 in column 0
+//   mode 1: z1 = zs z - sum coef W (to zout), then d[j] = W[j].z1 (FP16
+//           basis: and ||z1||^2 in column nvec)
+//   mode 2: z2 = z - sum coef W (to zout) and ||z2||^2 in column 0; with
+//           zout16 the last chunk stores FP16 of st.misc[M_BT] * z2 there
 int run_cgs(int mode, const GmresBufs &b, int nvec, const float *zin, float *zout, const double *coef,
-            const double *zscale, hipStream_t s) {
+            const double *zscale, hipStream_t s, __half *zout16 = nullptr) {
     if (mode == 0) {
         if (nvec == 0) return launch_mdot(b, 0, 0, zin, true, 0, s);
         for (int lo = 0; lo < nvec; lo += kCgsChunk) {
@@ -513,9 +544,10 @@ int run_cgs(int mode, const GmresBufs &b, int nvec, const float *zin, float *zou
         const double *zsc = lo == 0 ? zscale : nullptr;
         if (mode == 1 && last) {
             // the chunk that completes z1 also takes its own dots
-            CT_TRY(launch_maxpy_dot(b, lo, cnt, src, zout, coef, zsc, s));
+            CT_TRY(launch_maxpy_dot(b, lo, cnt, src, zout, coef, zsc, nvec, s));
         } else {
-            CT_TRY(launch_maxpy(b, lo, cnt, src, zout, coef, zsc, mode == 2 && last, 0, s));
+            CT_TRY(launch_maxpy(b, lo, cnt, src, zout, coef, zsc, mode == 2 && last, 0, s,
+                                mode == 2 && last ? zout16 : nullptr));
         }
     }
     if (mode == 1)
@@ -543,6 +575,17 @@ int check_solver_args(const ct_geometry *g, int solver, const ct_solver_opts *o,
     if (o->sino_dtype == CT_F16 && o->B == CT_B_AT) {
         set_error("solver: FP16 data storage is not implemented with B = A^T");
         return CT_ERR_UNSUPPORTED;
+    }
+    CT_ARG_CHECK(o->basis_dtype == CT_F32 || o->basis_dtype == CT_F16, "solver: bad basis_dtype");
+    if (o->basis_dtype == CT_F16) {
+        if (solver != CT_SOLVER_BA) {
+            set_error("solver: FP16 basis storage is implemented for BA-GMRES only");
+            return CT_ERR_UNSUPPORTED;
+        }
+        if (g->k.proj == CT_SIDDON && g->k.kind != CT_CONE_CIRCULAR_3D) {
+            set_error("solver: FP16 basis storage is not implemented with the 2D line-intersection projector");
+            return CT_ERR_UNSUPPORTED;
+        }
     }
     if (o->B == CT_B_RAMP && g->k.nu * 16 > 64 * 1024) {
         set_error("solver: detector rows longer than 4096 are not supported by the ramp filter");
@@ -640,29 +683,43 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
     CT_LAUNCH_CHECK();
     CT_TRY(launch_pad_zero(g, op.vx, op.vy, s));
 
-    // r0 = B b (BA) or b (AB), stored raw as W[0]
-    if (ba) CT_TRY(apply_B(g, o->B, b, CT_F32, bf.W, op, nullptr, nullptr, s));
-    else {
-        hipLaunchKernelGGL(k_copy, dim3(grid_1d(bf.len)), dim3(256), 0, s, b, bf.W, bf.len);
+    // FP16 basis: vectors of this length are stored scaled (gmres_red2)
+    const double blen = bf.w16 ? (double)bf.len : 0.0;
+    if (!bf.w16) {
+        // r0 = B b (BA) or b (AB), stored raw as W[0]
+        if (ba) CT_TRY(apply_B(g, o->B, b, CT_F32, bf.wf(0), op, nullptr, nullptr, s));
+        else {
+            hipLaunchKernelGGL(k_copy, dim3(grid_1d(bf.len)), dim3(256), 0, s, b, bf.wf(0), bf.len);
+            CT_LAUNCH_CHECK();
+        }
+        CT_TRY(run_cgs(2, bf, 0, bf.wf(0), bf.wf(0), st.coef, nullptr, s));   // ||r0||^2 (no update)
+        hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, s, st, nblk, qc, 0.0);
         CT_LAUNCH_CHECK();
+    } else {
+        // r0 = B b in FP32, its norm, then W[0] = FP16 of t0 r0 (BA only)
+        CT_TRY(apply_B(g, o->B, b, CT_F32, bf.z, op, nullptr, nullptr, s));
+        CT_TRY(run_cgs(0, bf, 0, bf.z, nullptr, nullptr, nullptr, s));
+        hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, s, st, nblk, qc, blen);
+        CT_LAUNCH_CHECK();
+        CT_TRY(launch_maxpy(bf, 0, 0, bf.z, nullptr, nullptr, nullptr, false, 0, s, bf.wh(0)));
     }
-    CT_TRY(run_cgs(2, bf, 0, bf.W, bf.W, st.coef, nullptr, s));   // ||r0||^2 (no update)
-    hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, s, st, nblk, qc);
-    CT_LAUNCH_CHECK();
     if (mon) {   // x_0 = 0: ||b|| and RMS(x_ref)
         CT_TRY(mon_curve(bf, b, bf.Q, bf.ldq, g->n_rays, -1, 1.0, bf.mon_data, s));
-        if (mon->x_ref) CT_TRY(mon_curve(bf, mon->x_ref, bf.W, bf.ldw, g->n_vox, -1, (double)g->n_vox, bf.mon_img, s));
+        if (mon->x_ref) CT_TRY(mon_curve(bf, mon->x_ref, bf.wf(0), bf.ldw, g->n_vox, -1, (double)g->n_vox, bf.mon_img, s));
     }
 
     const float *oscale = f16 ? st.fscale : nullptr;
     const float *iscale = f16 ? st.fscale + 1 : nullptr;
     for (int k = 0; k < K; ++k) {
-        float *wk = bf.W + (size_t)k * bf.ldw;
-        float *wn = bf.W + (size_t)(k + 1) * bf.ldw;
+        float *wk = bf.w16 ? nullptr : bf.wf(k);
+        // FP32 basis: CGS2 builds the new vector in its basis slot; FP16:
+        // in z, and its last pass stores the FP16 vector
+        float *wn = bf.w16 ? bf.z : bf.wf(k + 1);
         const bool pad_ready = o->B != CT_B_AT;
         if (ba) {
             void *qk = mon ? (void *)(bf.Q + (size_t)k * bf.ldq) : bf.q;
-            CT_TRY(apply_A(g, wk, qk, dt, op, pad_ready, oscale, stop, s));
+            if (bf.w16) CT_TRY(apply_A(g, bf.wh(k), qk, dt, op, pad_ready, oscale, stop, s, CT_F16));
+            else CT_TRY(apply_A(g, wk, qk, dt, op, pad_ready, oscale, stop, s));
             CT_TRY(apply_B(g, o->B, qk, dt, bf.z, op, iscale, stop, s));
         } else {
             CT_TRY(apply_B(g, o->B, wk, CT_F32, (float *)bf.q, op, nullptr, stop, s));
@@ -673,9 +730,9 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
         hipLaunchKernelGGL(k_gmres_red1, dim3(1), dim3(256), sizeof(double) * (nvec + 1), s, st, nblk, k);
         CT_LAUNCH_CHECK();
         CT_TRY(run_cgs(1, bf, nvec, bf.z, wn, st.coef, st.misc + M_ZS, s));
-        hipLaunchKernelGGL(k_gmres_red2, dim3(1), dim3(256), sizeof(double) * nvec, s, st, nblk, k);
+        hipLaunchKernelGGL(k_gmres_red2, dim3(1), dim3(256), sizeof(double) * (nvec + 1), s, st, nblk, k, blen);
         CT_LAUNCH_CHECK();
-        CT_TRY(run_cgs(2, bf, nvec, wn, wn, st.coef, nullptr, s));
+        CT_TRY(run_cgs(2, bf, nvec, wn, wn, st.coef, nullptr, s, bf.w16 ? bf.wh(k + 1) : nullptr));
         hipLaunchKernelGGL(k_gmres_red3, dim3(1), dim3(64), 0, s, st, nblk, k, tol, qc);
         CT_LAUNCH_CHECK();
         if (mon) {
@@ -683,18 +740,23 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
             CT_LAUNCH_CHECK();
             CT_TRY(mon_curve(bf, b, bf.Q, bf.ldq, g->n_rays, k, 1.0, bf.mon_data, s));
             if (mon->x_ref)
-                CT_TRY(mon_curve(bf, mon->x_ref, bf.W, bf.ldw, g->n_vox, k, (double)g->n_vox, bf.mon_img, s));
+                CT_TRY(mon_curve(bf, mon->x_ref, bf.wf(0), bf.ldw, g->n_vox, k, (double)g->n_vox, bf.mon_img, s));
         }
     }
     hipLaunchKernelGGL(k_gmres_trsv, dim3(1), dim3(64), 0, s, st);
     CT_LAUNCH_CHECK();
     if (ba) {
-        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, x,
-                           (int)accumulate);
+        if (bf.w16)
+            hipLaunchKernelGGL(k_combine<__half>, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.wh(0), bf.ldw, bf.len,
+                               st, x, (int)accumulate);
+        else
+            hipLaunchKernelGGL(k_combine<float>, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.wf(0), bf.ldw, bf.len,
+                               st, x, (int)accumulate);
         CT_LAUNCH_CHECK();
     } else {
         // x = B (W c): combine in data space, then back-project
-        hipLaunchKernelGGL(k_combine, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.W, bf.ldw, bf.len, st, bf.z, 0);
+        hipLaunchKernelGGL(k_combine<float>, dim3(grid_1d(bf.len)), dim3(256), 0, s, bf.wf(0), bf.ldw, bf.len, st,
+                           bf.z, 0);
         CT_LAUNCH_CHECK();
         CT_TRY(apply_B(g, o->B, bf.z, CT_F32, x, op, nullptr, nullptr, s));
     }
@@ -845,6 +907,10 @@ extern "C" int ct_ba_gmres_monitor(const ct_geometry *g, const float *b, float *
     CT_ARG_CHECK(opts != nullptr, "ct_ba_gmres_monitor: NULL options");
     if (opts->sino_dtype != CT_F32) {
         set_error("ct_ba_gmres_monitor: the kept projections are FP32 (sino_dtype must be CT_F32)");
+        return CT_ERR_UNSUPPORTED;
+    }
+    if (opts->basis_dtype != CT_F32) {
+        set_error("ct_ba_gmres_monitor: the monitored solve keeps an FP32 basis (basis_dtype must be CT_F32)");
         return CT_ERR_UNSUPPORTED;
     }
     MonitorOut mon{x_ref, data_res, img_rmse};

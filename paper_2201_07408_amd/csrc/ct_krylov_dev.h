@@ -23,7 +23,8 @@ struct KState {
     double *h1, *h2;   // K+1 CGS coefficients
     double *coef;      // K+1 coefficients applied by the next sweep
     double *res;       // K+1 residual history
-    double *misc;      // [0] scale of the raw z, [1] ||z|| before CGS, [2] CGLS gamma, [3] alpha/beta
+    double *misc;      // [0] scale of the raw z, [1] ||z|| before CGS, [2] CGLS gamma, [3] alpha/beta,
+                       // [4] power-of-two scale of the next FP16-stored basis vector (1 for FP32)
     float *fscale;     // [0] A output scale, [1] B input scale (FP16 storage)
     double *partials;  // [column][block]
     size_t pstride;    // column stride of partials (elements)
@@ -31,7 +32,7 @@ struct KState {
 };
 
 enum { F_KDONE = 0, F_STOP = 1, F_STATUS = 2 };
-enum { M_ZS = 0, M_ZN0 = 1, M_GAMMA = 2, M_AB = 3 };
+enum { M_ZS = 0, M_ZN0 = 1, M_GAMMA = 2, M_AB = 3, M_BT = 4 };
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -63,11 +64,35 @@ __device__ __forceinline__ void block_partials(double (&acc)[NV], int cnt, doubl
         partials[(size_t)ncol * cstride + slot] = (red[0][NV] + red[1][NV]) + (red[2][NV] + red[3][NV]);
 }
 
-// Multi-dot over float4 groups q0 + tid, q0 + tid + qstep, ... < q1:
+// Basis vectors are stored as FP32 or as FP16 (values scaled by a power of
+// two, see gmres_red2).  Four consecutive elements form a group: one 16-byte
+// or one 8-byte load.
+__device__ __forceinline__ float4 ld_group(const float *p, size_t q) { return reinterpret_cast<const float4 *>(p)[q]; }
+__device__ __forceinline__ float4 ld_group(const __half *p, size_t q) {
+    const uint2 r = reinterpret_cast<const uint2 *>(p)[q];
+    const float2 a = __half22float2(__builtin_bit_cast(__half2, r.x));
+    const float2 b = __half22float2(__builtin_bit_cast(__half2, r.y));
+    return make_float4(a.x, a.y, b.x, b.y);
+}
+// Store a group: FP32 as is; FP16 as round-to-nearest of scale * v (the
+// scale is a power of two, so the product is exact in FP32).
+__device__ __forceinline__ void st_group(float *p, size_t q, float4 v, float) {
+    reinterpret_cast<float4 *>(p)[q] = v;
+}
+__device__ __forceinline__ void st_group(__half *p, size_t q, float4 v, float scale) {
+    const __half2 a = __floats2half2_rn(scale * v.x, scale * v.y), b = __floats2half2_rn(scale * v.z, scale * v.w);
+    reinterpret_cast<uint2 *>(p)[q] = make_uint2(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b));
+}
+__device__ __forceinline__ float ld_elem(const float *p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ld_elem(const __half *p, size_t i) { return __half2float(p[i]); }
+__device__ __forceinline__ void st_elem(float *p, size_t i, float v, float) { p[i] = v; }
+__device__ __forceinline__ void st_elem(__half *p, size_t i, float v, float scale) { p[i] = __float2half_rn(scale * v); }
+
+// Multi-dot over groups q0 + tid, q0 + tid + qstep, ... < q1:
 // acc[j] += W[vlo+j] . z, nacc += z . z, all in FP64 (products of FP32
 // values are exact in FP64).
-template <int NV>
-__device__ __forceinline__ void mdot_groups(const float *__restrict__ Wc, size_t ldw, int cnt,
+template <int NV, typename WT>
+__device__ __forceinline__ void mdot_groups(const WT *__restrict__ Wc, size_t ldw, int cnt,
                                             const float *__restrict__ z, size_t q0, size_t q1, size_t qstep,
                                             double (&acc)[NV], double &nacc) {
     for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
@@ -77,42 +102,43 @@ __device__ __forceinline__ void mdot_groups(const float *__restrict__ Wc, size_t
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                const float4 w = ld_group(Wc + (size_t)j * ldw, q);
                 acc[j] += (double)w.x * z0 + (double)w.y * z1 + (double)w.z * z2 + (double)w.w * z3;
             }
     }
 }
 
-// Multi-axpy over float4 groups: z' = zs z - sum_j cf[j] W[vlo+j] (FP64),
-// rounded to FP32 and stored; nacc += z' . z'.
-template <int NV>
-__device__ __forceinline__ void maxpy_groups(const float *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
-                                             double zs, const float *zin, float *zout, size_t q0, size_t q1,
-                                             size_t qstep, double &nacc) {
+// Multi-axpy over groups: z' = zs z - sum_j cf[j] W[vlo+j] (FP64), rounded
+// to FP32; nacc += z' . z' (of the FP32 values); stored as OT (FP16 output:
+// oscale * z').
+template <int NV, typename WT, typename OT>
+__device__ __forceinline__ void maxpy_groups(const WT *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
+                                             double zs, const float *zin, OT *zout, float oscale, size_t q0,
+                                             size_t q1, size_t qstep, double &nacc) {
     for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
         const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
         double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                const float4 w = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                const float4 w = ld_group(Wc + (size_t)j * ldw, q);
                 const double c = cf[j];
                 u0 -= c * (double)w.x; u1 -= c * (double)w.y; u2 -= c * (double)w.z; u3 -= c * (double)w.w;
             }
         const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
-        reinterpret_cast<float4 *>(zout)[q] = o;
+        st_group(zout, q, o, oscale);
         nacc += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
     }
 }
 
-// Fused multi-axpy and multi-dot over float4 groups: z' = zs z - sum_j
-// cf[j] W[vlo+j] (FP64, rounded to FP32 and stored), then acc[j] +=
-// W[vlo+j] . z' with the same W values still in registers, so the chunk of
-// basis vectors is read once for both.
-template <int NV>
-__device__ __forceinline__ void maxpy_dot_groups(const float *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
+// Fused multi-axpy and multi-dot over groups: z' = zs z - sum_j cf[j]
+// W[vlo+j] (FP64, rounded to FP32 and stored), then acc[j] += W[vlo+j] . z'
+// with the same W values still in registers, so the chunk of basis vectors
+// is read once for both; nacc += z' . z'.
+template <int NV, typename WT>
+__device__ __forceinline__ void maxpy_dot_groups(const WT *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
                                                  double zs, const float *zin, float *zout, size_t q0, size_t q1,
-                                                 size_t qstep, double (&acc)[NV]) {
+                                                 size_t qstep, double (&acc)[NV], double &nacc) {
     for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
         const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
         double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
@@ -120,13 +146,14 @@ __device__ __forceinline__ void maxpy_dot_groups(const float *__restrict__ Wc, s
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                w[j] = reinterpret_cast<const float4 *>(Wc + (size_t)j * ldw)[q];
+                w[j] = ld_group(Wc + (size_t)j * ldw, q);
                 const double c = cf[j];
                 u0 -= c * (double)w[j].x; u1 -= c * (double)w[j].y; u2 -= c * (double)w[j].z; u3 -= c * (double)w[j].w;
             }
         const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
         reinterpret_cast<float4 *>(zout)[q] = o;
         const double o0 = o.x, o1 = o.y, o2 = o.z, o3 = o.w;
+        nacc += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) acc[j] += (double)w[j].x * o0 + (double)w[j].y * o1 + (double)w[j].z * o2 + (double)w[j].w * o3;
@@ -159,8 +186,19 @@ __device__ __forceinline__ float pow2_scale(double target) {
 // Each body is run by one workgroup (a multiple of 64 threads); `d` is
 // workgroup-shared scratch of at least K+2 doubles.
 
-// beta = ||r0|| from the partials; first basis vector's scale.
-__device__ inline void gmres_init(KState &st, int nblk, double qscale_c, double *d) {
+// Power of two t with t * norm in (sqrt(len) / 2, sqrt(len)]: the stored
+// values of an FP16 basis vector t * v then have an RMS near 1, and no value
+// can exceed sqrt(len) (< 2^15 for every supported length).
+__device__ __forceinline__ double basis_pow2(double norm, double len) {
+    if (!(norm > 0.0) || !isfinite(norm)) return 1.0;
+    const double e = floor(log2(sqrt(len) / norm));
+    return exp2(fmin(fmax(e, -1000.0), 1000.0));
+}
+
+// beta = ||r0|| from the partials; first basis vector's scale.  blen > 0:
+// the basis is stored in FP16 (vectors of length blen) and W[0] will hold
+// t0 r0, so its scale is 1 / (t0 beta).
+__device__ inline void gmres_init(KState &st, int nblk, double qscale_c, double *d, double blen = 0.0) {
     reduce_partials(st.partials, st.pstride, nblk, 1, d);
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -168,6 +206,7 @@ __device__ inline void gmres_init(KState &st, int nblk, double qscale_c, double 
     st.flags[F_KDONE] = 0;
     st.flags[F_STATUS] = CT_OK;
     st.res[0] = beta;
+    st.misc[M_BT] = 1.0;
     if (!isfinite(beta)) {
         st.flags[F_STOP] = 1;
         st.flags[F_STATUS] = CT_ERR_NUMERIC;
@@ -178,7 +217,9 @@ __device__ inline void gmres_init(KState &st, int nblk, double qscale_c, double 
         return;
     }
     st.flags[F_STOP] = 0;
-    st.sc[0] = 1.0 / beta;
+    const double t0 = blen > 0.0 ? basis_pow2(beta, blen) : 1.0;
+    st.misc[M_BT] = t0;
+    st.sc[0] = 1.0 / (beta * t0);
     st.gv[0] = beta;
     if (st.fscale) {
         const float qs = pow2_scale(st.sc[0] * qscale_c);
@@ -206,16 +247,20 @@ __device__ inline void gmres_red1(KState &st, int nblk, int k, double *d) {
     }
 }
 
-// After pass 2: h2 = V_k^T z1, coefficients for pass 3.
-__device__ inline void gmres_red2(KState &st, int nblk, int k, double *d) {
+// After pass 2: h2 = V_k^T z1, coefficients for pass 3.  blen > 0 (FP16
+// basis): the pass also summed ||z1||^2 (column nvec), from which the scale
+// of the vector that pass 3 stores is chosen (||z2|| differs from ||z1|| by
+// the second-pass correction only).
+__device__ inline void gmres_red2(KState &st, int nblk, int k, double *d, double blen = 0.0) {
     const int nvec = k + 1;
-    reduce_partials(st.partials, st.pstride, nblk, nvec, d);
+    reduce_partials(st.partials, st.pstride, nblk, blen > 0.0 ? nvec + 1 : nvec, d);
     __syncthreads();
     for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
         const double h = st.sc[j] * d[j];
         st.h2[j] = h;
         st.coef[j] = h * st.sc[j];
     }
+    if (blen > 0.0 && threadIdx.x == 0) st.misc[M_BT] = basis_pow2(sqrt(d[nvec]), blen);
 }
 
 // After pass 3: new column of H, Givens rotations, residual, breakdown test.
@@ -252,7 +297,7 @@ __device__ inline void gmres_red3(KState &st, int nblk, int k, double tol, doubl
         st.flags[F_STOP] = 1;
         return;
     }
-    st.sc[k + 1] = 1.0 / hn;
+    st.sc[k + 1] = 1.0 / (hn * st.misc[M_BT]);   // W[k+1] holds t z2 (t = 1 for FP32)
     if (st.fscale) {
         const float qs = pow2_scale(st.sc[k + 1] * qscale_c);
         st.fscale[0] = qs;

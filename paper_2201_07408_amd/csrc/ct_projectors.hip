@@ -90,7 +90,8 @@ __global__ void k_pad_zero(float *__restrict__ vx, float *__restrict__ vy, int n
 
 // x[z][y][x] -> Vx[x][z+pz][y+kPad] and Vy[y][z+pz][x+kPad] (interior only)
 // for the 32 x 32 tile at (x0, y0) of slice z; 256 work-items as 32 x 8.
-__device__ __forceinline__ void pad_tile(const float *__restrict__ x, float *__restrict__ vx,
+template <typename InT>
+__device__ __forceinline__ void pad_tile(const InT *__restrict__ x, float *__restrict__ vx,
                                          float *__restrict__ vy, int nx, int ny, const PadLayout &L, int x0,
                                          int y0, int z) {
     __shared__ float tile[32][33];
@@ -100,7 +101,7 @@ __device__ __forceinline__ void pad_tile(const float *__restrict__ x, float *__r
     for (int r = 0; r < 4; ++r) {
         const int yy = y0 + ty + 8 * r, xx = x0 + tx;
         if (yy < ny && xx < nx) {
-            const float v = x[zoff + (size_t)yy * nx + xx];
+            const float v = (float)x[zoff + (size_t)yy * nx + xx];
             tile[ty + 8 * r][tx] = v;
             vy[(size_t)yy * L.sy + (size_t)(z + L.pz) * L.ry + xx + kPad] = v;
         }
@@ -114,7 +115,8 @@ __device__ __forceinline__ void pad_tile(const float *__restrict__ x, float *__r
     }
 }
 
-__global__ __launch_bounds__(256) void k_pad_copy(const float *__restrict__ x, float *__restrict__ vx,
+template <typename InT>
+__global__ __launch_bounds__(256) void k_pad_copy(const InT *__restrict__ x, float *__restrict__ vx,
                                                   float *__restrict__ vy, int nx, int ny, PadLayout L,
                                                   const int *__restrict__ stop) {
     if (stop && *stop) return;
@@ -1801,10 +1803,15 @@ int launch_pad_zero(const ct_geometry *g, float *vx, float *vy, hipStream_t s) {
     return CT_OK;
 }
 
-int launch_pad_copy(const ct_geometry *g, const float *x, float *vx, float *vy, const int *stop,
+int launch_pad_copy(const ct_geometry *g, const void *x, int x_dtype, float *vx, float *vy, const int *stop,
                     hipStream_t s) {
     dim3 grid((g->k.nx + 31) / 32, (g->k.ny + 31) / 32, g->k.nz);
-    hipLaunchKernelGGL(k_pad_copy, grid, dim3(256), 0, s, x, vx, vy, g->k.nx, g->k.ny, g->pad, stop);
+    if (x_dtype == CT_F16)
+        hipLaunchKernelGGL(k_pad_copy<__half>, grid, dim3(256), 0, s, (const __half *)x, vx, vy, g->k.nx, g->k.ny,
+                           g->pad, stop);
+    else
+        hipLaunchKernelGGL(k_pad_copy<float>, grid, dim3(256), 0, s, (const float *)x, vx, vy, g->k.nx, g->k.ny,
+                           g->pad, stop);
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
@@ -2135,12 +2142,17 @@ OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *w
     return sc;
 }
 
-int apply_A(const ct_geometry *g, const float *x, void *y, int y_dtype, OpScratch &sc, bool pad_ready,
-            const float *out_scale, const int *stop, hipStream_t s) {
-    if (g->k.proj == CT_SIDDON && g->k.kind != CT_CONE_CIRCULAR_3D)
-        return launch_siddon(g, x, y, y_dtype, out_scale, stop, s);
+int apply_A(const ct_geometry *g, const void *x, void *y, int y_dtype, OpScratch &sc, bool pad_ready,
+            const float *out_scale, const int *stop, hipStream_t s, int x_dtype) {
+    if (g->k.proj == CT_SIDDON && g->k.kind != CT_CONE_CIRCULAR_3D) {
+        if (x_dtype != CT_F32) {
+            set_error("A: the 2D line-intersection projector reads FP32 input only");
+            return CT_ERR_UNSUPPORTED;
+        }
+        return launch_siddon(g, (const float *)x, y, y_dtype, out_scale, stop, s);
+    }
     if (!pad_ready) CT_TRY(launch_pad_zero(g, sc.vx, sc.vy, s));
-    CT_TRY(launch_pad_copy(g, x, sc.vx, sc.vy, stop, s));
+    CT_TRY(launch_pad_copy(g, x, x_dtype, sc.vx, sc.vy, stop, s));
     return launch_project(g, sc.vx, sc.vy, y, y_dtype, out_scale, stop, s);
 }
 

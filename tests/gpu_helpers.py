@@ -45,7 +45,7 @@ SMALL_GEOMS = {
 }
 
 
-def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0):
+def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0, basis="f64"):
     """How far FP32 arithmetic may move the oracle's K-th GMRES iterate.
 
     Each operator output of the oracle's solve is multiplied by
@@ -64,12 +64,15 @@ def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0):
     A = lambda v: np.asarray(oracle.project_A(desc, v.reshape(desc.vol_shape))).reshape(-1)
     Bop = oracle.back_projector(desc, B)
     Bf = lambda q: np.asarray(Bop(q.reshape(desc.sino_shape))).reshape(-1)
-    ref = (oracle.ba_gmres if solver == "ba" else oracle.ab_gmres)(desc, b, K, B=B).x.reshape(-1)
+    if solver == "ba":
+        ref = oracle.ba_gmres(desc, b, K, B=B, basis=basis).x.reshape(-1)
+    else:
+        ref = oracle.ab_gmres(desc, b, K, B=B).x.reshape(-1)
     worst = 0.0
     for _ in range(draws):
         p = lambda v: v * (1.0 + c * 2.0 ** -24 * rng.uniform(-1.0, 1.0, v.shape))
         if solver == "ba":
-            co, W, _, done, _ = oracle.gmres(lambda v: p(Bf(p(A(v)))), p(Bf(b)), K)
+            co, W, _, done, _ = oracle.gmres(lambda v: p(Bf(p(A(v)))), p(Bf(b)), K, basis=basis)
             x = W[:done].T @ co
         else:
             co, W, _, done, _ = oracle.gmres(lambda v: p(A(p(Bf(v)))), b, K)

@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 from paper_2201_07408_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -41,7 +43,35 @@ def test_struct_layouts_match_header():
     # ct_geometry_desc: 4 ints, double, int (+4 pad), pointer, 2 ints,
     # 4 doubles, int (+4 pad)
     assert ctypes.sizeof(_lib.GeometryDesc) == 4 * 4 + 8 + 8 + 8 + 8 + 4 * 8 + 8
-    assert ctypes.sizeof(_lib.SolverOpts) == 3 * 4 + 4 + 8
+    # ct_solver_opts: 3 ints (+4 pad), double, int (+4 pad)
+    assert ctypes.sizeof(_lib.SolverOpts) == 3 * 4 + 4 + 8 + 4 + 4
+
+
+def test_struct_offsets_match_the_c_compiler(tmp_path):
+    """Every field offset of the ctypes mirrors equals what a C compiler
+    makes of include/ct.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ct.h"', 'int main(void) {']
+    for cname, py in (("ct_geometry_desc", _lib.GeometryDesc), ("ct_solver_opts", _lib.SolverOpts)):
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in (("ct_geometry_desc", _lib.GeometryDesc), ("ct_solver_opts", _lib.SolverOpts)):
+        assert got[(cname, "size")] == ctypes.sizeof(py)
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_invalid_descriptor_rejected_on_host():
