@@ -17,7 +17,9 @@ follow the algorithm description of Sec. II of the paper:
 * BA-GMRES is GMRES on B A x = B b (Eq. 5); AB-GMRES is GMRES on A B y = b
   with x = B y (Eq. 4);
 * CGLS is the textbook conjugate-gradient recurrence for min ||A x - b||
-  (Eq. 2) with A^T replaced by the chosen back-projector.
+  (Eq. 2) with A^T replaced by the chosen back-projector;
+* optionally GMRES keeps its basis as FP16 values (``basis="f16"``, a storage
+  option of this implementation, see ``gmres``).
 """
 
 import ctypes
