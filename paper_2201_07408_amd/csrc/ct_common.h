@@ -76,6 +76,8 @@ struct GeomK {
     const int *axis;   // device: per-view dominant axis for 2D (0 = x, 1 = y)
     const ColT *colT;  // device: per (view, column) table of cone-beam rays, P x nu
     const int *vdom;   // device: per view, bit 0 / bit 1 set if any column is x- / y-dominant
+    const int4 *vrect; // device, cone: per view, detector columns [x, y] and rows [z, w] outside
+                       // of which no ray meets the volume (bounding box of its shadow)
 };
 
 // Padded, axis-permuted volume copies read by the forward projector and
@@ -116,6 +118,7 @@ struct ct_geometry {
     float *d_cs32 = nullptr;
     ct::ColT *d_colT = nullptr;
     int *d_vdom = nullptr;
+    int4 *d_vrect = nullptr;
     int *d_axis = nullptr;
     float *d_ramp = nullptr;       // du * h[j], j = 0..nu-1 (FP32)
     size_t n_vox = 0, n_rays = 0;

@@ -91,6 +91,45 @@ ProfScope::~ProfScope() {
     if (hipEventRecord(b_, s_) == hipSuccess) g_prof_recs.push_back(ProfRec{cls_, a_, b_});
 }
 
+// Per view of a circular cone-beam geometry: the detector columns
+// [x, y] and rows [z, w] that hold the shadow of the volume's box widened by
+// one voxel on every side (the reach of an interpolation or intersection
+// weight).  The shadow of a box seen from a point in front of it is the
+// convex hull of its corners' projections, so a ray through a pixel outside
+// the rectangle misses the widened box and its projection is exactly zero.
+// A view whose widened box reaches the source plane keeps the whole
+// detector.
+std::vector<int4> shadow_rects(const ct_geometry_desc &d, const std::vector<double> &cs) {
+    std::vector<int4> r((size_t)d.n_views);
+    const double hx = (0.5 * d.nx + 1.0) * d.voxel, hy = (0.5 * d.ny + 1.0) * d.voxel,
+                 hz = (0.5 * d.nz + 1.0) * d.voxel;
+    const double lim = 1.0e9;
+    for (int p = 0; p < d.n_views; ++p) {
+        const double c = cs[2 * (size_t)p], s = cs[2 * (size_t)p + 1];
+        double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+        bool ok = true;
+        for (int k = 0; k < 8; ++k) {
+            const double X = (k & 1) ? hx : -hx, Y = (k & 2) ? hy : -hy, Z = (k & 4) ? hz : -hz;
+            const double dx = X - d.sod * c, dy = Y - d.sod * s;
+            const double depth = -(dx * c + dy * s);            // along the central ray
+            if (!(depth > 1e-9 * d.sod)) { ok = false; break; }
+            const double u = d.sdd * (-dx * s + dy * c) / depth;  // along e_u = (-sin, cos, 0)
+            const double v = d.sdd * Z / depth;
+            const double au = u / d.du + 0.5 * (d.nu - 1), av = v / d.dv + 0.5 * (d.nv - 1);
+            umin = std::fmin(umin, au); umax = std::fmax(umax, au);
+            vmin = std::fmin(vmin, av); vmax = std::fmax(vmax, av);
+        }
+        if (!ok) {
+            r[p] = make_int4(0, d.nu - 1, 0, d.nv - 1);
+            continue;
+        }
+        const auto lo = [&](double a) { return (int)std::fmax(std::floor(a) - 1.0, -lim); };
+        const auto hi = [&](double a) { return (int)std::fmin(std::ceil(a) + 1.0, lim); };
+        r[p] = make_int4(lo(umin), hi(umax), lo(vmin), hi(vmax));
+    }
+    return r;
+}
+
 }  // namespace ct
 
 using namespace ct;
@@ -240,16 +279,25 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     k.axis = g->d_axis;
     k.colT = nullptr;
     k.vdom = nullptr;
+    k.vrect = nullptr;
     g->pad = pad_layout(k);
     if (d.kind == CT_CONE_CIRCULAR_3D) {
         if (hipMalloc(&g->d_colT, sizeof(ColT) * (size_t)P * d.nu) != hipSuccess ||
-            hipMalloc(&g->d_vdom, sizeof(int) * (size_t)P) != hipSuccess) {
+            hipMalloc(&g->d_vdom, sizeof(int) * (size_t)P) != hipSuccess ||
+            hipMalloc(&g->d_vrect, sizeof(int4) * (size_t)P) != hipSuccess) {
             ct_geometry_destroy(g);
             set_error("ct_geometry_create: hipMalloc failed");
             return CT_ERR_ALLOC;
         }
+        const std::vector<int4> rect = shadow_rects(d, g->h_cs);
+        if (hipMemcpy(g->d_vrect, rect.data(), sizeof(int4) * (size_t)P, hipMemcpyHostToDevice) != hipSuccess) {
+            ct_geometry_destroy(g);
+            set_error("ct_geometry_create: hipMemcpy failed");
+            return CT_ERR_HIP;
+        }
         k.colT = g->d_colT;
         k.vdom = g->d_vdom;
+        k.vrect = g->d_vrect;
         const int st = launch_col_table(g);
         if (st != CT_OK) {
             ct_geometry_destroy(g);
@@ -266,6 +314,7 @@ extern "C" void ct_geometry_destroy(ct_geometry *g) {
     if (g->d_cs32) (void)hipFree(g->d_cs32);
     if (g->d_colT) (void)hipFree(g->d_colT);
     if (g->d_vdom) (void)hipFree(g->d_vdom);
+    if (g->d_vrect) (void)hipFree(g->d_vrect);
     if (g->d_axis) (void)hipFree(g->d_axis);
     if (g->d_ramp) (void)hipFree(g->d_ramp);
     delete g;
