@@ -401,10 +401,6 @@ constexpr int kNQ = 8;                // staged 16-byte columns per row (32 floa
 constexpr int kStage = kSR * kNQ;     // work-items that stage (one cell per plane each)
 static_assert(kStage <= kTU * kTV && kNQ * 4 <= kSC, "staging layout");
 constexpr int kMaxChunks = 512;       // planes up to 2048 (longer: direct path)
-// consecutive views kept on one XCD; measured ms per launch at 256^3 with
-// 360 views / at 1024 x 1024 x 300 with 180 views: 6: 4.58 / 76.7,
-// 8: 4.72 / 78.7, 10: 4.51 / 77.2, 16: 4.64 / 88.6, 20: 4.66 / 91.5
-constexpr int kVGrp = 10;
 constexpr int kWaves = kTU * kTV / 64;
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -423,19 +419,20 @@ __device__ __forceinline__ int wave_max(int v) {
 // range of logical work, ordered [view group][tile][view in group].  The
 // workgroups resident on one XCD then project the same tiles for
 // neighbouring views, whose footprints overlap, and the XCD's L2 serves the
-// overlap.  Returns false for the padding workgroups of the last XCD.
-__device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int &tu, int &tv, int &p) {
+// overlap.  vgrp views form a group (the launch picks it, see
+// launch_staged).  Returns false for the padding workgroups of the last XCD.
+__device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int vgrp, int &tu, int &tv, int &p) {
     const int ntiles = ntu * ntv;
-    const int ngrp = (P + kVGrp - 1) / kVGrp;
-    const int nlog = ngrp * ntiles * kVGrp;
+    const int ngrp = (P + vgrp - 1) / vgrp;
+    const int nlog = ngrp * ntiles * vgrp;
     const int per = (nlog + 7) / 8;
     const int b = blockIdx.x;
     const int lg = (b & 7) * per + (b >> 3);
     if ((b >> 3) >= per || lg >= nlog) return false;
-    const int vv = lg % kVGrp;
-    const int t = (lg / kVGrp) % ntiles;
-    const int grp = lg / (kVGrp * ntiles);
-    p = grp * kVGrp + vv;
+    const int vv = lg % vgrp;
+    const int t = (lg / vgrp) % ntiles;
+    const int grp = lg / (vgrp * ntiles);
+    p = grp * vgrp + vv;
     tu = t % ntu;
     tv = t / ntu;
     return p < P;
@@ -450,10 +447,10 @@ template <typename OutT, bool SID>
 __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
                                                         uint32_t offy, OutT *__restrict__ y,
                                                         const float *__restrict__ out_scale,
-                                                        const int *__restrict__ stop) {
+                                                        const int *__restrict__ stop, int vgrp) {
     if (stop && *stop) return;
     int tu, tv, p;
-    if (!xcd_tile((g.nu + kTU - 1) / kTU, (g.nv + kTV - 1) / kTV, g.P, tu, tv, p)) return;
+    if (!xcd_tile((g.nu + kTU - 1) / kTU, (g.nv + kTV - 1) / kTV, g.P, vgrp, tu, tv, p)) return;
     {
         // no ray of the tile meets the volume: zeros, without the ray set-up
         const int4 rc = g.vrect[p];
@@ -1868,22 +1865,32 @@ static unsigned lds_for_occupancy(const void *kernel, int target) {
 // The staged projector re-reads each tile's planes from L2 for the
 // neighbouring views of its group.  While the padded copies fit the 256 MB
 // last-level cache the misses are cheap and the kernel is bound by VALU
-// issue, so it runs at full occupancy (seven workgroups per CU).  Beyond
-// that the misses go to HBM, and fewer resident tiles per XCD keep more of
-// each tile's planes in L2: at 1024 x 1024 x 300 with 180 views, 7, 5, 4, 3
-// and 2 workgroups per CU took 77.2, 68.0, 63.2, 64.1 and 80.3 ms; at 256^3
-// (copies of 140 MB) 4 per CU took 5.43 ms against 4.44 at 7.
+// issue, so it runs at full occupancy (seven workgroups per CU) with groups
+// of ten views (ms per launch at 256^3, 360 views: groups of 6: 4.50,
+// 10: 4.44, 16: 4.56, 24: 4.58; four workgroups per CU: 5.43).  Beyond
+// that the misses go to HBM, and fewer resident tiles per XCD and smaller
+// view groups keep more of each tile's planes in L2.  At 1024 x 1024 x 300
+// with 180 views: groups of ten at 7, 5, 4, 3 and 2 workgroups per CU took
+// 77.2, 68.0, 63.2, 64.1 and 80.3 ms; at four per CU, groups of 2, 3, 4, 6,
+// 8, 16 and 24 took 56.4, 54.2, 55.4, 55.3, 58.1, 70.7 and 77.3 ms (groups
+// of 3 at 3, 5 and 7 per CU: 62.2 (groups of 4), 58.7, 85.9).
 constexpr double kLlcBytes = 256.0 * 1024 * 1024;
+constexpr int kVGrpCached = 10;
+constexpr int kVGrpBig = 6;
 constexpr int kBigVolumeWgPerCu = 4;
+
+static int staged_view_group(const ct_geometry *g) {
+    return 4.0 * (double)(g->pad.nvx + g->pad.nvy) > kLlcBytes ? kVGrpBig : kVGrpCached;
+}
 
 template <typename OutT, bool SID>
 static int launch_staged(const ct_geometry *g, dim3 grid, const float *vx, uint32_t offy, void *y,
                          const float *out_scale, const int *stop, hipStream_t s) {
     const void *kern = (const void *)&k_project_staged<OutT, SID>;
-    const bool big = 4.0 * (double)(g->pad.nvx + g->pad.nvy) > kLlcBytes;
-    const unsigned lds = big ? lds_for_occupancy(kern, kBigVolumeWgPerCu) : 0u;
+    const int vgrp = staged_view_group(g);
+    const unsigned lds = vgrp == kVGrpBig ? lds_for_occupancy(kern, kBigVolumeWgPerCu) : 0u;
     hipLaunchKernelGGL((k_project_staged<OutT, SID>), grid, dim3(kTU, kTV), lds, s, g->k, g->pad, vx, offy,
-                       (OutT *)y, out_scale, stop);
+                       (OutT *)y, out_scale, stop, vgrp);
     return CT_OK;
 }
 
@@ -1903,7 +1910,8 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
     if (cone) {
         // 16 x 16 ray tiles, flat grid remapped per XCD inside the kernel
         const long ntiles = (long)((g->k.nu + kTU - 1) / kTU) * ((g->k.nv + kTV - 1) / kTV);
-        const long nlog = (long)((g->k.P + kVGrp - 1) / kVGrp) * ntiles * kVGrp;
+        const int vgrp = staged_view_group(g);
+        const long nlog = (long)((g->k.P + vgrp - 1) / vgrp) * ntiles * vgrp;
         const long per = (nlog + 7) / 8;
         if (8 * per > 2147483647L) {
             set_error("launch_project: too many ray tiles");
