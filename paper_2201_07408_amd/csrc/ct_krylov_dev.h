@@ -188,11 +188,13 @@ __device__ __forceinline__ float pow2_scale(double target) {
 
 // Power of two t with t * norm in (sqrt(len) / 2, sqrt(len)]: the stored
 // values of an FP16 basis vector t * v then have an RMS near 1, and no value
-// can exceed sqrt(len) (< 2^15 for every supported length).
+// can exceed sqrt(len) (< 2^15 for every supported length).  t stays within
+// 2^+-120 so that it is an FP32 number (the rule holds for every norm of an
+// FP32 vector above 2^-100).
 __device__ __forceinline__ double basis_pow2(double norm, double len) {
     if (!(norm > 0.0) || !isfinite(norm)) return 1.0;
     const double e = floor(log2(sqrt(len) / norm));
-    return exp2(fmin(fmax(e, -1000.0), 1000.0));
+    return exp2(fmin(fmax(e, -120.0), 120.0));
 }
 
 // beta = ||r0|| from the partials; first basis vector's scale.  blen > 0:
