@@ -555,18 +555,20 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     // return zero.
     const bool stager = tid < kStage;
     const int r_t = tid / kNQ, c4_t = tid % kNQ;
-    const uint32_t toff = __umul24((uint32_t)r_t, Rw) + 4u * (uint32_t)c4_t;
+    // byte offset of the work-item's cell within a box (the box origin and
+    // plane offsets are wavefront-uniform and added on the scalar unit)
+    const uint32_t toffb = 4u * (__umul24((uint32_t)r_t, Rw) + 4u * (uint32_t)c4_t);
     float4 pre[kPC];
-    auto fetch = [&](int c) {
-        const uint32_t bx = __builtin_amdgcn_readfirstlane(s_box[c]);
+    // chunk c's loads into registers; bx is its box word (0: not staged)
+    auto fetch = [&](int c, uint32_t bx) {
         if (bx == 0u) return;
         const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u), nr = (int)(bx & 63u);
         const int ja = jlo + c * kPC;
         if (stager && r_t < nr) {
-            const uint32_t e0 = base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0 + toff;
+            const uint32_t e0b = 4u * (base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0);
 #pragma unroll
             for (int pl = 0; pl < kPC; ++pl) {
-                const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((e0 + pl * S) * 4u), 0, 0);
+                const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(toffb + (e0b + 4u * pl * S)), 0, 0);
                 pre[pl] = make_float4(__builtin_bit_cast(float, (uint32_t)w[0]), __builtin_bit_cast(float, (uint32_t)w[1]),
                                       __builtin_bit_cast(float, (uint32_t)w[2]), __builtin_bit_cast(float, (uint32_t)w[3]));
             }
@@ -574,14 +576,16 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     };
     const float *tile = (const float *)tile4;
     __syncthreads();   // boxes visible
-    if (nch > 0) fetch(0);
+    // the box word of the next chunk, read once (prefetch, then use)
+    uint32_t bx_next = nch > 0 ? __builtin_amdgcn_readfirstlane(s_box[0]) : 0u;
+    if (nch > 0) fetch(0, bx_next);
     double acc = 0.0;
     // row slope plus the tile's plane stride in rows: plane pl of a chunk
     // sits kSR rows below plane pl - 1
     const float gcs = R.gc + (float)kSR;
     for (int c = 0; c < nch; ++c) {
         const int ja = jlo + c * kPC;
-        const uint32_t bx = __builtin_amdgcn_readfirstlane(s_box[c]);
+        const uint32_t bx = bx_next;
         const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u);
         if (bx != 0u) {
             const int nr = (int)(bx & 63u);
@@ -592,7 +596,10 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
             }
             __syncthreads();
         }
-        if (c + 1 < nch) fetch(c + 1);
+        if (c + 1 < nch) {
+            bx_next = __builtin_amdgcn_readfirstlane(s_box[c + 1]);
+            fetch(c + 1, bx_next);
+        }
         if (ja + kPC - 1 < wlo || ja > whi) continue;   // no lane of this wavefront samples the chunk
         const int jb = min(ja + kPC - 1, R.j1), jf = max(ja, R.j0);
         if (bx == 0u) {    // box too large: direct loads for this chunk
