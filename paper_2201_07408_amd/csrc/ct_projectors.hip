@@ -463,8 +463,13 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     }
     __shared__ float4 tile4[kPC * kSR * kSC / 4];
     __shared__ uint32_t s_box[kMaxChunks];   // (b0 + 1) << 16 | c0 << 6 | rows; b0 = -1: direct
-    __shared__ float s_corner[4][4];
-    __shared__ int s_wj[kWaves][5];   // per wavefront: min j0, max j1 (non-empty rays), max j0, min j1, axes
+    // The corner rays and the per-wavefront plane ranges are read only
+    // before the first chunk is staged (a barrier lies between), so they
+    // share the tile's space: 20,480 bytes of LDS in all, eight workgroups
+    // per CU.
+    float(*s_corner)[4] = reinterpret_cast<float(*)[4]>(tile4);
+    int(*s_wj)[5] = reinterpret_cast<int(*)[5]>(tile4 + 4);   // per wavefront: min j0, max j1 (non-empty rays),
+                                                               // max j0, min j1, axes
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx, wv = tid >> 6;
     const int au0 = tu * kTU, av0 = tv * kTV;
     const int au = au0 + tx, av = av0 + ty;
