@@ -1877,7 +1877,7 @@ static unsigned lds_for_occupancy(const void *kernel, int target) {
 // The staged projector re-reads each tile's planes from L2 for the
 // neighbouring views of its group.  While the padded copies fit the 256 MB
 // last-level cache the misses are cheap and the kernel is bound by VALU
-// issue, so it runs at full occupancy (seven workgroups per CU) with groups
+// issue, so it runs at full occupancy (eight workgroups per CU) with groups
 // of ten views (ms per launch at 256^3, 360 views: groups of 6: 4.50,
 // 10: 4.44, 16: 4.56, 24: 4.58; four workgroups per CU: 5.43).  Beyond
 // that the misses go to HBM, and fewer resident tiles per XCD and smaller
