@@ -34,12 +34,14 @@ if ROOT not in sys.path:
 ITERS = 30
 PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak, FLOP/s
 PEAK_HBM = 8.0e12               # bytes/s
-# algorithmic work per unit: a Joseph sample is 2 coordinate FMAs (4) + 2
-# fractions (2) + 3 linear interpolations of a sub and an FMA (9) + 1
-# accumulate = 16 FLOP; a voxel-driven update is 1 coordinate FMA (2) + 1
-# fraction (1) + 3 interpolations (9) + a weighted accumulate FMA (2) = 14
-FLOP_PER_A_UPDATE = 16.0
-FLOP_PER_B_UPDATE = 14.0
+# algorithmic work per unit, counting each step of a sample as one
+# operation: a Joseph sample is 2 coordinates, 2 fractions, 3 linear
+# interpolations and an accumulate (about 10 FLOP); a voxel-driven update a
+# coordinate, a fraction, 3 interpolations and a weighted accumulate (about
+# 8).  Counting an FMA as two and an interpolation as a subtract plus an FMA
+# gives 16 and 14 instead, and fractions 1.6 and 1.75 times higher.
+FLOP_PER_A_UPDATE = 10.0
+FLOP_PER_B_UPDATE = 8.0
 # HBM traffic of one projector launch on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes over this benchmark, each scaled by what
 # the counter reads for a 256 MiB copy (FETCH x2.0, WRITE x1.0); valid only
