@@ -78,6 +78,7 @@ struct GeomK {
     const int *vdom;   // device: per view, bit 0 / bit 1 set if any column is x- / y-dominant
     const int4 *vrect; // device, cone: per view, detector columns [x, y] and rows [z, w] outside
                        // of which no ray meets the volume (bounding box of its shadow)
+    const int *vshift; // device, cone: per view, column offset of the projector's ray tiles
 };
 
 // Padded, axis-permuted volume copies read by the forward projector and
@@ -119,6 +120,7 @@ struct ct_geometry {
     ct::ColT *d_colT = nullptr;
     int *d_vdom = nullptr;
     int4 *d_vrect = nullptr;
+    int *d_vshift = nullptr;
     int *d_axis = nullptr;
     float *d_ramp = nullptr;       // du * h[j], j = 0..nu-1 (FP32)
     size_t n_vox = 0, n_rays = 0;

@@ -280,11 +280,13 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     k.colT = nullptr;
     k.vdom = nullptr;
     k.vrect = nullptr;
+    k.vshift = nullptr;
     g->pad = pad_layout(k);
     if (d.kind == CT_CONE_CIRCULAR_3D) {
         if (hipMalloc(&g->d_colT, sizeof(ColT) * (size_t)P * d.nu) != hipSuccess ||
             hipMalloc(&g->d_vdom, sizeof(int) * (size_t)P) != hipSuccess ||
-            hipMalloc(&g->d_vrect, sizeof(int4) * (size_t)P) != hipSuccess) {
+            hipMalloc(&g->d_vrect, sizeof(int4) * (size_t)P) != hipSuccess ||
+            hipMalloc(&g->d_vshift, sizeof(int) * (size_t)P) != hipSuccess) {
             ct_geometry_destroy(g);
             set_error("ct_geometry_create: hipMalloc failed");
             return CT_ERR_ALLOC;
@@ -298,6 +300,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
         k.colT = g->d_colT;
         k.vdom = g->d_vdom;
         k.vrect = g->d_vrect;
+        k.vshift = g->d_vshift;
         const int st = launch_col_table(g);
         if (st != CT_OK) {
             ct_geometry_destroy(g);
@@ -315,6 +318,7 @@ extern "C" void ct_geometry_destroy(ct_geometry *g) {
     if (g->d_colT) (void)hipFree(g->d_colT);
     if (g->d_vdom) (void)hipFree(g->d_vdom);
     if (g->d_vrect) (void)hipFree(g->d_vrect);
+    if (g->d_vshift) (void)hipFree(g->d_vshift);
     if (g->d_axis) (void)hipFree(g->d_axis);
     if (g->d_ramp) (void)hipFree(g->d_ramp);
     delete g;

@@ -438,26 +438,33 @@ __device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int vgrp, int 
     return p < P;
 }
 
+// Tile columns per view: the detector's, plus one for the column offset.
+__host__ __device__ __forceinline__ int staged_tile_cols(int nu) { return (nu + kTU - 1) / kTU + 1; }
+
 // SID: the line-intersection model instead of Joseph's (same tiles, boxes
 // and staging; per plane a slab of three segments instead of a bilinear
 // sample).  Geometries admit no ray steeper than one voxel per plane in z
 // (ct_geometry_create rejects cone angles that allow z-dominant rays), as
 // the slab decomposition requires.
+// Eight workgroups per CU (LDS 20,480 bytes): the register budget is held
+// to 64 (two registers of the rare per-chunk direct path go to scratch).
 template <typename OutT, bool SID>
-__global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
+__global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L, const float *__restrict__ vol,
                                                         uint32_t offy, OutT *__restrict__ y,
                                                         const float *__restrict__ out_scale,
                                                         const int *__restrict__ stop, int vgrp) {
     if (stop && *stop) return;
     int tu, tv, p;
-    if (!xcd_tile((g.nu + kTU - 1) / kTU, (g.nv + kTV - 1) / kTV, g.P, vgrp, tu, tv, p)) return;
+    if (!xcd_tile(staged_tile_cols(g.nu), (g.nv + kTV - 1) / kTV, g.P, vgrp, tu, tv, p)) return;
+    // the view's tile columns start vshift columns left of the detector
+    const int au0 = tu * kTU - g.vshift[p], av0 = tv * kTV;
+    if (au0 + kTU <= 0 || au0 >= g.nu) return;   // no column of the detector
     {
         // no ray of the tile meets the volume: zeros, without the ray set-up
         const int4 rc = g.vrect[p];
-        const int u0 = tu * kTU, v0 = tv * kTV;
-        if (u0 + kTU - 1 < rc.x || u0 > rc.y || v0 + kTV - 1 < rc.z || v0 > rc.w) {
-            const int au = u0 + (int)threadIdx.x, av = v0 + (int)threadIdx.y;
-            if (au < g.nu && av < g.nv) y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(0.0f);
+        if (au0 + kTU - 1 < rc.x || au0 > rc.y || av0 + kTV - 1 < rc.z || av0 > rc.w) {
+            const int au = au0 + (int)threadIdx.x, av = av0 + (int)threadIdx.y;
+            if (au >= 0 && au < g.nu && av < g.nv) y[((size_t)p * g.nv + av) * g.nu + au] = from_f<OutT>(0.0f);
             return;
         }
     }
@@ -471,13 +478,12 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     int(*s_wj)[5] = reinterpret_cast<int(*)[5]>(tile4 + 4);   // per wavefront: min j0, max j1 (non-empty rays),
                                                                // max j0, min j1, axes
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTU + tx, wv = tid >> 6;
-    const int au0 = tu * kTU, av0 = tv * kTV;
     const int au = au0 + tx, av = av0 + ty;
-    const bool active = au < g.nu && av < g.nv;
+    const bool active = au >= 0 && au < g.nu && av < g.nv;
     // Lanes outside the detector repeat the ray of the tile's nearest
     // detector pixel: their samples are valid (inside the tile's boxes) and
     // are not stored, so no lane needs a separate inactive path.
-    const RaySetup R = ray_setup<true>(g, L, p, min(av, g.nv - 1), min(au, g.nu - 1));
+    const RaySetup R = ray_setup<true>(g, L, p, min(av, g.nv - 1), min(max(au, 0), g.nu - 1));
     {
         const bool ne = R.j0 <= R.j1;
         const int a = wave_min(ne ? R.j0 : 0x7fffffff), b = wave_max(ne ? R.j1 : -1);
@@ -487,10 +493,10 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomK g, PadLayout L, co
     }
     if (active) {
         // corner rays of the (possibly partial) tile
-        const int ulast = min(au0 + kTU, g.nu) - 1 - au0, vlast = min(av0 + kTV, g.nv) - 1 - av0;
+        const int ufirst = max(-au0, 0), ulast = min(au0 + kTU, g.nu) - 1 - au0, vlast = min(av0 + kTV, g.nv) - 1 - av0;
         for (int cy = 0; cy < 2; ++cy)
             for (int cx = 0; cx < 2; ++cx)
-                if ((cx ? tx == ulast : tx == 0) && (cy ? ty == vlast : ty == 0)) {
+                if ((cx ? tx == ulast : tx == ufirst) && (cy ? ty == vlast : ty == 0)) {
                     s_corner[cy * 2 + cx][0] = R.fb0;
                     s_corner[cy * 2 + cx][1] = R.gb;
                     s_corner[cy * 2 + cx][2] = R.fc0;
@@ -754,13 +760,23 @@ __global__ void k_col_table(GeomK g, ColT *__restrict__ T) {
     T[(size_t)p * g.nu + au] = e;
 }
 
-// Per view: which dominant axes occur among its columns.
-__global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict__ vdom) {
+// Per view: which dominant axes occur among its columns, and the column
+// offset of the projector's ray tiles that puts a tile edge at the first
+// column whose dominant axis differs from column 0's (the table's axis is
+// the projector's own decision), so that no tile mixes the two axes where
+// the axis changes once across the detector.
+__global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict__ vdom, int *__restrict__ vshift) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.P) return;
-    int f = 0;
-    for (int au = 0; au < g.nu; ++au) f |= T[(size_t)p * g.nu + au].is > 0.0f ? 1 : 2;
+    int f = 0, sw = 0;
+    const bool x0 = T[(size_t)p * g.nu].is > 0.0f;
+    for (int au = 0; au < g.nu; ++au) {
+        const bool xd = T[(size_t)p * g.nu + au].is > 0.0f;
+        f |= xd ? 1 : 2;
+        if (sw == 0 && xd != x0) sw = au;
+    }
     vdom[p] = f;
+    vshift[p] = (kTU - sw % kTU) % kTU;
 }
 
 // Exact transpose of the cone-beam Joseph projector, gathered per voxel
@@ -1921,7 +1937,7 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
     ProfScope prof(PROF_A, s);
     if (cone) {
         // 16 x 16 ray tiles, flat grid remapped per XCD inside the kernel
-        const long ntiles = (long)((g->k.nu + kTU - 1) / kTU) * ((g->k.nv + kTV - 1) / kTV);
+        const long ntiles = (long)staged_tile_cols(g->k.nu) * ((g->k.nv + kTV - 1) / kTV);
         const int vgrp = staged_view_group(g);
         const long nlog = (long)((g->k.P + vgrp - 1) / vgrp) * ntiles * vgrp;
         const long per = (nlog + 7) / 8;
@@ -1949,7 +1965,8 @@ int launch_col_table(ct_geometry *g) {
     dim3 grid((g->k.nu + 255) / 256, g->k.P), block(256);
     hipLaunchKernelGGL(k_col_table, grid, block, 0, 0, g->k, g->d_colT);
     CT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_view_dom, dim3((g->k.P + 255) / 256), dim3(256), 0, 0, g->k, g->d_colT, g->d_vdom);
+    hipLaunchKernelGGL(k_view_dom, dim3((g->k.P + 255) / 256), dim3(256), 0, 0, g->k, g->d_colT, g->d_vdom,
+                       g->d_vshift);
     CT_LAUNCH_CHECK();
     if (hipStreamSynchronize(0) != hipSuccess) {
         set_error("ct_geometry_create: column table kernel failed");
