@@ -51,10 +51,11 @@ __global__ __launch_bounds__(256) void k_mdot(const WT *__restrict__ W, size_t l
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     const WT *Wc = W + (size_t)vlo * ldw;
-    const size_t n4 = n / 4;
+    constexpr int GE = Group<WT>::n;   // elements per group
+    const size_t n4 = n / GE;
     mdot_groups<NV>(Wc, ldw, cnt, z, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)   // tail of fewer than four elements
-        for (size_t i = n4 * 4; i < n; ++i) {
+        for (size_t i = n4 * GE; i < n; ++i) {
             const double zd = z[i];
             nacc += zd * zd;
 #pragma unroll
@@ -80,11 +81,12 @@ __global__ __launch_bounds__(256) void k_maxpy(const WT *__restrict__ W, size_t 
     const float os = oscale ? (float)*oscale : 1.0f;
     double nacc = 0.0;
     const WT *Wc = W + (size_t)vlo * ldw;
-    const size_t n4 = n / 4;
+    constexpr int GE = Group<WT>::n;   // elements per group
+    const size_t n4 = n / GE;
     maxpy_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, os, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
                      nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (size_t i = n4 * 4; i < n; ++i) {
+        for (size_t i = n4 * GE; i < n; ++i) {
             double u = zs * (double)zin[i];
             for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)ld_elem(Wc + (size_t)j * ldw, i);
             const float o = (float)u;
@@ -117,11 +119,12 @@ __global__ __launch_bounds__(256) void k_maxpy_dot(const WT *__restrict__ W, siz
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     const WT *Wc = W + (size_t)vlo * ldw;
-    const size_t n4 = n / 4;
+    constexpr int GE = Group<WT>::n;   // elements per group
+    const size_t n4 = n / GE;
     maxpy_dot_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
                          acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (size_t i = n4 * 4; i < n; ++i) {
+        for (size_t i = n4 * GE; i < n; ++i) {
             double u = zs * (double)zin[i];
             for (int j = 0; j < cnt; ++j) u -= cf[j] * (double)ld_elem(Wc + (size_t)j * ldw, i);
             const float o = (float)u;

@@ -65,45 +65,81 @@ __device__ __forceinline__ void block_partials(double (&acc)[NV], int cnt, doubl
 }
 
 // Basis vectors are stored as FP32 or as FP16 (values scaled by a power of
-// two, see gmres_red2).  Four consecutive elements form a group: one 16-byte
-// or one 8-byte load.
-__device__ __forceinline__ float4 ld_group(const float *p, size_t q) { return reinterpret_cast<const float4 *>(p)[q]; }
-__device__ __forceinline__ float4 ld_group(const __half *p, size_t q) {
-    const uint2 r = reinterpret_cast<const uint2 *>(p)[q];
-    const float2 a = __half22float2(__builtin_bit_cast(__half2, r.x));
-    const float2 b = __half22float2(__builtin_bit_cast(__half2, r.y));
-    return make_float4(a.x, a.y, b.x, b.y);
+// two, see gmres_red2).  A group is the elements one 16-byte load of the
+// basis holds: four FP32 or eight FP16 values (kGroup<WT>).
+template <typename WT> struct Group;
+template <> struct Group<float> { static constexpr int n = 4; };
+template <> struct Group<__half> { static constexpr int n = 8; };
+
+__device__ __forceinline__ void ld_group(const float *p, size_t q, float (&v)[4]) {
+    const float4 t = reinterpret_cast<const float4 *>(p)[q];
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void ld_group(const __half *p, size_t q, float (&v)[8]) {
+    const uint4 r = reinterpret_cast<const uint4 *>(p)[q];
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float2 f = __half22float2(__builtin_bit_cast(__half2, w[k]));
+        v[2 * k] = f.x; v[2 * k + 1] = f.y;
+    }
+}
+// z (always FP32) for group q of GE elements
+template <int GE>
+__device__ __forceinline__ void ld_z(const float *p, size_t q, float (&v)[GE]) {
+#pragma unroll
+    for (int k = 0; k < GE / 4; ++k) {
+        const float4 t = reinterpret_cast<const float4 *>(p)[q * (GE / 4) + k];
+        v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+    }
+}
+template <int GE>
+__device__ __forceinline__ void st_z(float *p, size_t q, const float (&v)[GE]) {
+#pragma unroll
+    for (int k = 0; k < GE / 4; ++k)
+        reinterpret_cast<float4 *>(p)[q * (GE / 4) + k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
 }
 // Store a group: FP32 as is; FP16 as round-to-nearest of scale * v (the
 // scale is a power of two, so the product is exact in FP32).
-__device__ __forceinline__ void st_group(float *p, size_t q, float4 v, float) {
-    reinterpret_cast<float4 *>(p)[q] = v;
+__device__ __forceinline__ void st_group(float *p, size_t q, const float (&v)[4], float) { st_z<4>(p, q, v); }
+__device__ __forceinline__ void st_group(__half *p, size_t q, const float (&v)[8], float scale) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w[k] = __builtin_bit_cast(uint32_t, __floats2half2_rn(scale * v[2 * k], scale * v[2 * k + 1]));
+    reinterpret_cast<uint4 *>(p)[q] = make_uint4(w[0], w[1], w[2], w[3]);
 }
-__device__ __forceinline__ void st_group(__half *p, size_t q, float4 v, float scale) {
-    const __half2 a = __floats2half2_rn(scale * v.x, scale * v.y), b = __floats2half2_rn(scale * v.z, scale * v.w);
-    reinterpret_cast<uint2 *>(p)[q] = make_uint2(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b));
-}
+// FP32 output of an FP16-basis sweep (a partial z of several chunks)
+__device__ __forceinline__ void st_group(float *p, size_t q, const float (&v)[8], float) { st_z<8>(p, q, v); }
 __device__ __forceinline__ float ld_elem(const float *p, size_t i) { return p[i]; }
 __device__ __forceinline__ float ld_elem(const __half *p, size_t i) { return __half2float(p[i]); }
 __device__ __forceinline__ void st_elem(float *p, size_t i, float v, float) { p[i] = v; }
 __device__ __forceinline__ void st_elem(__half *p, size_t i, float v, float scale) { p[i] = __float2half_rn(scale * v); }
 
-// Multi-dot over groups q0 + tid, q0 + tid + qstep, ... < q1:
-// acc[j] += W[vlo+j] . z, nacc += z . z, all in FP64 (products of FP32
-// values are exact in FP64).
+// Multi-dot over groups q0 + tid, q0 + tid + qstep, ... < q1 (groups of
+// Group<WT>::n elements): acc[j] += W[vlo+j] . z, nacc += z . z, all in
+// FP64 (products of FP32 values are exact in FP64).
 template <int NV, typename WT>
 __device__ __forceinline__ void mdot_groups(const WT *__restrict__ Wc, size_t ldw, int cnt,
                                             const float *__restrict__ z, size_t q0, size_t q1, size_t qstep,
                                             double (&acc)[NV], double &nacc) {
+    constexpr int GE = Group<WT>::n;
     for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
-        const float4 zv = reinterpret_cast<const float4 *>(z)[q];
-        const double z0 = zv.x, z1 = zv.y, z2 = zv.z, z3 = zv.w;
-        nacc += z0 * z0 + z1 * z1 + z2 * z2 + z3 * z3;
+        float zf[GE];
+        ld_z<GE>(z, q, zf);
+        double zd[GE], zz = 0.0;
+#pragma unroll
+        for (int e = 0; e < GE; ++e) { zd[e] = zf[e]; zz += zd[e] * zd[e]; }
+        nacc += zz;
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                const float4 w = ld_group(Wc + (size_t)j * ldw, q);
-                acc[j] += (double)w.x * z0 + (double)w.y * z1 + (double)w.z * z2 + (double)w.w * z3;
+                float w[GE];
+                ld_group(Wc + (size_t)j * ldw, q, w);
+                double d = 0.0;
+#pragma unroll
+                for (int e = 0; e < GE; ++e) d += (double)w[e] * zd[e];
+                acc[j] += d;
             }
     }
 }
@@ -115,19 +151,28 @@ template <int NV, typename WT, typename OT>
 __device__ __forceinline__ void maxpy_groups(const WT *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
                                              double zs, const float *zin, OT *zout, float oscale, size_t q0,
                                              size_t q1, size_t qstep, double &nacc) {
+    constexpr int GE = Group<WT>::n;
     for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
-        const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
-        double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
+        float zf[GE];
+        ld_z<GE>(zin, q, zf);
+        double u[GE];
+#pragma unroll
+        for (int e = 0; e < GE; ++e) u[e] = zs * (double)zf[e];
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                const float4 w = ld_group(Wc + (size_t)j * ldw, q);
+                float w[GE];
+                ld_group(Wc + (size_t)j * ldw, q, w);
                 const double c = cf[j];
-                u0 -= c * (double)w.x; u1 -= c * (double)w.y; u2 -= c * (double)w.z; u3 -= c * (double)w.w;
+#pragma unroll
+                for (int e = 0; e < GE; ++e) u[e] -= c * (double)w[e];
             }
-        const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
+        float o[GE];
+        double oo = 0.0;
+#pragma unroll
+        for (int e = 0; e < GE; ++e) { o[e] = (float)u[e]; oo += (double)o[e] * o[e]; }
+        nacc += oo;
         st_group(zout, q, o, oscale);
-        nacc += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
     }
 }
 
@@ -139,24 +184,36 @@ template <int NV, typename WT>
 __device__ __forceinline__ void maxpy_dot_groups(const WT *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
                                                  double zs, const float *zin, float *zout, size_t q0, size_t q1,
                                                  size_t qstep, double (&acc)[NV], double &nacc) {
+    constexpr int GE = Group<WT>::n;
     for (size_t q = q0 + threadIdx.x; q < q1; q += qstep) {
-        const float4 zv = reinterpret_cast<const float4 *>(zin)[q];
-        double u0 = zs * (double)zv.x, u1 = zs * (double)zv.y, u2 = zs * (double)zv.z, u3 = zs * (double)zv.w;
-        float4 w[NV];
+        float zf[GE];
+        ld_z<GE>(zin, q, zf);
+        double u[GE];
+#pragma unroll
+        for (int e = 0; e < GE; ++e) u[e] = zs * (double)zf[e];
+        float w[NV][GE];
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                w[j] = ld_group(Wc + (size_t)j * ldw, q);
+                ld_group(Wc + (size_t)j * ldw, q, w[j]);
                 const double c = cf[j];
-                u0 -= c * (double)w[j].x; u1 -= c * (double)w[j].y; u2 -= c * (double)w[j].z; u3 -= c * (double)w[j].w;
+#pragma unroll
+                for (int e = 0; e < GE; ++e) u[e] -= c * (double)w[j][e];
             }
-        const float4 o = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
-        reinterpret_cast<float4 *>(zout)[q] = o;
-        const double o0 = o.x, o1 = o.y, o2 = o.z, o3 = o.w;
-        nacc += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
+        float o[GE];
+        double od[GE], oo = 0.0;
+#pragma unroll
+        for (int e = 0; e < GE; ++e) { o[e] = (float)u[e]; od[e] = o[e]; oo += od[e] * od[e]; }
+        nacc += oo;
+        st_z<GE>(zout, q, o);
 #pragma unroll
         for (int j = 0; j < NV; ++j)
-            if (j < cnt) acc[j] += (double)w[j].x * o0 + (double)w[j].y * o1 + (double)w[j].z * o2 + (double)w[j].w * o3;
+            if (j < cnt) {
+                double d = 0.0;
+#pragma unroll
+                for (int e = 0; e < GE; ++e) d += (double)w[j][e] * od[e];
+                acc[j] += d;
+            }
     }
 }
 
