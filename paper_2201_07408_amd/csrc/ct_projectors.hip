@@ -421,7 +421,27 @@ __device__ __forceinline__ int wave_max(int v) {
 // neighbouring views, whose footprints overlap, and the XCD's L2 serves the
 // overlap.  vgrp views form a group (the launch picks it, see
 // launch_staged).  Returns false for the padding workgroups of the last XCD.
+//
+// A negative vgrp selects the band order for volumes beyond the last-level
+// cache: groups of -vgrp views, ordered [tile row][view group][tile column]
+// [view in group], dealt to the XCDs in runs of one group's tile row (run r
+// to XCD r mod 8).  All XCDs then work on the same band of detector rows,
+// whose rays cross one slab of the volume, for eight neighbouring view
+// groups at a time, so the slab stays in the last-level cache while every
+// view passes it; within an XCD the L2 sharing of the same tile across a
+// group's views is as before.
 __device__ __forceinline__ bool xcd_tile(int ntu, int ntv, int P, int vgrp, int &tu, int &tv, int &p) {
+    if (vgrp < 0) {
+        const int G = -vgrp, ngrp = (P + G - 1) / G, run = ntu * G;
+        const int nlog = ntv * ngrp * run;
+        const int b = blockIdx.x, i = b >> 3;
+        const int lg = ((i / run) * 8 + (b & 7)) * run + i % run;
+        if (lg >= nlog) return false;
+        tu = (lg / G) % ntu;
+        tv = lg / (run * ngrp);
+        p = ((lg / run) % ngrp) * G + lg % G;
+        return p < P;
+    }
     const int ntiles = ntu * ntv;
     const int ngrp = (P + vgrp - 1) / vgrp;
     const int nlog = ngrp * ntiles * vgrp;
@@ -1901,10 +1921,16 @@ static unsigned lds_for_occupancy(const void *kernel, int target) {
 // with 180 views: groups of ten at 7, 5, 4, 3 and 2 workgroups per CU took
 // 77.2, 68.0, 63.2, 64.1 and 80.3 ms; at four per CU, groups of 2, 3, 4, 6,
 // 8, 16 and 24 took 56.4, 54.2, 55.4, 55.3, 58.1, 70.7 and 77.3 ms (groups
-// of 3 at 3, 5 and 7 per CU: 62.2 (groups of 4), 58.7, 85.9).
+// of 3 at 3, 5 and 7 per CU: 62.2 (groups of 4), 58.7, 85.9).  The band
+// order (xcd_tile, negative vgrp) then keeps the slab of the volume that a
+// band of detector rows sees in the last-level cache: at four per CU,
+// groups of 1, 2, 3, 4, 6, 8, 10 and 12 took 80.2, 53.6, 49.4, 47.9, 49.1,
+// 52.2, 54.8 and 60.5 ms, against 54.7 ms for the XCD-contiguous order with
+// groups of six (groups of 6 at 3, 5 and 8 per CU: 53.5, 58.5, 81.7; the
+// band order without view groups, views innermost across XCDs: 86.4).
 constexpr double kLlcBytes = 256.0 * 1024 * 1024;
 constexpr int kVGrpCached = 10;
-constexpr int kVGrpBig = 6;
+constexpr int kVGrpBig = -4;   // band order, groups of four views
 constexpr int kBigVolumeWgPerCu = 4;
 
 static int staged_view_group(const ct_geometry *g) {
@@ -1939,8 +1965,16 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
         // 16 x 16 ray tiles, flat grid remapped per XCD inside the kernel
         const long ntiles = (long)staged_tile_cols(g->k.nu) * ((g->k.nv + kTV - 1) / kTV);
         const int vgrp = staged_view_group(g);
-        const long nlog = (long)((g->k.P + vgrp - 1) / vgrp) * ntiles * vgrp;
-        const long per = (nlog + 7) / 8;
+        long per;   // workgroups per XCD
+        if (vgrp < 0) {
+            // band order: whole runs of one group's tile row per XCD
+            const long G = -vgrp, run = (long)staged_tile_cols(g->k.nu) * G;
+            const long nlog = (long)((g->k.nv + kTV - 1) / kTV) * ((g->k.P + G - 1) / G) * run;
+            per = (nlog + 8 * run - 1) / (8 * run) * run;
+        } else {
+            const long nlog = (long)((g->k.P + vgrp - 1) / vgrp) * ntiles * vgrp;
+            per = (nlog + 7) / 8;
+        }
         if (8 * per > 2147483647L) {
             set_error("launch_project: too many ray tiles");
             return CT_ERR_UNSUPPORTED;

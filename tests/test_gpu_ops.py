@@ -150,6 +150,23 @@ def test_project_A_axis_switch_views(projector):
     assert rel(y, oracle.project_A(desc, x)) <= TOL
 
 
+@pytest.mark.parametrize("projector", [0, 1])
+def test_project_A_volume_beyond_last_level_cache(projector):
+    """A volume whose two padded copies exceed the 256 MB last-level cache
+    (384 x 384 x 232, 281 MB of copies) is projected in the band order with
+    groups of four views; 7 views (a partial last group) of a ragged 77 x 53
+    detector whose pitch makes it span the whole volume: every ray must
+    match the oracle."""
+    desc = cone3d(384, 7, 77, nv=53, nz=232, pitch=10.0, projector=projector)
+    g = ct.Geometry(desc)
+    say("A beyond the last-level cache", projector)
+    x = f32(np.random.default_rng(10).uniform(0, 1, size=desc.vol_shape))
+    y = host(ct.ct_project_A(g, dev(x)))
+    ref = oracle.project_A(desc, x)
+    assert np.count_nonzero(ref) > 0.5 * ref.size
+    assert rel(y, ref) <= TOL
+
+
 def test_batch_equals_single_calls(geoms):
     desc, g = geoms["cone_24"]
     rng = np.random.default_rng(6)
