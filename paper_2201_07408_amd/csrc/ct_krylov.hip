@@ -730,10 +730,13 @@ int gmres_impl(const ct_geometry *g, int solver, const float *b, float *x, const
         }
         const int nvec = k + 1;
         CT_TRY(run_cgs(0, bf, nvec, bf.z, nullptr, nullptr, nullptr, s));
-        hipLaunchKernelGGL(k_gmres_red1, dim3(1), dim3(256), sizeof(double) * (nvec + 1), s, st, nblk, k);
+        // one wavefront per column of block partials, sixteen wavefronts: the
+        // column sums are latency-bound loops, and each column's order of
+        // summation does not depend on the number of wavefronts
+        hipLaunchKernelGGL(k_gmres_red1, dim3(1), dim3(1024), sizeof(double) * (nvec + 1), s, st, nblk, k);
         CT_LAUNCH_CHECK();
         CT_TRY(run_cgs(1, bf, nvec, bf.z, wn, st.coef, st.misc + M_ZS, s));
-        hipLaunchKernelGGL(k_gmres_red2, dim3(1), dim3(256), sizeof(double) * (nvec + 1), s, st, nblk, k, blen);
+        hipLaunchKernelGGL(k_gmres_red2, dim3(1), dim3(1024), sizeof(double) * (nvec + 1), s, st, nblk, k, blen);
         CT_LAUNCH_CHECK();
         CT_TRY(run_cgs(2, bf, nvec, wn, wn, st.coef, nullptr, s, bf.w16 ? bf.wh(k + 1) : nullptr));
         hipLaunchKernelGGL(k_gmres_red3, dim3(1), dim3(64), 0, s, st, nblk, k, tol, qc);
