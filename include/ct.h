@@ -166,8 +166,10 @@ int ct_backproject_B(const ct_geometry *g, const void *y, int y_dtype, float *x,
                      void *stream);
 
 /* x = A^T y, the exact transpose of ct_project_A (Sec. I: CGLS requires
- * B = A^T).  Scatter form with FP32 atomics: results are deterministic only
- * up to FP32 summation order.  ws: >= ct_op_workspace_bytes(CT_OP_AT). */
+ * B = A^T).  Gathered per voxel (each voxel sums the weighted values of the
+ * rays whose samples touch it, in a fixed order, without atomics), so the
+ * result is the same bits on every run.
+ * ws: >= ct_op_workspace_bytes(CT_OP_AT). */
 int ct_backproject_AT(const ct_geometry *g, const void *y, int y_dtype, float *x,
                       int batch, void *ws, size_t ws_bytes, void *stream);
 
@@ -177,7 +179,7 @@ int ct_ramp_filter(const ct_geometry *g, const float *q, float *y, int batch,
                    void *stream);
 
 /* One-shot filtered back-projection, the reference reconstruction the paper
- * compares against (Sec. IV), built from B_un and F:
+ * compares against (Sec. III), built from B_un and F:
  *   2D parallel beam:  x = (pi/P) (du/d^2) B_un F y;
  *   3D circular cone:  x = (pi/P) (SOD/SDD) (du dv/d^3) B_un F (w . y),
  *     w = SDD / sqrt(SDD^2 + u^2 + v^2) (Feldkamp-Davis-Kress cosine
@@ -205,7 +207,7 @@ int ct_ba_gmres(const ct_geometry *g, const float *b, float *x,
                 double *res_hist, int *iters_done, void *stream);
 
 /* BA-GMRES as ct_ba_gmres, plus the per-iteration curves the paper plots
- * (Sec. IV: data residual and image error against the iteration number),
+ * (Sec. III, Figs. 2 and 4: data residual and image error against the iteration number),
  * without applying A again: the projections A w_k computed by the
  * iteration are kept (n_views*nv*nu floats per iteration in the
  * workspace; query with solver CT_SOLVER_BA_MONITOR) and combined with the

@@ -192,7 +192,7 @@ def ramp(g, y) -> np.ndarray:
 
 def fbp(g, y) -> np.ndarray:
     """One-shot filtered back-projection with the paper's B_un and F (the
-    reference reconstruction it compares against, Sec. IV), scaled to
+    reference reconstruction it compares against, Sec. III), scaled to
     approximate the inverse Radon / cone-beam transform:
       2D parallel beam:  x = (pi / P) (du / vox^2) B_un F y
          (the ramp-filtered projection interpolated at x . n and summed over

@@ -678,7 +678,11 @@ extern "C" int ct_ba_gmres_batched(const ct_geometry *const *g, int count, const
 
     if (g_use_graph) {
         std::ostringstream key;
-        key << shape << '|' << ws << '|' << P.K << '|' << tol << '|' << tl.a << ',' << tl.b;
+        // tol is baked into the captured kernel arguments: key on its exact bits
+        uint64_t tol_bits;
+        std::memcpy(&tol_bits, &tol, sizeof(tol_bits));
+        key << shape << '|' << ws << '|' << P.K << '|' << std::hex << tol_bits << std::dec << '|' << tl.a
+            << ',' << tl.b;
         hipGraphExec_t exec = nullptr;
         CT_TRY(graph_for(key.str(), dev, P, d, tl, tol, exec));
         CT_HIP_CHECK(hipGraphLaunch(exec, s));

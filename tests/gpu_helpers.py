@@ -34,6 +34,52 @@ def rel(a, b) -> float:
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
+def elem_err(a, b):
+    """Largest element-wise distance relative to the largest reference
+    element: max_i |a_i - b_i| / max_i |b_i|, and the index where it
+    occurs.  Unlike the 2-norm distance, a defect confined to a few
+    elements is not diluted by the size of the whole vector."""
+    a = np.asarray(a, np.float64).reshape(-1)
+    b = np.asarray(b, np.float64).reshape(-1)
+    if a.size == 0:
+        return 0.0, -1
+    d = np.abs(a - b)
+    i = int(np.argmax(d))
+    nb = float(np.max(np.abs(b)))
+    return float(d[i] / (nb if nb > 0 else 1.0)), i
+
+
+def assert_close(a, b, tol, what="", elem_tol=None):
+    """Both bounds at once: the relative 2-norm distance <= tol and every
+    element within elem_tol (default tol) times the largest reference
+    element.  The message names the worst element."""
+    e2 = rel(a, b)
+    ei, i = elem_err(a, b)
+    et = tol if elem_tol is None else elem_tol
+    a1 = np.asarray(a, np.float64).reshape(-1)
+    b1 = np.asarray(b, np.float64).reshape(-1)
+    msg = "%s: rel 2-norm %.3e (tol %.1e), worst element %d: %.9g vs %.9g, %.3e of max|ref| (tol %.1e)" % (
+        what, e2, tol, i, a1[i] if i >= 0 else 0.0, b1[i] if i >= 0 else 0.0, ei, et)
+    say(msg)
+    assert e2 <= tol and ei <= et, msg
+    return e2, ei
+
+
+def assert_hist_close(a, b, tol, what=""):
+    """Residual histories: every entry within tol of the reference entry,
+    relative to that entry (late, small residuals are not hidden behind the
+    first one)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    r = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+    k = int(np.argmax(r))
+    msg = "%s: residual history worst entry k=%d: %.9g vs %.9g (rel %.3e, tol %.1e)" % (what, k, a[k], b[k], r[k], tol)
+    say(msg)
+    assert r[k] <= tol, msg
+    return float(r[k])
+
+
 # small geometries spanning several tiles with ragged tails
 SMALL_GEOMS = {
     "w1_2d_64": parallel2d(64, 90, 96),
@@ -42,7 +88,49 @@ SMALL_GEOMS = {
     "cone_24": cone3d(24, 20, 36),
     "ragged_cone": GeometryDesc(CONE_3D, 33, 30, 17, 1.0, 13, 45, 29, 1.7, 2.3, 140.0, 290.0),
     "cone_45deg_views": cone3d(20, 8, 30),   # views at multiples of 45 deg
+    # P divisible by 4: views at exactly 45 and 135 deg, where the dominant
+    # axis is decided by the integer tie rule (x-major iff P <= 4p <= 3P)
+    "exact45_2d": parallel2d(64, 180, 96),
 }
+
+
+def special_rays(desc, views=None, rows=None):
+    """Ray indices where tiling decisions of a cone-beam projector change:
+    the detector's first and last columns and rows, the columns on both
+    sides of each view's dominant-axis switch (where the in-plane direction
+    has |r_x| = |r_y|), and row and column indices around multiples of 16.
+    Computed from the geometry's definition in FP64 on the host."""
+    P, nv, nu = desc.sino_shape
+    if views is None:
+        views = sorted(set([0, P - 1, P // 8, P // 4, (3 * P) // 8, P // 2] + list(range(0, P, max(1, P // 24)))))
+    if rows is None:
+        rows = sorted(set(r for r in [0, 1, 15, 16, 17, nv // 2, nv - 17, nv - 16, nv - 2, nv - 1] if 0 <= r < nv))
+    angles = np.asarray(desc.angles, np.float64) if desc.angles is not None else \
+        np.array([(2.0 * np.pi * p) / P for p in range(P)])
+    u = (np.arange(nu) - 0.5 * (nu - 1)) * desc.du
+
+    def switches(p):
+        c, s = np.cos(angles[p]), np.sin(angles[p])
+        ax = np.abs(-desc.sdd * c - u * s) >= np.abs(-desc.sdd * s + u * c)
+        return np.nonzero(ax[1:] != ax[:-1])[0]
+
+    # add up to eight views whose switch column lies inside the detector
+    with_switch = [p for p in range(P) if len(switches(p)) > 0]
+    views = sorted(set(views) | set(with_switch[::max(1, len(with_switch) // 8)]))
+    ids = set()
+    for p in views:
+        c, s = np.cos(angles[p]), np.sin(angles[p])
+        rx = -desc.sdd * c - u * s
+        ry = -desc.sdd * s + u * c
+        ax = np.abs(rx) >= np.abs(ry)
+        cols = {0, 1, nu - 2, nu - 1, 15, 16, nu - 17, nu - 16}
+        for a in np.nonzero(ax[1:] != ax[:-1])[0]:
+            cols.update({a - 1, a, a + 1, a + 2})
+        for a in cols:
+            if 0 <= a < nu:
+                for r in rows:
+                    ids.add((p * nv + r) * nu + a)
+    return np.array(sorted(ids), dtype=np.int64)
 
 
 def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0, basis="f64"):

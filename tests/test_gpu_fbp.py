@@ -8,7 +8,7 @@ import torch
 import oracle
 import paper_2201_07408_amd as ct
 from synth.geometry import GeometryDesc, parallel2d, cone3d, CONE_3D
-from tests.gpu_helpers import dev, f32, host, rel, say
+from tests.gpu_helpers import assert_close, dev, f32, host, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def test_fbp_matches_oracle(name):
     g = ct.Geometry(desc)
     y = f32(np.random.default_rng(31).uniform(size=desc.sino_shape))
     say("fbp", name)
-    assert rel(host(ct.ct_fbp(g, dev(y))), oracle.fbp(desc, y)) <= 1e-5
+    assert_close(host(ct.ct_fbp(g, dev(y))), oracle.fbp(desc, y), 1e-5, "fbp " + name)
 
 
 def test_fbp_half_input_and_batch():
@@ -37,4 +37,4 @@ def test_fbp_half_input_and_batch():
     xb = host(ct.ct_fbp(g, yh))
     for i in range(2):
         ref = oracle.fbp(desc, yh[i].float().cpu().numpy())
-        assert rel(xb[i], ref) <= 1e-5
+        assert_close(xb[i], ref, 1e-5, "fbp half item %d" % i)

@@ -1,6 +1,8 @@
 """GPU operator parity with the FP64 oracle (same seeded FP32 inputs).
 
-Tolerance: relative 2-norm error <= 1e-5 for FP32 outputs.  Derivation: the
+Tolerance: relative 2-norm error <= 1e-5 for FP32 outputs, and every
+element within 1e-5 of the largest reference element (so that a defect in
+a few rays or voxels cannot hide in the norm of the whole output).  Derivation: the
 kernels evaluate each sample position in FP32 from FP64 per-ray set-up, so
 the interpolation weights carry errors of a few units of 2^-24 times the
 coordinate magnitude (<= 2^9 voxels here), i.e. <= 3e-5 per weight at worst
@@ -17,7 +19,7 @@ import oracle
 import paper_2201_07408_amd as ct
 from synth import workloads
 from synth.geometry import GeometryDesc, PARALLEL_2D, cone3d
-from tests.gpu_helpers import SMALL_GEOMS, dev, f32, host, rel, say
+from tests.gpu_helpers import SMALL_GEOMS, assert_close, dev, f32, host, rel, say, special_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +39,7 @@ def test_project_A(geoms, name):
     x = f32(np.random.default_rng(1).uniform(0, 1, size=desc.vol_shape))
     y = host(ct.ct_project_A(g, dev(x)))
     ref = oracle.project_A(desc, x)
-    assert rel(y, ref) <= TOL
+    assert_close(y, ref, TOL, "A " + name)
 
 
 @pytest.mark.parametrize("name", list(SMALL_GEOMS))
@@ -46,7 +48,7 @@ def test_backproject_B(geoms, name):
     say("B parity", name)
     y = f32(np.random.default_rng(2).uniform(0, 1, size=desc.sino_shape))
     x = host(ct.ct_backproject_B(g, dev(y)))
-    assert rel(x, oracle.backproject_Bun(desc, y)) <= TOL
+    assert_close(x, oracle.backproject_Bun(desc, y), TOL, "B_un " + name)
 
 
 @pytest.mark.parametrize("name", list(SMALL_GEOMS))
@@ -56,7 +58,7 @@ def test_backproject_AT(geoms, name):
     rng = np.random.default_rng(3)
     y = f32(rng.uniform(0, 1, size=desc.sino_shape))
     x = host(ct.ct_backproject_AT(g, dev(y)))
-    assert rel(x, oracle.backproject_AT(desc, y)) <= TOL
+    assert_close(x, oracle.backproject_AT(desc, y), TOL, "A^T " + name)
     # adjoint identity of the GPU pair itself
     v = f32(rng.standard_normal(desc.vol_shape))
     w = f32(rng.standard_normal(desc.sino_shape))
@@ -72,9 +74,9 @@ def test_ramp_and_filtered_backprojection(geoms, name):
     y = f32(np.random.default_rng(4).uniform(0, 1, size=desc.sino_shape))
     f = host(ct.ct_ramp_filter(g, dev(y)))
     fref = oracle.ramp(desc, y)
-    assert rel(f, fref) <= TOL
+    assert_close(f, fref, TOL, "F " + name)
     x = host(ct.ct_backproject_B(g, dev(y), ramp=True))
-    assert rel(x, oracle.backproject_Bun(desc, oracle.ramp(desc, y))) <= TOL
+    assert_close(x, oracle.backproject_Bun(desc, oracle.ramp(desc, y)), TOL, "B_FBP " + name)
 
 
 @pytest.mark.parametrize("nu", [1, 2, 15, 33, 96, 385, 768, 769, 896, 897, 1088, 1089, 1600, 1601, 2048, 4096])
@@ -88,7 +90,7 @@ def test_ramp_row_lengths(nu):
     g = ct.Geometry(desc)
     say("F row length", nu)
     y = f32(np.random.default_rng(nu).normal(size=desc.sino_shape))
-    assert rel(host(ct.ct_ramp_filter(g, dev(y))), oracle.ramp(desc, y)) <= TOL
+    assert_close(host(ct.ct_ramp_filter(g, dev(y))), oracle.ramp(desc, y), TOL, "F nu=%d" % nu)
 
 
 @pytest.mark.parametrize("name", ["w1_2d_64", "cone_24", "ragged_cone"])
@@ -99,12 +101,15 @@ def test_fp16_storage(geoms, name):
     y16 = ct.ct_project_A(g, dev(x), y_dtype=torch.float16)
     assert y16.dtype == torch.float16
     ref = oracle.project_A(desc, x)
-    assert rel(host(y16), ref) <= 2.0 ** -11
+    # each element rounded once to FP16: within 2^-11 of itself
+    yh = host(y16).reshape(-1)
+    assert np.all(np.abs(yh - ref) <= 2.0 ** -11 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+    assert rel(yh, ref) <= 2.0 ** -11
     xb = host(ct.ct_backproject_B(g, y16))
     ref_b = oracle.backproject_Bun(desc, host(y16))   # same FP16-rounded data
-    assert rel(xb, ref_b) <= TOL
+    assert_close(xb, ref_b, TOL, "B_un FP16 data " + name)
     xt = host(ct.ct_backproject_AT(g, y16))
-    assert rel(xt, oracle.backproject_AT(desc, host(y16))) <= TOL
+    assert_close(xt, oracle.backproject_AT(desc, host(y16)), TOL, "A^T FP16 data " + name)
 
 
 @pytest.mark.parametrize("projector", [0, 1])
@@ -119,7 +124,7 @@ def test_project_A_small_shadow(projector):
     x = f32(np.random.default_rng(8).uniform(0, 1, size=desc.vol_shape))
     y = host(ct.ct_project_A(g, dev(x))).reshape(desc.sino_shape)
     ref = np.asarray(oracle.project_A(desc, x)).reshape(desc.sino_shape)
-    assert rel(y, ref) <= TOL
+    assert_close(y, ref, TOL, "A small shadow")
     # exact zeros away from the edge of the shadow (pixels whose 3 x 3
     # neighbourhood is zero in the oracle), where rounding cannot decide
     # whether a grazing ray picks up a sample
@@ -147,7 +152,7 @@ def test_project_A_axis_switch_views(projector):
     say("A axis-switch views", projector)
     x = f32(np.random.default_rng(9).uniform(0, 1, size=desc.vol_shape))
     y = host(ct.ct_project_A(g, dev(x)))
-    assert rel(y, oracle.project_A(desc, x)) <= TOL
+    assert_close(y, oracle.project_A(desc, x), TOL, "A axis-switch views")
 
 
 @pytest.mark.parametrize("projector", [0, 1])
@@ -164,7 +169,7 @@ def test_project_A_volume_beyond_last_level_cache(projector):
     y = host(ct.ct_project_A(g, dev(x)))
     ref = oracle.project_A(desc, x)
     assert np.count_nonzero(ref) > 0.5 * ref.size
-    assert rel(y, ref) <= TOL
+    assert_close(y, ref, TOL, "A beyond the last-level cache")
 
 
 def test_batch_equals_single_calls(geoms):
@@ -189,20 +194,28 @@ def test_empty_batch(geoms):
 
 # ------------------------------------------------ full workload sizes
 def _sampled_parity(desc, g, vol, nsamp=3000, seed=7):
+    """Random rays and voxels, plus the rays where the projector's tiling
+    decisions change (detector edges, where the view's tiles are partial,
+    the columns around each view's dominant-axis switch, where the tile
+    columns are offset, and rows and columns around tile boundaries), and
+    the volume's corner and edge voxels."""
     rng = np.random.default_rng(seed)
     y = ct.ct_project_A(g, dev(vol))
     yh = host(y).reshape(-1)
-    rays = rng.choice(desc.n_rays, size=nsamp, replace=False)
+    rays = np.union1d(rng.choice(desc.n_rays, size=nsamp, replace=False), special_rays(desc))
     ref = oracle.project_A_rays(desc, vol, rays)
-    assert rel(yh[rays], ref) <= TOL
+    assert_close(yh[rays], ref, TOL, "A sampled rays")
     x = host(ct.ct_backproject_B(g, y)).reshape(-1)
-    vox = rng.choice(desc.n_vox, size=nsamp, replace=False)
+    nz, ny, nx = desc.vol_shape
+    edge = [(z * ny + yy) * nx + xx for z in (0, nz // 2, nz - 1) for yy in (0, ny // 2, ny - 1)
+            for xx in (0, 1, nx // 2, nx - 2, nx - 1)]
+    vox = np.union1d(rng.choice(desc.n_vox, size=nsamp, replace=False), np.array(edge, np.int64))
     refb = oracle.backproject_Bun_voxels(desc, f32(yh), vox)
-    assert rel(x[vox], refb) <= TOL
+    assert_close(x[vox], refb, TOL, "B_un sampled voxels")
     xr = host(ct.ct_backproject_B(g, y, ramp=True)).reshape(-1)
     fy = oracle.ramp(desc, f32(yh))
     refr = oracle.backproject_Bun_voxels(desc, fy, vox)
-    assert rel(xr[vox], refr) <= TOL
+    assert_close(xr[vox], refr, TOL, "B_FBP sampled voxels")
 
 
 def test_w2_full_size_sampled():

@@ -17,7 +17,7 @@ import paper_2201_07408_amd as ct
 from synth import workloads
 from synth.phantoms import random_ellipsoids, rasterize_ellipsoids
 from synth.geometry import cone3d
-from tests.gpu_helpers import dev, f32, fp32_envelope, host, rel, say
+from tests.gpu_helpers import assert_close, assert_hist_close, dev, f32, fp32_envelope, host, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -42,10 +42,12 @@ def cone_small():
     return desc, ct.Geometry(desc), b
 
 
-def _compare(res_gpu, ref, x_tol=TOL):
+def _compare(res_gpu, ref, x_tol=TOL, what="", hist_tol=TOL):
+    """Iterate: relative 2-norm and every voxel against the largest one;
+    residual history: every entry relative to itself."""
     assert res_gpu.iters_done == ref.iters_done
-    assert rel(host(res_gpu.x), ref.x) <= x_tol, rel(host(res_gpu.x), ref.x)
-    assert rel(np.array(res_gpu.res), np.array(ref.res)) <= TOL
+    assert_close(host(res_gpu.x), ref.x, x_tol, what + " x")
+    assert_hist_close(res_gpu.res, ref.res, hist_tol, what)
 
 
 # At 15 iterations FP32 arithmetic moves these iterates by under 4e-5
@@ -56,18 +58,22 @@ def _compare(res_gpu, ref, x_tol=TOL):
 def test_ba_gmres_w1(w1, B):
     desc, g, b = w1
     say("BA-GMRES W1", B)
-    _compare(ct.ct_ba_gmres(g, dev(b), 15, B=B), oracle.ba_gmres(desc, b, 15, B=B))
+    _compare(ct.ct_ba_gmres(g, dev(b), 15, B=B), oracle.ba_gmres(desc, b, 15, B=B), what="BA %s k=15" % B)
     r = ct.ct_ba_gmres(g, dev(b), 30, B=B)
-    _compare(r, oracle.ba_gmres(desc, b, 30, B=B), max(TOL, 3.0 * fp32_envelope(desc, b, 30, B)))
+    env = fp32_envelope(desc, b, 30, B)
+    say("BA-GMRES W1 %s k=30 FP32 envelope %.3e" % (B, env))
+    _compare(r, oracle.ba_gmres(desc, b, 30, B=B), max(TOL, 3.0 * env), "BA %s k=30" % B)
 
 
 @pytest.mark.parametrize("B", ["un", "ramp"])
 def test_ab_gmres_w1(w1, B):
     desc, g, b = w1
     say("AB-GMRES W1", B)
-    _compare(ct.ct_ab_gmres(g, dev(b), 15, B=B), oracle.ab_gmres(desc, b, 15, B=B))
+    _compare(ct.ct_ab_gmres(g, dev(b), 15, B=B), oracle.ab_gmres(desc, b, 15, B=B), what="AB %s k=15" % B)
     r = ct.ct_ab_gmres(g, dev(b), 30, B=B)
-    _compare(r, oracle.ab_gmres(desc, b, 30, B=B), max(TOL, 3.0 * fp32_envelope(desc, b, 30, B, "ab")))
+    env = fp32_envelope(desc, b, 30, B, "ab")
+    say("AB-GMRES W1 %s k=30 FP32 envelope %.3e" % (B, env))
+    _compare(r, oracle.ab_gmres(desc, b, 30, B=B), max(TOL, 3.0 * env), "AB %s k=30" % B)
 
 
 def test_cgls_AT_w1(w1):
@@ -79,7 +85,7 @@ def test_cgls_AT_w1(w1):
     ||b - A x_30|| must agree to 2 % and x to 3 %."""
     desc, g, b = w1
     say("CGLS(A^T) W1")
-    _compare(ct.ct_cgls(g, dev(b), 6, B="AT"), oracle.cgls(desc, b, 6, B="AT"))
+    _compare(ct.ct_cgls(g, dev(b), 6, B="AT"), oracle.cgls(desc, b, 6, B="AT"), what="CGLS(A^T) k=6")
     r = ct.ct_cgls(g, dev(b), 30, B="AT")
     ref = oracle.cgls(desc, b, 30, B="AT")
     assert r.iters_done == 30
@@ -94,7 +100,7 @@ def test_cgls_unmatched_w1_reported(w1):
     first iterations only, for the reason given above."""
     desc, g, b = w1
     r = ct.ct_cgls(g, dev(b), 6, B="un")
-    _compare(r, oracle.cgls(desc, b, 6, B="un"))
+    _compare(r, oracle.cgls(desc, b, 6, B="un"), what="CGLS(B_un) k=6")
 
 
 @pytest.mark.parametrize("B", ["un", "ramp"])
@@ -102,14 +108,14 @@ def test_ba_gmres_cone_small(cone_small, B):
     desc, g, b = cone_small
     say("BA-GMRES cone 48^3", B)
     r = ct.ct_ba_gmres(g, dev(b), 20, B=B)
-    _compare(r, oracle.ba_gmres(desc, b, 20, B=B))
+    _compare(r, oracle.ba_gmres(desc, b, 20, B=B), what="BA cone 48^3 %s k=20" % B)
 
 
 def test_ab_gmres_and_cgls_cone_small(cone_small):
     desc, g, b = cone_small
     say("AB-GMRES / CGLS cone 48^3")
-    _compare(ct.ct_ab_gmres(g, dev(b), 12, B="un"), oracle.ab_gmres(desc, b, 12, B="un"))
-    _compare(ct.ct_cgls(g, dev(b), 6, B="AT"), oracle.cgls(desc, b, 6, B="AT"))
+    _compare(ct.ct_ab_gmres(g, dev(b), 12, B="un"), oracle.ab_gmres(desc, b, 12, B="un"), what="AB cone k=12")
+    _compare(ct.ct_cgls(g, dev(b), 6, B="AT"), oracle.cgls(desc, b, 6, B="AT"), what="CGLS(A^T) cone k=6")
 
 
 def test_ba_gmres_fp16_storage_w1(w1):
@@ -145,4 +151,7 @@ def test_ba_gmres_full_w3_properties():
     Ax = ct.ct_project_A(g, r.x)
     rr = Bb - ct.ct_backproject_B(g, Ax, ramp=True)
     true = float(torch.linalg.vector_norm(rr.double()))
-    assert abs(true - res[-1]) <= 1e-3 * res[0]
+    say("W3 recomputed residual %.6e, carried %.6e" % (true, res[-1]))
+    # relative to the last residual itself (a bound relative to res[0] would
+    # be wider than res[-1] once the residual has fallen below it)
+    assert abs(true - res[-1]) <= 2e-2 * res[-1]

@@ -375,3 +375,59 @@ def test_fdk_reconstructs_ball_midplane(oracle):
         centres.append(float(mid[n // 2 - 1:n // 2 + 1, n // 2 - 1:n // 2 + 1].mean()))
     assert max(errs) < 0.02, errs
     assert all(abs(c - 1.0) < 0.01 for c in centres), centres
+
+
+# ------------------------------------------- sampled evaluation of A, B_un
+# The full-size GPU tests and the benchmark check the GPU against the
+# oracle's sampled evaluations (selected rays of A, selected voxels of
+# B_un), so these must be the same numbers as the full operators pinned
+# above: bit for bit, at random indices and at the first and last ray or
+# voxel, for both geometries and both forward models.
+_SAMPLED_GEOMS = {
+    "2d": parallel2d(37, 45, 53),
+    "2d_siddon": parallel2d(29, 36, 41, projector=1),
+    "cone": cone3d(14, 9, 21, nz=11, nv=17),
+    "cone_siddon": cone3d(12, 7, 19, projector=1),
+}
+
+
+@pytest.mark.parametrize("name", list(_SAMPLED_GEOMS))
+def test_sampled_rays_equal_full_projection(oracle, name):
+    g = _SAMPLED_GEOMS[name]
+    rng = np.random.default_rng(31)
+    x = rng.uniform(0.0, 1.0, size=g.vol_shape)
+    full = oracle.project_A(g, x)
+    ids = np.concatenate([[0, g.n_rays - 1], rng.choice(g.n_rays, size=200, replace=False),
+                          [g.n_rays // 2, 0]])   # repeats are allowed
+    part = oracle.project_A_rays(g, x, ids)
+    assert np.count_nonzero(full[ids]) > 0.3 * ids.size
+    assert np.array_equal(part, full[ids])
+
+
+@pytest.mark.parametrize("name", ["2d", "cone"])
+def test_sampled_voxels_equal_full_backprojection(oracle, name):
+    g = _SAMPLED_GEOMS[name]
+    rng = np.random.default_rng(32)
+    y = rng.uniform(-1.0, 1.0, size=g.sino_shape)
+    full = oracle.backproject_Bun(g, y)
+    ids = np.concatenate([[0, g.n_vox - 1], rng.choice(g.n_vox, size=200, replace=False), [g.n_vox // 3]])
+    part = oracle.backproject_Bun_voxels(g, y, ids)
+    assert np.count_nonzero(full[ids]) > 0.9 * ids.size
+    assert np.array_equal(part, full[ids])
+
+
+def test_sampled_rays_cone_workload_proportions(oracle):
+    """The cone-beam workloads' proportions (detector 1.5 N, SOD = 4 N,
+    SDD = 8 N) at 32^3 and 18 views, on a random volume and on its own
+    projection: sampled rays and voxels, plus the first and last, equal the
+    full operators."""
+    from synth import workloads
+    g = workloads.w2_geometry(32, 18)
+    rng = np.random.default_rng(33)
+    x = rng.uniform(0.0, 1.0, size=g.vol_shape)
+    full = oracle.project_A(g, x)
+    ids = np.concatenate([[0, g.n_rays - 1], rng.choice(g.n_rays, size=500, replace=False)])
+    assert np.array_equal(oracle.project_A_rays(g, x, ids), full[ids])
+    fb = oracle.backproject_Bun(g, full)
+    vids = np.concatenate([[0, g.n_vox - 1], rng.choice(g.n_vox, size=500, replace=False)])
+    assert np.array_equal(oracle.backproject_Bun_voxels(g, full, vids), fb[vids])
