@@ -49,12 +49,33 @@ def elem_err(a, b):
     return float(d[i] / (nb if nb > 0 else 1.0)), i
 
 
-def assert_close(a, b, tol, what="", elem_tol=None):
+def op_elem_tol(desc, tol=1e-5):
+    """Per-element bound for one FP32 operator application, relative to the
+    largest element of the operator applied to |input|: max(tol, 4 N u),
+    u = 2^-24, N the largest grid or detector dimension.  Sample positions
+    are computed in FP32 from coordinates of magnitude up to about N cells,
+    so every position of a ray (or voxel) can carry the same rounding of
+    about 2 N u cells; coherent over the L samples of a ray, that moves the
+    ray by up to 2 N u L times the largest difference of neighbouring input
+    values, i.e. up to about 4 N u of the largest output for inputs in
+    [0, 1] (largest over mean 2).  A wrong sample or tap moves its element
+    by about 1 / L of a typical element (>= 2e-3 here), far beyond it."""
+    n = max(desc.nx, desc.ny, desc.nz, desc.nu, desc.nv)
+    return max(tol, 4.0 * n * 2.0 ** -24)
+
+
+def assert_close(a, b, tol, what="", elem_tol=None, scale=None):
     """Both bounds at once: the relative 2-norm distance <= tol and every
-    element within elem_tol (default tol) times the largest reference
-    element.  The message names the worst element."""
+    element within elem_tol (default tol) times `scale` (default the largest
+    reference element; for an operator applied to signed input, the largest
+    element of the operator applied to |input|, which removes the
+    cancellation from the normalisation).  The message names the worst
+    element."""
     e2 = rel(a, b)
     ei, i = elem_err(a, b)
+    if scale is not None and i >= 0:
+        nb = float(np.max(np.abs(np.asarray(b, np.float64))))
+        ei = ei * nb / scale if scale > 0 else ei
     et = tol if elem_tol is None else elem_tol
     a1 = np.asarray(a, np.float64).reshape(-1)
     b1 = np.asarray(b, np.float64).reshape(-1)
@@ -68,11 +89,13 @@ def assert_close(a, b, tol, what="", elem_tol=None):
 def assert_hist_close(a, b, tol, what=""):
     """Residual histories: every entry within tol of the reference entry,
     relative to that entry (late, small residuals are not hidden behind the
-    first one)."""
+    first one), plus 1e-12 of the first entry for residuals that are zero up
+    to rounding (after a breakdown)."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     assert a.shape == b.shape, (what, a.shape, b.shape)
-    r = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+    floor = 1e-12 * abs(b[0]) if b.size else 0.0
+    r = np.maximum(np.abs(a - b) - floor, 0.0) / np.maximum(np.abs(b), 1e-300)
     k = int(np.argmax(r))
     msg = "%s: residual history worst entry k=%d: %.9g vs %.9g (rel %.3e, tol %.1e)" % (what, k, a[k], b[k], r[k], tol)
     say(msg)
@@ -134,6 +157,11 @@ def special_rays(desc, views=None, rows=None):
 
 
 def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0, basis="f64"):
+    """The iterate part of fp32_envelopes (see there)."""
+    return fp32_envelopes(desc, b, K, B, solver, draws, seed, basis)[0]
+
+
+def fp32_envelopes(desc, b, K, B="un", solver="ba", draws=3, seed=0, basis="f64"):
     """How far FP32 arithmetic may move the oracle's K-th GMRES iterate.
 
     Each operator output of the oracle's solve is multiplied by
@@ -144,7 +172,11 @@ def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0, basis="f64")
     draws.  Problems whose exact iterate amplifies perturbations (noisy data
     at 20-30 iterations, where the Krylov vectors grow nearly dependent)
     move by 1e-4..1e-3 here; a GPU iterate is held to a small multiple of
-    this envelope rather than to a fixed tolerance."""
+    this envelope rather than to a fixed tolerance.  Returns (iterate
+    envelope, residual envelope), the second being the largest move of any
+    entry of the residual history relative to that entry: a residual far
+    below the first one carries the iterate's perturbation magnified by
+    their ratio."""
     import oracle
     b = np.asarray(b, np.float64).reshape(-1)
     c = float(np.sqrt(oracle.count_A_updates(desc) / desc.n_rays))
@@ -153,17 +185,24 @@ def fp32_envelope(desc, b, K, B="un", solver="ba", draws=3, seed=0, basis="f64")
     Bop = oracle.back_projector(desc, B)
     Bf = lambda q: np.asarray(Bop(q.reshape(desc.sino_shape))).reshape(-1)
     if solver == "ba":
-        ref = oracle.ba_gmres(desc, b, K, B=B, basis=basis).x.reshape(-1)
+        r0 = oracle.ba_gmres(desc, b, K, B=B, basis=basis)
     else:
-        ref = oracle.ab_gmres(desc, b, K, B=B).x.reshape(-1)
-    worst = 0.0
+        r0 = oracle.ab_gmres(desc, b, K, B=B)
+    ref = r0.x.reshape(-1)
+    rres = np.asarray(r0.res, np.float64)
+    worst, worst_res = 0.0, 0.0
     for _ in range(draws):
         p = lambda v: v * (1.0 + c * 2.0 ** -24 * rng.uniform(-1.0, 1.0, v.shape))
         if solver == "ba":
-            co, W, _, done, _ = oracle.gmres(lambda v: p(Bf(p(A(v)))), p(Bf(b)), K, basis=basis)
+            co, W, res, done, _ = oracle.gmres(lambda v: p(Bf(p(A(v)))), p(Bf(b)), K, basis=basis)
             x = W[:done].T @ co
         else:
-            co, W, _, done, _ = oracle.gmres(lambda v: p(A(p(Bf(v)))), b, K)
+            co, W, res, done, _ = oracle.gmres(lambda v: p(A(p(Bf(v)))), b, K)
             x = p(Bf(W[:done].T @ co))
         worst = max(worst, float(np.linalg.norm(x - ref) / np.linalg.norm(ref)))
-    return worst
+        res = np.asarray(res, np.float64)
+        if res.shape == rres.shape:
+            worst_res = max(worst_res, float(np.max(np.abs(res - rres) / np.maximum(rres, 1e-300))))
+        else:
+            worst_res = float("inf")
+    return worst, worst_res

@@ -11,13 +11,15 @@ FP32 (both sides read the same FP32 values).
   iterate insensitive to FP32-sized perturbations of the operators at this
   K (the sensitivity that forces the FP32 envelope on the noisy 2D problem
   does not arise here).
-* CGLS(A^T), K = 50: a short recurrence whose iterates, in any FP32
-  implementation, drift from the FP64 ones as the recurrence loses
-  conjugacy; the data residual ||b - A x_k||, which CGLS minimises, is held
-  to 1e-3 at every k, and the iterate to 2e-2 (the spread measured for the
-  oracle's own recurrence with its vectors rounded to FP32 at each step on
-  this workload: 4.7e-3 at k = 50, recorded in
-  tests/golden/cgls_fp32_spread.json by tests/golden/make_cgls_spread.py).
+* CGLS(A^T), K = 50: a short recurrence, whose iterates in FP32 can drift
+  from the FP64 ones as the recurrence loses conjugacy (on the noisy 2D
+  problem by 1e-2 at k = 10).  On these noiseless data the oracle's own
+  recurrence with every vector rounded to FP32 at each step, and its
+  operator outputs perturbed at FP32 accumulation size, moves x_50 by
+  1.8e-6 and the residuals by at most 1.3e-7 (tests/golden/
+  cgls_fp32_spread.json, written by tests/golden/make_cgls_spread.py from
+  the oracle alone), so the iterate and every residual entry are held to
+  1e-4, or three times that spread if it were larger.
 * Both: properties at any size (monotone histories, first entry the norm of
   the right-hand side, last entry the recomputed residual of the returned
   iterate, relative to that last entry).
@@ -99,7 +101,7 @@ def test_cgls_AT_50_iterations_match_the_oracle(c2):
     assert r.iters_done == ref.iters_done == 50
     spread = _cgls_spread()
     say("C2 CGLS(A^T) oracle FP32-vector spread: x %.3e, residual %.3e" % (spread["x"], spread["res"]))
-    assert_hist_close(r.res, ref.res, max(1e-3, 3.0 * spread["res"]), "C2 CGLS(A^T) K=50")
+    assert_hist_close(r.res, ref.res, max(1e-4, 3.0 * spread["res"]), "C2 CGLS(A^T) K=50")
     assert_close(host(r.x), ref.x, max(1e-4, 3.0 * spread["x"]), "C2 CGLS(A^T) K=50 x")
 
 

@@ -41,7 +41,9 @@ def c3():
 def test_headline_workload_data(c3):
     desc, g, b = c3
     assert b.shape == (desc.n_rays,)
-    assert np.all(np.isfinite(b)) and float(b.max()) > 3.0 and float(b.min()) >= 0.0
+    # line integrals up to 4 plus Poisson noise; rays through air can count
+    # more than the incident photons, so b dips slightly below zero
+    assert np.all(np.isfinite(b)) and 3.5 < float(b.max()) < 4.5 and float(b.min()) > -0.1
 
 
 def test_ba_gmres_ramp_matches_the_oracle(c3):

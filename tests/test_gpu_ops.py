@@ -1,8 +1,10 @@
 """GPU operator parity with the FP64 oracle (same seeded FP32 inputs).
 
 Tolerance: relative 2-norm error <= 1e-5 for FP32 outputs, and every
-element within 1e-5 of the largest reference element (so that a defect in
-a few rays or voxels cannot hide in the norm of the whole output).  Derivation: the
+element within max(1e-5, 4 N 2^-24) of the largest reference element, N
+the largest grid dimension (op_elem_tol: coherent FP32 rounding of the
+sample positions), so that a defect in a few rays or voxels cannot hide in
+the norm of the whole output.  Derivation: the
 kernels evaluate each sample position in FP32 from FP64 per-ray set-up, so
 the interpolation weights carry errors of a few units of 2^-24 times the
 coordinate magnitude (<= 2^9 voxels here), i.e. <= 3e-5 per weight at worst
@@ -19,7 +21,7 @@ import oracle
 import paper_2201_07408_amd as ct
 from synth import workloads
 from synth.geometry import GeometryDesc, PARALLEL_2D, cone3d
-from tests.gpu_helpers import SMALL_GEOMS, assert_close, dev, f32, host, rel, say, special_rays
+from tests.gpu_helpers import SMALL_GEOMS, assert_close, dev, f32, host, op_elem_tol, rel, say, special_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +41,7 @@ def test_project_A(geoms, name):
     x = f32(np.random.default_rng(1).uniform(0, 1, size=desc.vol_shape))
     y = host(ct.ct_project_A(g, dev(x)))
     ref = oracle.project_A(desc, x)
-    assert_close(y, ref, TOL, "A " + name)
+    assert_close(y, ref, TOL, "A " + name, op_elem_tol(desc))
 
 
 @pytest.mark.parametrize("name", list(SMALL_GEOMS))
@@ -48,7 +50,7 @@ def test_backproject_B(geoms, name):
     say("B parity", name)
     y = f32(np.random.default_rng(2).uniform(0, 1, size=desc.sino_shape))
     x = host(ct.ct_backproject_B(g, dev(y)))
-    assert_close(x, oracle.backproject_Bun(desc, y), TOL, "B_un " + name)
+    assert_close(x, oracle.backproject_Bun(desc, y), TOL, "B_un " + name, op_elem_tol(desc))
 
 
 @pytest.mark.parametrize("name", list(SMALL_GEOMS))
@@ -58,7 +60,7 @@ def test_backproject_AT(geoms, name):
     rng = np.random.default_rng(3)
     y = f32(rng.uniform(0, 1, size=desc.sino_shape))
     x = host(ct.ct_backproject_AT(g, dev(y)))
-    assert_close(x, oracle.backproject_AT(desc, y), TOL, "A^T " + name)
+    assert_close(x, oracle.backproject_AT(desc, y), TOL, "A^T " + name, op_elem_tol(desc))
     # adjoint identity of the GPU pair itself
     v = f32(rng.standard_normal(desc.vol_shape))
     w = f32(rng.standard_normal(desc.sino_shape))
@@ -124,7 +126,7 @@ def test_project_A_small_shadow(projector):
     x = f32(np.random.default_rng(8).uniform(0, 1, size=desc.vol_shape))
     y = host(ct.ct_project_A(g, dev(x))).reshape(desc.sino_shape)
     ref = np.asarray(oracle.project_A(desc, x)).reshape(desc.sino_shape)
-    assert_close(y, ref, TOL, "A small shadow")
+    assert_close(y, ref, TOL, "A small shadow", op_elem_tol(desc))
     # exact zeros away from the edge of the shadow (pixels whose 3 x 3
     # neighbourhood is zero in the oracle), where rounding cannot decide
     # whether a grazing ray picks up a sample
@@ -152,7 +154,7 @@ def test_project_A_axis_switch_views(projector):
     say("A axis-switch views", projector)
     x = f32(np.random.default_rng(9).uniform(0, 1, size=desc.vol_shape))
     y = host(ct.ct_project_A(g, dev(x)))
-    assert_close(y, oracle.project_A(desc, x), TOL, "A axis-switch views")
+    assert_close(y, oracle.project_A(desc, x), TOL, "A axis-switch views", op_elem_tol(desc))
 
 
 @pytest.mark.parametrize("projector", [0, 1])
@@ -169,7 +171,7 @@ def test_project_A_volume_beyond_last_level_cache(projector):
     y = host(ct.ct_project_A(g, dev(x)))
     ref = oracle.project_A(desc, x)
     assert np.count_nonzero(ref) > 0.5 * ref.size
-    assert_close(y, ref, TOL, "A beyond the last-level cache")
+    assert_close(y, ref, TOL, "A beyond the last-level cache", op_elem_tol(desc))
 
 
 def test_batch_equals_single_calls(geoms):
@@ -204,14 +206,14 @@ def _sampled_parity(desc, g, vol, nsamp=3000, seed=7):
     yh = host(y).reshape(-1)
     rays = np.union1d(rng.choice(desc.n_rays, size=nsamp, replace=False), special_rays(desc))
     ref = oracle.project_A_rays(desc, vol, rays)
-    assert_close(yh[rays], ref, TOL, "A sampled rays")
+    assert_close(yh[rays], ref, TOL, "A sampled rays", op_elem_tol(desc))
     x = host(ct.ct_backproject_B(g, y)).reshape(-1)
     nz, ny, nx = desc.vol_shape
     edge = [(z * ny + yy) * nx + xx for z in (0, nz // 2, nz - 1) for yy in (0, ny // 2, ny - 1)
             for xx in (0, 1, nx // 2, nx - 2, nx - 1)]
     vox = np.union1d(rng.choice(desc.n_vox, size=nsamp, replace=False), np.array(edge, np.int64))
     refb = oracle.backproject_Bun_voxels(desc, f32(yh), vox)
-    assert_close(x[vox], refb, TOL, "B_un sampled voxels")
+    assert_close(x[vox], refb, TOL, "B_un sampled voxels", op_elem_tol(desc))
     xr = host(ct.ct_backproject_B(g, y, ramp=True)).reshape(-1)
     fy = oracle.ramp(desc, f32(yh))
     refr = oracle.backproject_Bun_voxels(desc, fy, vox)

@@ -15,7 +15,7 @@ import paper_2201_07408_amd as ct
 from paper_2201_07408_amd import _lib as L
 from synth import workloads
 from synth.geometry import GeometryDesc, parallel2d, cone3d, PARALLEL_2D, CONE_3D
-from tests.gpu_helpers import assert_close, assert_hist_close, special_rays, dev, f32, fp32_envelope, host, rel, say
+from tests.gpu_helpers import assert_close, assert_hist_close, special_rays, dev, f32, fp32_envelope, fp32_envelopes, op_elem_tol, host, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,12 @@ def test_siddon_A_and_AT(geoms, name):
     x = f32(rng.uniform(size=desc.vol_shape))
     y = f32(rng.normal(size=desc.sino_shape))
     say("siddon", name)
-    assert_close(host(ct.ct_project_A(g, dev(x))), oracle.project_A(desc, x), OP_TOL, "siddon A " + name)
-    assert_close(host(ct.ct_backproject_AT(g, dev(y))), oracle.backproject_AT(desc, y), OP_TOL, "siddon A^T " + name)
+    et = op_elem_tol(desc, OP_TOL)
+    assert_close(host(ct.ct_project_A(g, dev(x))), oracle.project_A(desc, x), OP_TOL, "siddon A " + name, et)
+    # y has both signs: per-element errors against A^T |y|
+    sc = float(np.max(np.abs(oracle.backproject_AT(desc, np.abs(y)))))
+    assert_close(host(ct.ct_backproject_AT(g, dev(y))), oracle.backproject_AT(desc, y), OP_TOL, "siddon A^T " + name,
+                 et, scale=sc)
 
 
 @pytest.mark.parametrize("which", ["w2", "w3"])
@@ -59,7 +63,7 @@ def test_siddon_full_size_sampled(which):
     y = host(ct.ct_project_A(g, dev(vol))).reshape(-1)
     rays = np.union1d(np.random.default_rng(7).choice(desc.n_rays, size=1500, replace=False), special_rays(desc))
     ref = oracle.project_A_rays(desc, vol.astype(np.float64), rays)
-    assert_close(y[rays], ref, OP_TOL, "siddon sampled rays " + which)
+    assert_close(y[rays], ref, OP_TOL, "siddon sampled rays " + which, op_elem_tol(desc, OP_TOL))
 
 
 def test_siddon_ba_gmres_2d_matches_oracle():
@@ -75,10 +79,11 @@ def test_siddon_ba_gmres_2d_matches_oracle():
         for K in (15, 30):
             r = ct.ct_ba_gmres(g, dev(b), K, B=B)
             ref = oracle.ba_gmres(desc, b, K, B=B)
-            tol = SOLVE_TOL if K == 15 else max(SOLVE_TOL, 3.0 * fp32_envelope(desc, b, K, B))
+            ex, er = fp32_envelopes(desc, b, K, B)
+            say("siddon BA %s K=%d FP32 envelope: iterate %.3e, residual entries %.3e" % (B, K, ex, er))
             assert r.iters_done == ref.iters_done == K
-            assert_close(host(r.x), ref.x, tol, "siddon BA %s K=%d x" % (B, K))
-            assert_hist_close(r.res, ref.res, SOLVE_TOL, "siddon BA %s K=%d" % (B, K))
+            assert_close(host(r.x), ref.x, max(SOLVE_TOL, 3.0 * ex), "siddon BA %s K=%d x" % (B, K))
+            assert_hist_close(r.res, ref.res, max(SOLVE_TOL, 3.0 * er), "siddon BA %s K=%d" % (B, K))
 
 
 def test_siddon_ba_gmres_cone_and_cgls():

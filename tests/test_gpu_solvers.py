@@ -17,7 +17,7 @@ import paper_2201_07408_amd as ct
 from synth import workloads
 from synth.phantoms import random_ellipsoids, rasterize_ellipsoids
 from synth.geometry import cone3d
-from tests.gpu_helpers import assert_close, assert_hist_close, dev, f32, fp32_envelope, host, rel, say
+from tests.gpu_helpers import assert_close, assert_hist_close, dev, f32, fp32_envelope, fp32_envelopes, host, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -50,30 +50,37 @@ def _compare(res_gpu, ref, x_tol=TOL, what="", hist_tol=TOL):
     assert_hist_close(res_gpu.res, ref.res, hist_tol, what)
 
 
-# At 15 iterations FP32 arithmetic moves these iterates by under 4e-5
-# (fp32_envelope), so they are held to 1e-4; at 30 the noisy-data iterate
-# amplifies perturbations of FP32 size to 1e-4..3e-4 and is held to three
-# times that envelope.  Residual histories stay within 1e-4 throughout.
+def _compare_in_envelope(res_gpu, ref, desc, b, K, B, solver, what):
+    """Noisy data: the iterate and each residual entry within three times
+    the move that FP32-sized perturbations of the oracle's own operators
+    cause (fp32_envelopes), and never looser than 1e-4."""
+    ex, er = fp32_envelopes(desc, b, K, B, solver)
+    say("%s FP32 envelope: iterate %.3e, residual entries %.3e" % (what, ex, er))
+    _compare(res_gpu, ref, max(TOL, 3.0 * ex), what, max(TOL, 3.0 * er))
+
+
+# On the noisy 64^2 problem FP32-sized perturbations of the oracle's own
+# operators move the BA-GMRES iterate by up to 2.1e-4 at k = 15 and 1.1e-4
+# at k = 30 (B_un, A^T; 9e-6 and 8e-5 with B_FBP), and its residual entries,
+# which lie 1e2..1e4 below the first one, by up to 7.8e-3 at k = 15 and 18 %
+# at k = 30 (mid-history entries, which recover by the last iteration).
+# Both are held to three times the envelope measured on the spot.
 @pytest.mark.parametrize("B", ["un", "ramp", "AT"])
 def test_ba_gmres_w1(w1, B):
     desc, g, b = w1
     say("BA-GMRES W1", B)
-    _compare(ct.ct_ba_gmres(g, dev(b), 15, B=B), oracle.ba_gmres(desc, b, 15, B=B), what="BA %s k=15" % B)
-    r = ct.ct_ba_gmres(g, dev(b), 30, B=B)
-    env = fp32_envelope(desc, b, 30, B)
-    say("BA-GMRES W1 %s k=30 FP32 envelope %.3e" % (B, env))
-    _compare(r, oracle.ba_gmres(desc, b, 30, B=B), max(TOL, 3.0 * env), "BA %s k=30" % B)
+    for K in (15, 30):
+        r = ct.ct_ba_gmres(g, dev(b), K, B=B)
+        _compare_in_envelope(r, oracle.ba_gmres(desc, b, K, B=B), desc, b, K, B, "ba", "BA %s k=%d" % (B, K))
 
 
 @pytest.mark.parametrize("B", ["un", "ramp"])
 def test_ab_gmres_w1(w1, B):
     desc, g, b = w1
     say("AB-GMRES W1", B)
-    _compare(ct.ct_ab_gmres(g, dev(b), 15, B=B), oracle.ab_gmres(desc, b, 15, B=B), what="AB %s k=15" % B)
-    r = ct.ct_ab_gmres(g, dev(b), 30, B=B)
-    env = fp32_envelope(desc, b, 30, B, "ab")
-    say("AB-GMRES W1 %s k=30 FP32 envelope %.3e" % (B, env))
-    _compare(r, oracle.ab_gmres(desc, b, 30, B=B), max(TOL, 3.0 * env), "AB %s k=30" % B)
+    for K in (15, 30):
+        r = ct.ct_ab_gmres(g, dev(b), K, B=B)
+        _compare_in_envelope(r, oracle.ab_gmres(desc, b, K, B=B), desc, b, K, B, "ab", "AB %s k=%d" % (B, K))
 
 
 def test_cgls_AT_w1(w1):
