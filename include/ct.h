@@ -157,6 +157,23 @@ int ct_op_workspace_bytes(const ct_geometry *g, int op, int batch, size_t *bytes
 int ct_project_A(const ct_geometry *g, const float *x, void *y, int y_dtype,
                  int batch, void *ws, size_t ws_bytes, void *stream);
 
+/* y = A x as ct_project_A, for callers that cannot allocate device memory
+ * or pass a workspace: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The padded volume copies live in a
+ * static device array of CT_NOALLOC_SCRATCH_BYTES bytes (enough for volumes
+ * up to 256^3: 138.4 MB), one per GPU, held from the first call on that GPU
+ * until the process ends.  Allocates nothing and records no kernel timing;
+ * the results are those of ct_project_A bit for bit.
+ * Every call on one GPU shares that GPU's array (it keeps the last call's
+ * contents; each call rewrites what it reads): calls that overlap on one
+ * GPU, from any stream or thread, race and must be serialised by the
+ * caller.  CT_ERR_UNSUPPORTED (with the sizes in ct_last_error) when the
+ * geometry's copies need more than CT_NOALLOC_SCRATCH_BYTES; other errors as
+ * ct_project_A. */
+#define CT_NOALLOC_SCRATCH_BYTES (144u << 20)
+int ct_project_A_noalloc(const ct_geometry *g, const float *x, void *y, int y_dtype,
+                         int batch, void *stream);
+
 /* x = B_un y, or x = B_un F y when ramp_filter != 0 (Sec. III, B_un and
  * B_FBP).  y: float or half [batch][n_views][nv][nu]; x: float[batch][...].
  * ws: >= ct_op_workspace_bytes(CT_OP_B or CT_OP_B_RAMP) bytes (may be NULL

@@ -13,11 +13,12 @@ CT_F32, CT_F16 = 0, 1
 CT_B_UNMATCHED, CT_B_RAMP, CT_B_AT = 0, 1, 2
 CT_SOLVER_BA, CT_SOLVER_AB, CT_SOLVER_CGLS, CT_SOLVER_BA_MONITOR, CT_SOLVER_BA_RESTARTED = 0, 1, 2, 3, 4
 CT_OP_A, CT_OP_B, CT_OP_B_RAMP, CT_OP_AT, CT_OP_FBP = 0, 1, 2, 3, 4
+CT_NOALLOC_SCRATCH_BYTES = 144 << 20
 
 # every symbol the header declares
 EXPORTS = [
     "ct_geometry_create", "ct_geometry_destroy", "ct_geometry_sizes",
-    "ct_op_workspace_bytes", "ct_project_A", "ct_backproject_B",
+    "ct_op_workspace_bytes", "ct_project_A", "ct_project_A_noalloc", "ct_backproject_B",
     "ct_backproject_AT", "ct_ramp_filter", "ct_fbp", "ct_solver_workspace_bytes",
     "ct_ba_gmres", "ct_ab_gmres", "ct_cgls", "ct_last_error", "ct_version", "ct_ba_gmres_monitor",
     "ct_ba_gmres_restarted",
@@ -75,6 +76,7 @@ def load(path: str = LIBPATH):
         "ct_geometry_sizes": ([gp, szp, szp], i),
         "ct_op_workspace_bytes": ([gp, i, i, szp], i),
         "ct_project_A": ([gp, vp, vp, i, i, vp, sz, vp], i),
+        "ct_project_A_noalloc": ([gp, vp, vp, i, i, vp], i),
         "ct_backproject_B": ([gp, vp, i, vp, i, i, vp, sz, vp], i),
         "ct_backproject_AT": ([gp, vp, i, vp, i, vp, sz, vp], i),
         "ct_ramp_filter": ([gp, vp, vp, i, vp], i),

@@ -138,6 +138,7 @@ class ProfScope {
   public:
     // no event pairs while a stream is being captured into a graph
     static void suppress(bool on);
+    static bool suppressed();
 
     ProfScope(int cls, hipStream_t s);
     ~ProfScope();

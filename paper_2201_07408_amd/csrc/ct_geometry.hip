@@ -75,6 +75,7 @@ int prof_drain() {
 static thread_local bool t_prof_suppressed = false;
 
 void ProfScope::suppress(bool on) { t_prof_suppressed = on; }
+bool ProfScope::suppressed() { return t_prof_suppressed; }
 
 ProfScope::ProfScope(int cls, hipStream_t s) : cls_(cls), s_(s) {
     if (t_prof_suppressed) return;

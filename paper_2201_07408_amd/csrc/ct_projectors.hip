@@ -2342,6 +2342,77 @@ extern "C" int ct_project_A(const ct_geometry *g, const float *x, void *y, int y
     return CT_OK;
 }
 
+// ------------------------------------------- allocation-free projection
+// The padded volume copies of ct_project_A_noalloc live in this array, one
+// per GPU that the library runs on (each GPU holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: its
+// device address, per device, comes from hipGetSymbolAddress on the first
+// call made with that device current.
+static __device__ __align__(256) unsigned char scratch[CT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+int noalloc_scratch(void **out) {
+    int dev = 0;
+    CT_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        set_error("ct_project_A_noalloc: device index beyond the scratch table");
+        return CT_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        CT_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("ct_project_A_noalloc: no device address for the scratch array");
+            return CT_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CT_OK;
+}
+
+// kernel timing records hipEvents; none are created inside this entry point
+struct NoProfile {
+    const bool was = ProfScope::suppressed();
+    NoProfile() { ProfScope::suppress(true); }
+    ~NoProfile() { ProfScope::suppress(was); }
+};
+}  // namespace
+
+extern "C" int ct_project_A_noalloc(const ct_geometry *g, const float *x, void *y, int y_dtype, int batch,
+                                    void *stream) {
+    clear_error();
+    CT_ARG_CHECK(g, "ct_project_A_noalloc: geometry is NULL");
+    CT_ARG_CHECK(batch >= 0, "ct_project_A_noalloc: negative batch");
+    CT_ARG_CHECK(check_dtype(y_dtype), "ct_project_A_noalloc: bad y_dtype");
+    if (batch == 0) return CT_OK;
+    CT_ARG_CHECK(x && y, "ct_project_A_noalloc: NULL array");
+    const size_t need = op_scratch_bytes(g, CT_OP_A, CT_F32);
+    if (need > (size_t)CT_NOALLOC_SCRATCH_BYTES) {
+        set_error("ct_project_A_noalloc: this geometry's padded volume copies need " + std::to_string(need) +
+                  " bytes; the allocation-free scratch holds " +
+                  std::to_string((size_t)CT_NOALLOC_SCRATCH_BYTES) + " (use ct_project_A with a workspace)");
+        return CT_ERR_UNSUPPORTED;
+    }
+    void *ws = nullptr;
+    CT_TRY(noalloc_scratch(&ws));
+    NoProfile np;
+    hipStream_t s = (hipStream_t)stream;
+    // the copies' zero border is rewritten by the first item of every call,
+    // so the previous call's contents (any geometry) do not matter
+    OpScratch sc = carve_op_scratch(g, CT_OP_A, CT_F32, ws);
+    const size_t es = y_dtype == CT_F16 ? 2 : 4;
+    for (int b = 0; b < batch; ++b)
+        CT_TRY(apply_A(g, x + (size_t)b * g->n_vox, (char *)y + (size_t)b * g->n_rays * es, y_dtype, sc,
+                       b > 0, nullptr, nullptr, s));
+    return CT_OK;
+}
+
 extern "C" int ct_backproject_B(const ct_geometry *g, const void *y, int y_dtype, float *x, int ramp_filter,
                                 int batch, void *ws, size_t ws_bytes, void *stream) {
     clear_error();
