@@ -2,19 +2,25 @@
 
 One step = one BA-GMRES solve (K = 30 iterations, B = B_un F, the
 ramp-filtered voxel-driven back-projector) from b resident in HBM to x in
-HBM, including the final host copy of the residual history.
+HBM, including the final host copy of the residual history.  The timed
+steps run without kernel timing; the per-kernel times come from a separate
+pass with the library's event pairs.
 
 Workload (synthetic stand-in for the paper's scanner data): 256^3 volume of
 12 random ellipsoids plus 5 % smoothed Gaussian texture; circular cone beam,
 360 views over 360 deg, 384 x 384 detector at one voxel per pixel at the
-isocentre, SOD = 4 N, SDD = 8 N; data from the projector, scaled so the
-largest line integral is 4, Poisson counts at 1e5 photons per ray, negative
-log.
+isocentre, SOD = 4 N, SDD = 8 N; data from the FP64 oracle's projector
+(from the GPU's with --no-cpu), scaled so the largest line integral is 4,
+Poisson counts at 1e5 photons per ray, negative log.
 
-Prints one JSON line (rank 0) with the throughput, the roofline position of
-the dominant kernel and the FP64 CPU oracle timed on a bounded sample.
+Prints one JSON line with the throughput, the roofline position of the
+dominant kernel, the FP64 CPU oracle timed on a bounded sample of the same
+workload and the distance of the GPU iterate from the oracle's, plus the
+extra legs (FP16 data storage, the matched transpose, the per-iteration
+curves of Sec. III / Fig. 2 on the 128^3 workload, FP16 basis, the
+line-intersection model, the batched 2D slices).
 
-    python bench.py [--steps K] [--warmup W] [--sino-dtype f32|f16] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--sino-dtype f32|f16] [--no-cpu] ...
 """
 
 import argparse
@@ -54,16 +60,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_inputs(ct, desc, g, torch):
-    from synth import workloads
+def phantom_scaled_data(vol, clean, seed=303):
+    """b = -log of Poisson counts at 1e5 photons of the line integrals scaled
+    so that the largest is 4; returns (b as FP32, the attenuation that makes
+    exactly those line integrals)."""
     from synth.phantoms import poisson_log_counts
-    vol = workloads.w3_phantom()
-    x = torch.from_numpy(vol).cuda()
-    ax = ct.ct_project_A(g, x)
-    mu = 4.0 / float(ax.max())
-    clean = (ax * mu).double().cpu().numpy().reshape(-1)
-    b = poisson_log_counts(303, clean, 1e5).astype(np.float32)
-    return torch.from_numpy(b).cuda(), vol * mu
+    mu = 4.0 / float(clean.max())
+    b = poisson_log_counts(seed, clean * mu, 1e5).astype(np.float32)
+    return b, vol * mu
 
 
 def projector_src_hash():
@@ -76,37 +80,166 @@ def projector_src_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def cpu_baseline(desc, b_host, x_phantom):
-    """FP64 oracle BA-GMRES (ramp) on a bounded sample: the same volume and
-    detector with every 4th view (90 of 360), 3 iterations.  The operator
-    cost is linear in the number of views, so seconds per full iteration are
-    estimated as (sample seconds per iteration) * 4."""
+# ------------------------------------------------------------ CPU oracle leg
+# Everything that runs the FP64 oracle: the data of the 256^3 and 128^3
+# workloads from the oracle's own projector (so that no GPU operator shapes
+# the right-hand sides both sides solve), the oracle's 256^3 iterate the GPU
+# is compared with, and the oracle timed on the host's threads.
+def oracle_data(desc3, vol3, desc2, vol2):
+    import oracle
+    t0 = time.perf_counter()
+    clean3 = np.asarray(oracle.project_A(desc3, vol3))
+    t_a3 = time.perf_counter() - t0
+    clean2 = np.asarray(oracle.project_A(desc2, vol2))
+    return clean3, clean2, t_a3
+
+
+def cpu_baseline(desc3, b3, K=2):
+    """FP64 oracle BA-GMRES (B_un F) on the 256^3 workload, K iterations on
+    all of the host's threads: the iterate the GPU's is compared with, and
+    the oracle's rate (the start vector costs about half an iteration, so
+    seconds per iteration are the time over K + 0.5)."""
+    import oracle
+    t0 = time.perf_counter()
+    ref = oracle.ba_gmres(desc3, b3.astype(np.float64), K, B="ramp")
+    dt = time.perf_counter() - t0
+    per_iter = dt / (ref.iters_done + 0.5)
+    out = {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": "FP64 oracle BA-GMRES (B_un F), %d iterations on the full 256^3 workload (360 views, "
+                     "384x384 detector) on %d host threads; %.1f s of CPU work, seconds per iteration "
+                     "= time / (K + 0.5)" % (K, oracle.num_threads(), dt)}
+    return out, ref
+
+
+def cpu_small_configs(desc1, b1, desc2, b2):
+    """The oracle's BA-GMRES (B_un) rate on the 64^2 workload (30
+    iterations) and the 128^3 workload (2 iterations) at one thread and at
+    all threads; at one thread the 128^3 solve runs on every 10th view and
+    its seconds are scaled by 10 (operator cost is linear in views)."""
     import oracle
     from synth.geometry import GeometryDesc
-    sub = 4
-    angles = [2 * math.pi * p / desc.n_views for p in range(0, desc.n_views, sub)]
-    gs = GeometryDesc(desc.kind, desc.nx, desc.ny, desc.nz, desc.voxel, len(angles), desc.nu,
-                      desc.nv, desc.du, desc.dv, desc.sod, desc.sdd, tuple(angles))
-    bs = b_host.reshape(desc.sino_shape)[::sub].astype(np.float64)
-    t = time.perf_counter()
-    r = oracle.ba_gmres(gs, bs, 3, B="ramp")
-    dt = time.perf_counter() - t
-    # one extra B for the start vector: (iters + 1) back-projections, iters projections
-    per_iter = dt / (r.iters_done + 0.5) * sub
-    out = {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.num_threads(),
-           "kind": "oracle",
-           "sample": "FP64 oracle BA-GMRES (B_un F), 3 iterations on the 256^3 volume and "
-                     "384x384 detector with 90 of the 360 views (every 4th); seconds per "
-                     "iteration scaled by 4 (operator cost is linear in views); %.1f s of CPU "
-                     "work" % dt}
-    return out, oracle
+    nthr = oracle.num_threads()
+    out = {"threads_all": nthr}
+
+    def rate(desc, b, K):
+        t0 = time.perf_counter()
+        r = oracle.ba_gmres(desc, b, K, B="un")
+        return (r.iters_done + 0.5) / (time.perf_counter() - t0)
+
+    try:
+        for name, th in (("1_thread", 1), ("all_threads", nthr)):
+            oracle.set_threads(th)
+            out.setdefault("C1_64x64_K30_iters_per_s", {})[name] = rate(desc1, b1, 30)
+        oracle.set_threads(nthr)
+        out.setdefault("C2_128cube_iters_per_s", {})["all_threads"] = rate(desc2, b2, 2)
+        sub = 10
+        angles = [2 * math.pi * p / desc2.n_views for p in range(0, desc2.n_views, sub)]
+        gs = GeometryDesc(desc2.kind, desc2.nx, desc2.ny, desc2.nz, desc2.voxel, len(angles), desc2.nu,
+                          desc2.nv, desc2.du, desc2.dv, desc2.sod, desc2.sdd, tuple(angles))
+        bs = np.ascontiguousarray(b2.reshape(desc2.sino_shape)[::sub])
+        oracle.set_threads(1)
+        out["C2_128cube_iters_per_s"]["1_thread"] = rate(gs, bs, 2) / sub
+        out["C2_128cube_iters_per_s"]["1_thread_sample"] = "every %dth view, seconds scaled by %d" % (sub, sub)
+    finally:
+        oracle.set_threads(nthr)
+    return out
+
+
+def sampled_errors(desc, ct, g, torch, x_phantom):
+    """Relative error of the GPU operators against the FP64 oracle on sampled
+    rays / voxels of the benchmark workload."""
+    import oracle
+    rng = np.random.default_rng(11)
+    x = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
+    y = ct.ct_project_A(g, x)
+    yh = y.double().cpu().numpy().reshape(-1)
+    rays = rng.choice(desc.n_rays, size=1500, replace=False)
+    ra = oracle.project_A_rays(desc, x.double().cpu().numpy(), rays)
+    ea = float(np.linalg.norm(yh[rays] - ra) / np.linalg.norm(ra))
+    xb = ct.ct_backproject_B(g, y, ramp=True).double().cpu().numpy().reshape(-1)
+    vox = rng.choice(desc.n_vox, size=1500, replace=False)
+    fy = oracle.ramp(desc, y.float().cpu().numpy())
+    rb = oracle.backproject_Bun_voxels(desc, fy, vox)
+    eb = float(np.linalg.norm(xb[vox] - rb) / np.linalg.norm(rb))
+    return {"A_sampled": ea, "B_FBP_sampled": eb}
+
+
+# ------------------------------------------------------------------ GPU legs
+def gpu_data(ct, g, torch, vol):
+    """Line integrals of the phantom from the GPU's projector (used only when
+    the oracle leg is switched off)."""
+    x = torch.from_numpy(vol).cuda()
+    return ct.ct_project_A(g, x).double().cpu().numpy().reshape(-1)
+
+
+def bench_f16_data(ct, torch, g, b, x_phantom, x32, steps=3):
+    """The headline solve with the solver's projections stored in FP16
+    (FP32 arithmetic): rate, distance from the FP32-storage iterate and
+    image RMSE of both."""
+    x_ref = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
+    rmse = lambda v: float(torch.sqrt(torch.mean((v.double() - x_ref.double()) ** 2)))
+    ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=torch.float16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(steps):
+        r = ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=torch.float16)
+        done += r.iters_done
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"iters_per_s": done / dt, "data_bytes_per_projection": 2 * g.n_rays,
+            "rel_diff_vs_fp32_storage": float(torch.linalg.vector_norm(r.x - x32) / torch.linalg.vector_norm(x32)),
+            "image_rmse": rmse(r.x), "image_rmse_fp32_storage": rmse(x32),
+            "residual_at_30": r.res[-1], "residual_at_30_fp32_storage": None}
+
+
+def bench_fig2(ct, torch, clean2, vol2, K=50):
+    """The comparison of Sec. III / Fig. 2 on the 128^3 workload: the data
+    residual ||A x_k - b|| (and the data RMSE, that norm over sqrt(m)) of
+    CGLS with the unmatched B_un, CGLS with A^T, BA-GMRES with B_un and
+    BA-GMRES with B_FBP, for k = 0..K, on noiseless data and with 1 %
+    Gaussian noise (seed 202).  Reported, not asserted: on this synthetic
+    problem the unmatched CGLS need not diverge within K."""
+    from synth import workloads
+    desc = workloads.w2_geometry()
+    g = ct.Geometry(desc)
+    x_ref = torch.from_numpy(np.ascontiguousarray(vol2, dtype=np.float32)).cuda()
+    sm = math.sqrt(desc.n_rays)
+    out = {"workload": "128^3 cone beam, 180 views, 192x192 detector, 12 ellipsoids; %d iterations" % K,
+           "every": 5}
+    for name, noise in (("noiseless", 0.0), ("noise_1pct", 0.01)):
+        y = clean2 + (workloads.relative_gaussian_noise(clean2, noise, 202) if noise > 0 else 0.0)
+        b = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).cuda()
+        curves = {}
+        t0 = time.perf_counter()
+        for B, label in (("un", "CGLS_B_un"), ("AT", "CGLS_AT")):
+            r = ct.ct_cgls(g, b, K, B=B)
+            img = float(torch.sqrt(torch.mean((r.x.double() - x_ref.double()) ** 2)))
+            curves[label] = {"data_residual": [round(v, 6) for v in r.res[::5]],
+                             "min_at": int(np.argmin(r.res)), "last_over_min": r.res[-1] / min(r.res),
+                             "image_rmse_at_K": img}
+        for B, label in (("un", "BA_GMRES_B_un"), ("ramp", "BA_GMRES_B_FBP")):
+            r = ct.ct_ba_gmres_monitor(g, b, K, B=B, x_ref=x_ref)
+            curves[label] = {"data_residual": [round(v, 6) for v in r.data_res[::5]],
+                             "min_at": int(np.nanargmin(r.data_res)),
+                             "last_over_min": r.data_res[-1] / np.nanmin(r.data_res),
+                             "image_rmse": [round(v, 7) for v in r.img_rmse[::5]],
+                             "min_image_rmse_at": int(np.nanargmin(r.img_rmse))}
+        torch.cuda.synchronize()
+        curves["data_rmse_divisor"] = sm
+        curves["s_all_curves"] = time.perf_counter() - t0
+        out[name] = curves
+    return out
 
 
 def bench_batched(ct, torch, reps=3):
     """64 uneven 2D slices (N in {128..512}, 90/180/360 views, ceil(1.5 N)
     bins, ellipse phantoms, 1 % noise), BA-GMRES(B_un) for 40 iterations
     each: one batched solve (hipGraph replay) against the same 64 solves
-    one after another.  Inputs are made with the library's own projector."""
+    one after another.  Both are warmed first (every geometry's solver
+    workspace exists before the timed passes) and both are timed over the
+    same number of repetitions.  Inputs are made with the library's own
+    projector."""
     from synth import workloads
     K = 40
     slices = workloads.w5_slices()
@@ -119,6 +252,7 @@ def bench_batched(ct, torch, reps=3):
         geoms.append(g)
         bs.append(torch.from_numpy(y.astype(np.float32)).cuda())
     out = ct.ct_ba_gmres_batched(geoms, bs, K)          # autotune + graph capture
+    seq = [ct.ct_ba_gmres(g, b, K) for g, b in zip(geoms, bs)]   # every workspace allocated
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -126,13 +260,11 @@ def bench_batched(ct, torch, reps=3):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
     done_b = sum(r.iters_done for r in out)
-    for g, b in zip(geoms[:4], bs[:4]):                  # warm the one-problem path
-        ct.ct_ba_gmres(g, b, K)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    seq = [ct.ct_ba_gmres(g, b, K) for g, b in zip(geoms, bs)]
+    for _ in range(reps):
+        seq = [ct.ct_ba_gmres(g, b, K) for g, b in zip(geoms, bs)]
     torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
+    ts = (time.perf_counter() - t0) / reps
     done_s = sum(r.iters_done for r in seq)
     diff = max(float(torch.linalg.norm(r.x - s.x) / torch.linalg.norm(s.x)) for r, s in zip(out, seq))
     graph, a_var, b_var = ct.ct_batched_last_config()
@@ -140,7 +272,7 @@ def bench_batched(ct, torch, reps=3):
                         "ceil(1.5N) bins, BA-GMRES(B_un) 40 iterations each",
             "batched_iters_per_s": done_b / tb, "sequential_iters_per_s": done_s / ts,
             "speedup": ts / tb * done_b / max(done_s, 1), "batched_ms": tb * 1e3, "sequential_ms": ts * 1e3,
-            "max_rel_diff_x_vs_sequential": diff, "hipgraph": graph,
+            "reps_each": reps, "max_rel_diff_x_vs_sequential": diff, "hipgraph": graph,
             "projector_variant": a_var, "backprojector_variant": b_var}
 
 
@@ -316,22 +448,24 @@ def bench_paper_scale(ct, torch, lib):
     return out
 
 
-def sampled_errors(oracle, desc, ct, g, torch, x_phantom):
-    """Relative error of the GPU operators against the FP64 oracle on sampled
-    rays / voxels of the benchmark workload."""
-    rng = np.random.default_rng(11)
-    x = torch.from_numpy(np.ascontiguousarray(x_phantom, dtype=np.float32)).cuda()
-    y = ct.ct_project_A(g, x)
-    yh = y.double().cpu().numpy().reshape(-1)
-    rays = rng.choice(desc.n_rays, size=1500, replace=False)
-    ra = oracle.project_A_rays(desc, x.double().cpu().numpy(), rays)
-    ea = float(np.linalg.norm(yh[rays] - ra) / np.linalg.norm(ra))
-    xb = ct.ct_backproject_B(g, y, ramp=True).double().cpu().numpy().reshape(-1)
-    vox = rng.choice(desc.n_vox, size=1500, replace=False)
-    fy = oracle.ramp(desc, y.float().cpu().numpy())
-    rb = oracle.backproject_Bun_voxels(desc, fy, vox)
-    eb = float(np.linalg.norm(xb[vox] - rb) / np.linalg.norm(rb))
-    return {"A_sampled": ea, "B_FBP_sampled": eb}
+def kernel_times(ct, lib, g, b, sdt, steps):
+    """Average duration of each kernel class over `steps` headline solves,
+    from the library's event pairs on the solver's stream (a pass of its
+    own, after the timed steps)."""
+    import torch
+    lib.ct_profile_reset()
+    lib.ct_profile_enable(1)
+    done = 0
+    for _ in range(steps):
+        done += ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=sdt).iters_done
+    torch.cuda.synchronize()
+    lib.ct_profile_enable(0)
+    kern = {}
+    for name in ("A", "B", "F", "CGS"):
+        n_l, t_l = ctypes.c_long(), ctypes.c_double()
+        lib.ct_profile_read(name.encode(), ctypes.byref(n_l), ctypes.byref(t_l))
+        kern[name] = (n_l.value, t_l.value / 1e3)
+    return kern, done
 
 
 def main():
@@ -339,12 +473,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--sino-dtype", default="f32", choices=["f32", "f16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-siddon", action="store_true")
     ap.add_argument("--no-monitor", action="store_true")
     ap.add_argument("--no-basis16", action="store_true")
+    ap.add_argument("--no-fig2", action="store_true")
     ap.add_argument("--paper-scale", action="store_true",
                     help="also solve at the paper's data size (1024x1024x300, 180 x 1088x896)")
     args = ap.parse_args()
@@ -361,8 +497,21 @@ def main():
     torch.cuda.set_device(0)
     desc = workloads.w3_geometry()
     g = ct.Geometry(desc)
+    desc2 = workloads.w2_geometry()
     log("bench: generating inputs")
-    b, x_phantom = make_inputs(ct, desc, g, torch)
+    vol3 = workloads.w3_phantom()
+    vol2 = workloads.w2_phantom()
+    t_oracle_a3 = None
+    if not args.no_cpu:
+        log("bench: CPU oracle leg (data from the oracle's projector)")
+        clean3, clean2, t_oracle_a3 = oracle_data(desc, vol3, desc2, vol2)
+        data_from = "oracle"
+    else:
+        clean3 = gpu_data(ct, g, torch, vol3)
+        clean2 = gpu_data(ct, ct.Geometry(desc2), torch, vol2)
+        data_from = "gpu"
+    b_host, x_phantom = phantom_scaled_data(vol3, clean3)
+    b = torch.from_numpy(b_host).cuda()
     sdt = torch.float16 if args.sino_dtype == "f16" else torch.float32
 
     log("bench: warmup")
@@ -370,12 +519,6 @@ def main():
         r = ct.ct_ba_gmres(g, b, ITERS, B="ramp", sino_dtype=sdt)
     torch.cuda.synchronize()
     log("bench: timed solves")
-    # kernel classes are timed inside the timed region by the library's
-    # event pairs, recorded on the stream the kernels run on
-    lib = ct.api.L.load()
-    lib.ct_profile_reset()
-    lib.ct_profile_enable(1)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
     for _ in range(args.steps):
@@ -383,14 +526,13 @@ def main():
         done += r.iters_done
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    lib.ct_profile_enable(0)
     ms_per_step = dt / args.steps * 1e3
     value = done / dt
-    kern = {}
-    for name in ("A", "B", "F", "CGS"):
-        n_l, t_l = ctypes.c_long(), ctypes.c_double()
-        lib.ct_profile_read(name.encode(), ctypes.byref(n_l), ctypes.byref(t_l))
-        kern[name] = (n_l.value, t_l.value / 1e3)
+    x32 = r.x.clone()
+
+    log("bench: kernel timing pass")
+    lib = ct.api.L.load()
+    kern, done_p = kernel_times(ct, lib, g, b, sdt, args.profile_steps)
     t_a = kern["A"][1] / max(kern["A"][0], 1)
     t_b = kern["B"][1] / max(kern["B"][0], 1)
     t_f = kern["F"][1] / max(kern["F"][0], 1)
@@ -421,15 +563,20 @@ def main():
         "config": {"workload": "cone-beam 256^3, 360 views over 360 deg, 384x384 detector, "
                                "ellipsoids + 5% texture, Poisson 1e5 photons, log; BA-GMRES with "
                                "B = ramp-filtered voxel-driven B_un, 30 iterations per step",
-                   "iters_per_step": ITERS, "sino_dtype": args.sino_dtype},
+                   "iters_per_step": ITERS, "sino_dtype": args.sino_dtype, "data_projector": data_from},
         "A_updates_per_s": a_upd / t_a,
         "B_updates_per_s": b_upd / t_b,
         "kernel_ms_per_launch": {"A": t_a * 1e3, "B_un": t_b * 1e3, "F": t_f * 1e3,
-                                 "CGS_per_iteration": kern["CGS"][1] / max(done, 1) * 1e3},
+                                 "CGS_per_iteration": kern["CGS"][1] / max(done_p, 1) * 1e3,
+                                 "pass": "%d solves after the timed ones, library event pairs" % args.profile_steps},
         "roofline": {"bound": "alu", "kernel": dom[0], "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
     }
+    if sdt == torch.float32:
+        log("bench: FP16 data storage")
+        line["fp16_data_storage"] = bench_f16_data(ct, torch, g, b, x_phantom, x32)
+        line["fp16_data_storage"]["residual_at_30_fp32_storage"] = r.res[-1]
     # the matched transpose (CGLS with A^T, autograd backward), outside the
     # timed solves: three launches on the same data
     log("bench: matched transpose")
@@ -444,12 +591,15 @@ def main():
     torch.cuda.synchronize()
     line["AT_ms_per_launch"] = e0.elapsed_time(e1) / 3
     del yat, xat
+    if not args.no_fig2:
+        log("bench: data-residual curves on the 128^3 workload")
+        line["fig2_128cube"] = bench_fig2(ct, torch, clean2, vol2)
     if not args.no_monitor:
         log("bench: monitored solves")
         line["monitor"] = bench_monitor(ct, torch, b, x_phantom, ms_per_step)
     if not args.no_basis16 and sdt == torch.float32:
         log("bench: FP16 Krylov basis")
-        line["basis_fp16"] = bench_basis16(ct, torch, lib, g, b, x_phantom, r.x.clone())
+        line["basis_fp16"] = bench_basis16(ct, torch, lib, g, b, x_phantom, x32)
     if not args.no_siddon:
         log("bench: line-intersection forward model")
         line["siddon_A"] = bench_siddon(ct, torch, lib)
@@ -460,10 +610,30 @@ def main():
         log("bench: batched 2D slices")
         line["batched_2d"] = bench_batched(ct, torch)
     if not args.no_cpu:
-        log("bench: CPU oracle baseline")
-        cb, orc = cpu_baseline(desc, b.cpu().numpy(), x_phantom)
+        log("bench: CPU oracle BA-GMRES on the headline workload")
+        K = 2
+        rk = ct.ct_ba_gmres(g, b, K, B="ramp")
+        xk = rk.x.double().cpu().numpy().reshape(-1)
+        cb, ref = cpu_baseline(desc, b_host)
         line["cpu_baseline"] = cb
-        line["rel_err_vs_fp64"] = sampled_errors(orc, desc, ct, g, torch, x_phantom)
+        xr = np.asarray(ref.x).reshape(-1)
+        d = np.abs(xk - xr)
+        line["rel_err_vs_fp64"] = {
+            "x_%d_headline" % K: float(np.linalg.norm(xk - xr) / np.linalg.norm(xr)),
+            "x_%d_worst_voxel_of_max" % K: float(d.max() / np.abs(xr).max()),
+            "residual_history_%d_worst_entry" % K:
+                float(np.max(np.abs(np.array(rk.res) - np.array(ref.res)) / np.array(ref.res))),
+            "note": "GPU BA-GMRES(B_FBP) iterate after %d iterations on the full headline workload against the "
+                    "FP64 oracle's (same FP32 data)" % K}
+        line["rel_err_vs_fp64"].update(sampled_errors(desc, ct, g, torch, x_phantom))
+        line["cpu_baseline"]["oracle_projection_s"] = t_oracle_a3
+        log("bench: CPU oracle on the 64^2 and 128^3 workloads")
+        d1 = workloads.w1_geometry()
+        import oracle
+        c1 = oracle.project_A(d1, workloads.w1_phantom())
+        b1 = (c1 + workloads.relative_gaussian_noise(c1, 0.01, 102)).astype(np.float32).astype(np.float64)
+        line["cpu_oracle_configs"] = cpu_small_configs(d1, b1, desc2,
+                                                       clean2.astype(np.float32).astype(np.float64))
     print(json.dumps(line), flush=True)
 
 

@@ -186,7 +186,8 @@ int ct_backproject_B(const ct_geometry *g, const void *y, int y_dtype, float *x,
  * B = A^T).  Gathered per voxel (each voxel sums the weighted values of the
  * rays whose samples touch it, in a fixed order, without atomics), so the
  * result is the same bits on every run.
- * ws: >= ct_op_workspace_bytes(CT_OP_AT). */
+ * ws: >= ct_op_workspace_bytes(CT_OP_AT) bytes (cone beam: the data
+ * weighted by each ray's step length; 2D: none, ws may be NULL). */
 int ct_backproject_AT(const ct_geometry *g, const void *y, int y_dtype, float *x,
                       int batch, void *ws, size_t ws_bytes, void *stream);
 

@@ -163,13 +163,13 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
 // fills g->d_colT (cone geometries) from the kernel view; synchronous
 int launch_col_table(ct_geometry *g);
-int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx,
-                     float *vy, const int *stop, hipStream_t s);
-// cone-beam A^T gathered per voxel straight into x (times *scale if given)
+// cone-beam A^T gathered per voxel straight into x (times *scale if given);
+// ys: n_rays floats of scratch for the step-weighted data
 int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, float *x,
-                            const float *scale, const int *stop, hipStream_t s);
-int launch_unpad_sum(const ct_geometry *g, const float *vx, const float *vy, float *x,
-                     const float *scale, const int *stop, hipStream_t s);
+                            const float *scale, const int *stop, hipStream_t s, float *ys);
+// 2D Joseph A^T gathered per pixel straight into x (times *scale if given)
+int launch_project_T_par(const ct_geometry *g, const void *y, int y_dtype, float *x,
+                         const float *scale, const int *stop, hipStream_t s);
 int launch_backproject(const ct_geometry *g, const void *y, int y_dtype, float *x,
                        const float *in_scale, const int *stop, hipStream_t s);
 int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out,
@@ -185,7 +185,8 @@ int launch_siddon_T(const ct_geometry *g, const void *y, int y_dtype, float *x,
 // Composite operators used by the solvers and the ABI: x/y of one item.
 struct OpScratch {
     float *vx = nullptr, *vy = nullptr;   // padded copies (A, A^T)
-    void *filt = nullptr;                  // filtered data (ramp), dtype as data
+    void *filt = nullptr;                  // filtered data (ramp), dtype as data; step-weighted
+                                           // data of the cone-beam A^T (FP32)
 };
 size_t op_scratch_bytes(const ct_geometry *g, int op, int data_dtype);
 OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *ws);

@@ -417,14 +417,16 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
     b.opA.vx = c.take<float>(g->pad.nvx);
     b.opA.vy = c.take<float>(g->pad.nvy);
     const size_t es = o.sino_dtype == CT_F16 ? 2 : 4;
+    // filtered data (B_un F) or the step-weighted data of the cone-beam A^T
+    const bool filt = o.B == CT_B_RAMP || (o.B == CT_B_AT && g->k.kind == CT_CONE_CIRCULAR_3D);
     if (ba) {
         b.q = c.take<char>(g->n_rays * es);
         // the first back-projection filters the FP32 data whatever the storage
-        if (o.B == CT_B_RAMP) b.filt = c.take<char>(g->n_rays * 4);
+        if (filt) b.filt = c.take<char>(g->n_rays * 4);
         b.z = c.take<float>(g->n_vox);
     } else {
         b.q = c.take<float>(g->n_vox);               // u = B w
-        if (o.B == CT_B_RAMP) b.filt = c.take<float>(g->n_rays);
+        if (filt) b.filt = c.take<float>(g->n_rays);
         b.z = c.take<float>(g->n_rays);
     }
     b.opA.filt = b.filt;
@@ -607,7 +609,8 @@ size_t carve_cgls(const ct_geometry *g, const ct_solver_opts &o, void *ws, float
     *p = c.take<float>(g->n_vox);
     op.vx = c.take<float>(g->pad.nvx);
     op.vy = c.take<float>(g->pad.nvy);
-    op.filt = o.B == CT_B_RAMP ? c.take<float>(g->n_rays) : nullptr;
+    op.filt = o.B == CT_B_RAMP || (o.B == CT_B_AT && g->k.kind == CT_CONE_CIRCULAR_3D) ? c.take<float>(g->n_rays)
+                                                                                     : nullptr;
     st.K = o.iters;
     st.pstride = kMaxBlk;
     st.flags = c.take<int>(16);

@@ -1,24 +1,26 @@
-// CT operators of the ABBA method on gfx950: Joseph forward projector A,
-// its exact scatter transpose A^T, the voxel-driven back-projector B_un and
-// the Ram-Lak ramp filter F (Sec. III of the paper names A, B_un, F and
-// B_FBP = B_un F; the discretisations are the ones stated in ct.h).
+// CT operators of the ABBA method on gfx950: Joseph forward projector A
+// (and the line-intersection model), its exact transpose A^T, the
+// voxel-driven back-projector B_un and the Ram-Lak ramp filter F (Sec. III
+// of the paper names A, B_un, F and B_FBP = B_un F; the discretisations are
+// the ones stated in ct.h).
 //
-// None of these is a dense contraction, so none uses MFMA.  The design:
-//  * A is ray-driven, one work-item per ray.  A workgroup is a tile of one
-//    view's detector (64 u x 4 v in 3D), so stores are coalesced along u.
+// The projectors are gathers, not dense contractions, so they run on the
+// vector units; only F, two Toeplitz products per row, runs on MFMA.
+//  * A is ray-driven.  In 3D a workgroup is a 16 x 16 tile of one view's
+//    detector: per chunk of four sampling planes the patch of the volume its
+//    rays cross is staged in LDS with 16-byte loads from a zero-padded,
+//    axis-permuted copy, and each ray interpolates its samples from there.
 //    Per-ray set-up (direction, dominant axis, plane range) is FP64; the
-//    plane loop is FP32, with each sample position computed from the plane
-//    index by one FMA.  Samples are read from a zero-padded copy of the
-//    volume permuted so that the in-plane axis that varies across a
-//    wavefront (y for x-major views, x for y-major views) is contiguous;
-//    the padding removes every bounds test from the loop and the reads go
-//    through a buffer resource whose range check returns 0 outside.
-//  * A^T walks the same samples and scatters with FP32 atomics into padded
-//    copies, which are then summed back into the volume.
-//  * B_un is voxel-driven: one work-item per (x, y) column and a chunk of z.
-//    The view's perspective set-up (U, M, u-taps, weight) is FP64 and shared
-//    by the whole chunk; the z loop is FP32 with FMA-from-index.
-//  * F convolves each detector row in LDS.
+//    plane loop is FP32 with FMA-from-index positions and FP64 accumulation
+//    of groups of four samples.  In 2D one work-item walks one ray.
+//  * A^T is gathered per voxel (each voxel sums the weighted values of the
+//    rays whose samples touch it, in a fixed order), so its results do not
+//    depend on scheduling: in 3D from LDS-staged footprints of the
+//    step-weighted data, in 2D per pixel from a tent on the detector.
+//  * B_un is voxel-driven: a workgroup owns 16 x 16 columns and a chunk of
+//    z, stages each view's detector footprint in LDS, and interpolates there.
+//  * F: per detector row, the even and odd outputs are two dense Toeplitz
+//    products of the odd-lag taps (v_mfma_f32_16x16x4f32).
 #include <type_traits>
 #include <cmath>
 #include <map>
@@ -124,33 +126,6 @@ __global__ __launch_bounds__(256) void k_pad_copy(const InT *__restrict__ x, flo
                                                   const int *__restrict__ stop) {
     if (stop && *stop) return;
     pad_tile(x, vx, vy, nx, ny, L, blockIdx.x * 32, blockIdx.y * 32, blockIdx.z);
-}
-
-// x[z][y][x] = Vx[x][z+pz][y+kPad] + Vy[y][z+pz][x+kPad]
-__global__ __launch_bounds__(256) void k_unpad_sum(const float *__restrict__ vx, const float *__restrict__ vy,
-                                                   float *__restrict__ x, int nx, int ny, PadLayout L,
-                                                   const float *__restrict__ scale,
-                                                   const int *__restrict__ stop) {
-    if (stop && *stop) return;
-    __shared__ float tile[32][33];
-    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int xx = x0 + ty + 8 * r, yy = y0 + tx;
-        if (yy < ny && xx < nx)
-            tile[ty + 8 * r][tx] = vx[(size_t)xx * L.sx + (size_t)(z + L.pz) * L.rx + yy + kPad];
-    }
-    __syncthreads();
-    const size_t zoff = (size_t)z * ny * nx;
-    const float sc = scale ? *scale : 1.0f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int yy = y0 + ty + 8 * r, xx = x0 + tx;
-        if (yy < ny && xx < nx)
-            x[zoff + (size_t)yy * nx + xx] =
-                sc * (tile[tx][ty + 8 * r] + vy[(size_t)yy * L.sy + (size_t)(z + L.pz) * L.ry + xx + kPad]);
-    }
 }
 
 // ------------------------------------------------------------ Joseph ray
@@ -713,51 +688,6 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
     if (active) store_ray(g, y, p, av, au, acc, R.step, out_scale);
 }
 
-__device__ __forceinline__ uint32_t clampu(int v, int hi) { return (uint32_t)min(max(v, 0), hi); }
-
-template <bool CONE, typename InT>
-__global__ __launch_bounds__(256) void k_project_T(GeomK g, PadLayout L, const InT *__restrict__ y,
-                                                   float *__restrict__ vx, float *__restrict__ vy,
-                                                   const int *__restrict__ stop) {
-    if (stop && *stop) return;
-    const int au = blockIdx.x * blockDim.x + threadIdx.x;
-    const int av = blockIdx.y * blockDim.y + threadIdx.y;
-    const int p = blockIdx.z;
-    if (au >= g.nu || av >= g.nv) return;
-    const float yv = to_f(y[((size_t)p * g.nv + av) * g.nu + au]);
-    if (yv == 0.0f) return;
-    const RaySetup R = ray_setup<CONE>(g, L, p, av, au);
-    const bool isx = R.ax == 0;
-    float *V = isx ? vx : vy;
-    const uint32_t S = isx ? L.sx : L.sy, Rw = isx ? L.rx : L.ry;
-    // clamping keeps every address inside the padded copy; a clamped tap can
-    // only be a border tap, whose accumulated value is discarded
-    const int bmax = (int)Rw - 2;
-    const int cmax = g.nz + 2 * L.pz - 2;
-    const float val = yv * R.step;
-    for (int j = R.j0; j <= R.j1; ++j) {
-        const float fj = (float)j;
-        const float fb = fmaf(fj, R.gb, R.fb0);
-        const float ibf = floorf(fb);
-        const float wb = fb - ibf;
-        uint32_t off = (uint32_t)j * S + clampu((int)ibf, bmax);
-        if (CONE) {
-            const float fc = fmaf(fj, R.gc, R.fc0);
-            const float icf = floorf(fc);
-            const float wc = fc - icf;
-            off += clampu((int)icf, cmax) * Rw;
-            const float a0 = val * (1.0f - wc), a1 = val * wc;
-            unsafeAtomicAdd(V + off, a0 * (1.0f - wb));
-            unsafeAtomicAdd(V + off + 1, a0 * wb);
-            unsafeAtomicAdd(V + off + Rw, a1 * (1.0f - wb));
-            unsafeAtomicAdd(V + off + Rw + 1, a1 * wb);
-        } else {
-            unsafeAtomicAdd(V + off, val * (1.0f - wb));
-            unsafeAtomicAdd(V + off + 1, val * wb);
-        }
-    }
-}
-
 constexpr int kZC = 16;   // z voxels per work-item in the voxel-driven cone kernels
 
 // Per (view, column) ray table of a cone geometry (ColT), from the same
@@ -799,8 +729,8 @@ __global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict_
     vshift[p] = (kTU - sw % kTU) % kTU;
 }
 
-// Exact transpose of the cone-beam Joseph projector, gathered per voxel
-// instead of scattered per sample.  Voxel (ix, iy, iz) receives, from every
+// Exact transpose of the cone-beam Joseph projector (k_project_T_staged),
+// gathered per voxel instead of scattered per sample.  Voxel (ix, iy, iz) receives, from every
 // ray that samples its plane (x = ix for x-dominant rays, y = iy for
 // y-dominant ones) within one voxel of it in both in-plane coordinates, the
 // ray's value times the bilinear weight tent(f_b - i_b) tent(f_c - iz) and
@@ -841,105 +771,201 @@ __device__ __forceinline__ void slab_interval(float d, float g, float &s0, float
     s1 = fminf(fmaxf(a, b), 1.0f);
 }
 
-template <typename InT, bool SID>
-__global__ __launch_bounds__(256) void k_project_T_gather(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
+// Step weights of the cone-beam transpose applied once per ray: ys = y *
+// step, with step = vox |r| / |r_a| = |is| sqrt(v^2 + r_x^2 + r_y^2) from the
+// column table, so that the transpose reads one value per ray and row.
+template <typename InT>
+__global__ __launch_bounds__(256) void k_ray_step_scale(GeomK g, const InT *__restrict__ y, float *__restrict__ ys,
+                                                        const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const size_t n = (size_t)g.P * g.nv * g.nu;
+    const float Cvf = (float)(0.5 * (g.nv - 1)), dvf = (float)g.dv;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int au = (int)(i % (size_t)g.nu);
+        const size_t pv = i / (size_t)g.nu;
+        const int av = (int)(pv % (size_t)g.nv), p = (int)(pv / (size_t)g.nv);
+        const ColT &T = g.colT[(size_t)p * g.nu + au];
+        const float vv = ((float)av - Cvf) * dvf;
+        ys[i] = fabsf(T.is) * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(y[i]);
+    }
+}
+
+// The cone-beam transpose with each view's footprint of the step-weighted
+// data staged in LDS (as the back-projector stages its footprint): per
+// group of kTVG views, the box of detector cells whose rays can sample the
+// workgroup's voxel block (the projection of the block widened by one
+// voxel on every side, the reach of a weight, with a cell of margin) is
+// copied with 16-byte loads, and the candidate rows of every candidate
+// column are read from there instead of from global memory.  Candidate
+// columns, weights and the z splat are described above.  A group whose box
+// does not fit the tile reads the data from global memory.
+constexpr int kTVG = 3;               // views per staged group
+constexpr int kTSU = 36, kTSV = 32;   // staged detector columns / rows per view
+
+template <bool SID>
+__global__ __launch_bounds__(256) void k_project_T_staged(GeomK g, const float *__restrict__ ys, float *__restrict__ x,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ stop) {
     if (stop && *stop) return;
     __shared__ float s_acc[256 * kATS];
+    __shared__ float4 tile4[kTVG * kTSV * kTSU / 4];
+    __shared__ int s_box[kTVG][2];
+    __shared__ int s_fit;
+    const float *tile = (const float *)tile4;
     const int tid = threadIdx.y * 16 + threadIdx.x;
-    const int ix = blockIdx.x * 16 + threadIdx.x, iy = blockIdx.y * 16 + threadIdx.y, iz0 = blockIdx.z * kZC;
-    if (ix >= g.nx || iy >= g.ny) return;   // no barriers below: the slots are private
+    const int ix0 = blockIdx.x * 16, iy0 = blockIdx.y * 16, iz0 = blockIdx.z * kZC;
+    const int ix = ix0 + threadIdx.x, iy = iy0 + threadIdx.y;
+    const bool active = ix < g.nx && iy < g.ny;   // the others stage and meet the barriers
     float *slot = s_acc + tid * kATS;
 #pragma unroll
     for (int z = 0; z < kZC; ++z) slot[z] = 0.0f;
     const int nu = g.nu, nv = g.nv, P = g.P;
     const double vox = g.vox, ivox = 1.0 / vox;
-    const double Cx = 0.5 * (g.nx - 1), Cy = 0.5 * (g.ny - 1), Cu = 0.5 * (nu - 1);
-    const float Cvf = (float)(0.5 * (nv - 1)), dvf = (float)g.dv;
+    const double Cx = 0.5 * (g.nx - 1), Cy = 0.5 * (g.ny - 1), Cz = 0.5 * (g.nz - 1), Cu = 0.5 * (nu - 1);
+    const float Cvf = (float)(0.5 * (nv - 1));
     const float zoff = (float)(0.5 * (g.nz - 1) - iz0);   // f_c - iz0 = zoff + a1 (av - Cv)
     const double xc = (ix - Cx) * vox, yc = (iy - Cy) * vox;
+    // the block widened by one voxel (the reach of a weight) in every axis
+    const double bx0 = (ix0 - 1 - Cx) * vox, bx1 = (min(ix0 + 15, g.nx - 1) + 1 - Cx) * vox;
+    const double by0 = (iy0 - 1 - Cy) * vox, by1 = (min(iy0 + 15, g.ny - 1) + 1 - Cy) * vox;
+    const double bz0 = (iz0 - 1 - Cz) * vox, bz1 = (min(iz0 + kZC - 1, g.nz - 1) + 1 - Cz) * vox;
+    constexpr int Q = kTSU / 4;                      // 16-byte cells per staged row
+    constexpr int kCells = kTVG * kTSV * Q;
     double acc[kZC];
 #pragma unroll
     for (int z = 0; z < kZC; ++z) acc[z] = 0.0;
-    for (int p = 0; p < P; ++p) {
-        const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
-        const double ox = g.sod * c, oy = g.sod * s;
-        const InT *yp = y + (size_t)p * nv * nu;
-        const ColT *Tp = g.colT + (size_t)p * nu;
-        const int vd = g.vdom[p];
-#pragma unroll 1
-        for (int axis = 0; axis < 2; ++axis) {
-            if (!(vd & (1 << axis))) continue;   // no column of this view has this dominant axis
-            // axis 0: x-dominant rays on the plane x = xc (b = y); axis 1:
-            // y-dominant rays on the plane y = yc (b = x)
-            const double D = axis ? yc - oy : xc - ox;
-            const int ib = axis ? ix : iy;
-            const double e0 = (axis ? ox : oy) - (ib - (axis ? Cx : Cy)) * vox;   // f_b - ib = (e0 + D t) / vox
-            // t(u) = (al u + be) / (ga u + de), inverted at f_b - ib = -+1
-            const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
-            const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
-            const double iD = 1.0 / D, tm = (-vox - e0) * iD, tp = (vox - e0) * iD;
-            const double dm = ga * tm - al, dp = ga * tp - al;
-            int a_lo = 0, a_hi = nu - 1;
-            if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
-                const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
-                const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
-                a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
-                a_hi = ahi < (double)nu ? min((int)ceil(ahi), nu - 1) : nu - 1;
-                if (alo >= (double)nu || ahi <= -1.0) a_hi = -1;   // interval off the detector
+    for (int p0 = 0; p0 < P; p0 += kTVG) {
+        __syncthreads();   // the previous group's readers are done with the tile and boxes
+        if (tid == 0) s_fit = 1;
+        if (tid < kTVG && p0 + tid < P) {
+            const int p = p0 + tid;
+            const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+            for (int k = 0; k < 4; ++k) {
+                const double px = (k & 1) ? bx1 : bx0, py = (k & 2) ? by1 : by0;
+                const double U = g.sod - (px * c + py * s);
+                const double M = g.sdd / U;
+                const double fu = M * (py * c - px * s) / g.du + Cu;
+                umin = fmin(umin, fu); umax = fmax(umax, fu);
+                const double va = M * bz0 / g.dv + 0.5 * (nv - 1), vb = M * bz1 / g.dv + 0.5 * (nv - 1);
+                vmin = fmin(vmin, fmin(va, vb)); vmax = fmax(vmax, fmax(va, vb));
             }
-            const float Df = (float)D;
-            for (int au = a_lo; au <= a_hi; ++au) {
-                const ColT T = Tp[au];
-                if ((T.is > 0.0f) != (axis == 0)) continue;   // the projector's dominant axis
-                const float db = (float)((e0 + D * T.t) * ivox);   // f_b - ib at the plane
-                float wb, lb = 0.0f, hb = 0.0f;
-                if (SID) {
-                    slab_interval(db, (float)T.t, lb, hb);   // slab part inside the voxel's b range
-                    wb = hb > lb ? 1.0f : 0.0f;
-                } else {
-                    wb = 1.0f - fabsf(db);
+            const int u0 = ((int)floor(umin) - 1) & ~3, u1 = (int)floor(umax) + 2;
+            const int v0 = (int)floor(vmin) - 1, v1 = (int)floor(vmax) + 2;
+            s_box[tid][0] = u0;
+            s_box[tid][1] = v0;
+            if (u1 - u0 >= kTSU || v1 - v0 >= kTSV || !(umin > -1e6 && umax < 1e6 && vmin > -1e6 && vmax < 1e6))
+                atomicAnd(&s_fit, 0);
+        }
+        __syncthreads();
+        const bool fit = s_fit != 0;
+        if (fit) {
+            for (int q = tid; q < kCells; q += 256) {
+                const int vv = q / (kTSV * Q), r = (q / Q) % kTSV, c4 = 4 * (q % Q);
+                const int p = p0 + vv;
+                float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (p < P) {
+                    const int v = s_box[vv][1] + r, u = s_box[vv][0] + c4;
+                    if ((unsigned)v < (unsigned)nv) {
+                        const float *row = ys + ((size_t)p * nv + v) * nu;
+                        if ((nu & 3) == 0 && (unsigned)u <= (unsigned)(nu - 4)) {
+                            e = *reinterpret_cast<const float4 *>(row + u);
+                        } else {
+                            float t4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                if (u + k >= 0 && u + k < nu) t4[k] = row[u + k];
+                            e = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                        }
+                    }
                 }
-                if (!(wb > 0.0f)) continue;
-                // f_c(av) - iz0 = zoff + a1 (av - Cv): rows feeding the chunk
-                // [iz0 - 1, iz0 + kZC]
-                const float a1 = Df * T.ar, ia1 = 1.0f / a1;
-                const float r1 = fmaf(-1.0f - zoff, ia1, Cvf), r2 = fmaf((float)kZC - zoff, ia1, Cvf);
-                const int v0 = max((int)ceilf(fminf(r1, r2)), 0), v1 = min((int)floorf(fmaxf(r1, r2)), nv - 1);
-                const float wis = wb * fabsf(T.is);
-                const InT *col = yp + au;
-                for (int av = v0; av <= v1; ++av) {
-                    const float dv = (float)av - Cvf;
-                    const float zf = fmaf(a1, dv, zoff);
-                    const float zl = floorf(zf), w1 = zf - zl;
-                    const int zi = (int)zl;
-                    const float vv = dv * dvf;
-                    const float val = wis * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(col[av * nu]);
-                    if (SID) {
-                        // c slope per slab r_z / r_a; the slab's c range covers
-                        // voxels floor(zf + 1/2 -+ gc / 2) of the chunk
-                        const float gc = T.ar * (float)vox * dv;
-                        const float c0 = fmaf(-0.5f, gc, zf + 0.5f), c1 = fmaf(0.5f, gc, zf + 0.5f);
-                        const float k0f = floorf(c0), k1f = floorf(c1);
-                        const float sc = k0f == k1f ? 1.0f : (fmaxf(k0f, k1f) - c0) / gc;
-                        const float f0 = fmaxf(fminf(sc, hb) - lb, 0.0f);
-                        const float f1 = k0f == k1f ? 0.0f : fmaxf(hb - fmaxf(sc, lb), 0.0f);
-                        const int k0 = (int)k0f, k1 = (int)k1f;
-                        if ((unsigned)k0 < (unsigned)kZC) slot[k0] = fmaf(f0, val, slot[k0]);
-                        if ((unsigned)k1 < (unsigned)kZC && k1 != k0) slot[k1] = fmaf(f1, val, slot[k1]);
-                    } else {
-                        if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
-                        if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
+                tile4[q] = e;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            for (int vv = 0; vv < kTVG && p0 + vv < P; ++vv) {
+                const int p = p0 + vv;
+                const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+                const double ox = g.sod * c, oy = g.sod * s;
+                const float *yp = ys + (size_t)p * nv * nu;
+                const float *tv = tile + vv * kTSV * kTSU;
+                const int bu0 = s_box[vv][0], bv0 = s_box[vv][1];
+                const ColT *Tp = g.colT + (size_t)p * nu;
+                const int vd = g.vdom[p];
+#pragma unroll 1
+                for (int axis = 0; axis < 2; ++axis) {
+                    if (!(vd & (1 << axis))) continue;
+                    const double D = axis ? yc - oy : xc - ox;
+                    const int ib = axis ? ix : iy;
+                    const double e0 = (axis ? ox : oy) - (ib - (axis ? Cx : Cy)) * vox;
+                    const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
+                    const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
+                    const double iD = 1.0 / D, tm = (-vox - e0) * iD, tp = (vox - e0) * iD;
+                    const double dm = ga * tm - al, dp = ga * tp - al;
+                    int a_lo = 0, a_hi = nu - 1;
+                    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
+                        const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
+                        const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
+                        a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
+                        a_hi = ahi < (double)nu ? min((int)ceil(ahi), nu - 1) : nu - 1;
+                        if (alo >= (double)nu || ahi <= -1.0) a_hi = -1;
+                    }
+                    const float Df = (float)D;
+                    for (int au = a_lo; au <= a_hi; ++au) {
+                        const ColT T = Tp[au];
+                        if ((T.is > 0.0f) != (axis == 0)) continue;
+                        const float db = (float)((e0 + D * T.t) * ivox);
+                        float wb, lb = 0.0f, hb = 0.0f;
+                        if (SID) {
+                            slab_interval(db, (float)T.t, lb, hb);
+                            wb = hb > lb ? 1.0f : 0.0f;
+                        } else {
+                            wb = 1.0f - fabsf(db);
+                        }
+                        if (!(wb > 0.0f)) continue;
+                        const float a1 = Df * T.ar, ia1 = 1.0f / a1;
+                        const float r1 = fmaf(-1.0f - zoff, ia1, Cvf), r2 = fmaf((float)kZC - zoff, ia1, Cvf);
+                        const int v0 = max((int)ceilf(fminf(r1, r2)), 0), v1 = min((int)floorf(fmaxf(r1, r2)), nv - 1);
+                        // this column's staged cells (clamped into the tile: the
+                        // box covers every row and column that can carry a
+                        // weight here, up to rounding)
+                        const int lu = min(max(au - bu0, 0), kTSU - 1);
+                        for (int av = v0; av <= v1; ++av) {
+                            const float dv = (float)av - Cvf;
+                            const float zf = fmaf(a1, dv, zoff);
+                            const float zl = floorf(zf), w1 = zf - zl;
+                            const int zi = (int)zl;
+                            const float yv = fit ? tv[min(max(av - bv0, 0), kTSV - 1) * kTSU + lu] : yp[(size_t)av * nu + au];
+                            const float val = wb * yv;
+                            if (SID) {
+                                // the slab's c range, [zc + q -+ gc/2] with zc = zoff + 1/2
+                                // (an exact integer or half-integer) and q = a1 dv: the
+                                // crossing is taken relative to zc, so that a small slope
+                                // does not divide the rounding of the absolute coordinate
+                                const float gc = T.ar * (float)vox * dv, q = a1 * dv, zc = zoff + 0.5f;
+                                const float r0 = fmaf(-0.5f, gc, q), r1 = fmaf(0.5f, gc, q);
+                                const float k0f = floorf(zc + r0), k1f = floorf(zc + r1);
+                                const float sc = k0f == k1f ? 1.0f : ((fmaxf(k0f, k1f) - zc) - r0) / gc;
+                                const float f0 = fmaxf(fminf(sc, hb) - lb, 0.0f);
+                                const float f1 = k0f == k1f ? 0.0f : fmaxf(hb - fmaxf(sc, lb), 0.0f);
+                                const int k0 = (int)k0f, k1 = (int)k1f;
+                                if ((unsigned)k0 < (unsigned)kZC) slot[k0] = fmaf(f0, val, slot[k0]);
+                                if ((unsigned)k1 < (unsigned)kZC && k1 != k0) slot[k1] = fmaf(f1, val, slot[k1]);
+                            } else {
+                                if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
+                                if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
+                            }
+                        }
                     }
                 }
             }
-        }
-        if ((p & 3) == 3 || p == P - 1) {
+            // views summed in FP32 over the group, then in FP64
 #pragma unroll
             for (int z = 0; z < kZC; ++z) { acc[z] += (double)slot[z]; slot[z] = 0.0f; }
         }
     }
+    if (!active) return;
     const double sc = scale ? (double)*scale : 1.0;
 #pragma unroll
     for (int z = 0; z < kZC; ++z) {
@@ -1363,6 +1389,48 @@ __global__ __launch_bounds__(256) void k_bp_par(GeomK g, const InT *__restrict__
     }
     const double sc = in_scale ? (double)*in_scale : 1.0;
     x[(size_t)iy * g.nx + ix] = (float)(acc * (g.vox * g.vox * inv_du) * sc);
+}
+
+// 2D Joseph A^T gathered per pixel, deterministic.  For a parallel-beam
+// view with direction d = (-sin t, cos t) and dominant component r_a
+// (sin t for x-major views, whose samples lie on the columns x = const;
+// cos t for y-major views), the sample of ray a on the pixel's plane lies
+// (s_a - p.n) / r_a from the pixel centre along the other axis, s_a the
+// bin's offset and p.n the pixel centre projected on n = (cos t, sin t).
+// The pixel's weight in that ray is therefore tent((s_a - p.n) / (r_a vox))
+// times the step vox / |r_a|: a tent on the detector of half-width
+// |r_a| vox, which covers at most three bins.  The dominant axis is the
+// forward projector's (the per-view table with the integer tie rule).
+// Views are summed in FP32 in groups of four, groups in FP64.
+template <typename InT>
+__global__ __launch_bounds__(256) void k_project_T_par(GeomK g, const InT *__restrict__ y, float *__restrict__ x,
+                                                       const float *__restrict__ in_scale,
+                                                       const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int ix = blockIdx.x * 16 + threadIdx.x, iy = blockIdx.y * 16 + threadIdx.y;
+    if (ix >= g.nx || iy >= g.ny) return;
+    const double px = (ix - 0.5 * (g.nx - 1)) * g.vox, py = (iy - 0.5 * (g.ny - 1)) * g.vox;
+    const double cu = 0.5 * (g.nu - 1), inv_du = 1.0 / g.du;
+    const int nu = g.nu;
+    double acc = 0.0;
+    float grp = 0.0f;
+    for (int p = 0; p < g.P; ++p) {
+        const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+        const double ra = fabs(g.axis[p] == 0 ? s : c);
+        const double pn = px * c + py * s, hw = ra * g.vox;
+        const double lo = (pn - hw) * inv_du + cu, hi = (pn + hw) * inv_du + cu;
+        const int a0 = max((int)ceil(lo), 0), a1 = min((int)floor(hi), nu - 1);
+        const InT *yp = y + (size_t)p * nu;
+        float v = 0.0f;
+        for (int a = a0; a <= a1; ++a) {
+            const double w = 1.0 - fabs(((a - cu) * g.du - pn) / hw);
+            if (w > 0.0) v = fmaf((float)w, to_f(yp[a]), v);
+        }
+        grp = fmaf((float)(g.vox / ra), v, grp);
+        if ((p & 3) == 3 || p == g.P - 1) { acc += (double)grp; grp = 0.0f; }
+    }
+    const double sc = in_scale ? (double)*in_scale : 1.0;
+    x[(size_t)iy * g.nx + ix] = (float)(acc * sc);
 }
 
 // ----------------------------------------------------------------- F
@@ -1874,14 +1942,6 @@ int launch_pad_copy(const ct_geometry *g, const void *x, int x_dtype, float *vx,
     return CT_OK;
 }
 
-int launch_unpad_sum(const ct_geometry *g, const float *vx, const float *vy, float *x, const float *scale,
-                     const int *stop, hipStream_t s) {
-    dim3 grid((g->k.nx + 31) / 32, (g->k.ny + 31) / 32, g->k.nz);
-    hipLaunchKernelGGL(k_unpad_sum, grid, dim3(32, 8), 0, s, vx, vy, x, g->k.nx, g->k.ny, g->pad, scale, stop);
-    CT_LAUNCH_CHECK();
-    return CT_OK;
-}
-
 static void ray_grid(const ct_geometry *g, dim3 &grid, dim3 &block) {
     if (g->k.kind == CT_CONE_CIRCULAR_3D) block = dim3(64, 4);
     else block = dim3(256, 1);
@@ -2010,40 +2070,40 @@ int launch_col_table(ct_geometry *g) {
 }
 
 int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, float *x, const float *scale,
-                            const int *stop, hipStream_t s) {
-    ProfScope prof(PROF_AT, s);
-    dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC), block(16, 16);
-    if (g->k.proj == CT_SIDDON) {
-        if (y_dtype == CT_F32)
-            hipLaunchKernelGGL((k_project_T_gather<float, true>), grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
-        else
-            hipLaunchKernelGGL((k_project_T_gather<__half, true>), grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
-    } else {
-        if (y_dtype == CT_F32)
-            hipLaunchKernelGGL((k_project_T_gather<float, false>), grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
-        else
-            hipLaunchKernelGGL((k_project_T_gather<__half, false>), grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
+                            const int *stop, hipStream_t s, float *ys) {
+    if (!ys) {
+        set_error("A^T: no scratch for the step-weighted data");
+        return CT_ERR_ARG;
     }
+    ProfScope prof(PROF_AT, s);
+    size_t blocks = (g->n_rays + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (y_dtype == CT_F32)
+        hipLaunchKernelGGL(k_ray_step_scale<float>, dim3((unsigned)blocks), dim3(256), 0, s, g->k, (const float *)y, ys, stop);
+    else
+        hipLaunchKernelGGL(k_ray_step_scale<__half>, dim3((unsigned)blocks), dim3(256), 0, s, g->k, (const __half *)y, ys, stop);
+    CT_LAUNCH_CHECK();
+    dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC), block(16, 16);
+    if (g->k.proj == CT_SIDDON)
+        hipLaunchKernelGGL((k_project_T_staged<true>), grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
+    else
+        hipLaunchKernelGGL((k_project_T_staged<false>), grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
 
-int launch_project_T(const ct_geometry *g, const void *y, int y_dtype, float *vx, float *vy,
-                     const int *stop, hipStream_t s) {
+int launch_project_T_par(const ct_geometry *g, const void *y, int y_dtype, float *x, const float *scale,
+                         const int *stop, hipStream_t s) {
     ProfScope prof(PROF_AT, s);
-    dim3 grid, block;
-    ray_grid(g, grid, block);
-    const bool cone = g->k.kind == CT_CONE_CIRCULAR_3D;
-    if (y_dtype == CT_F32) {
-        if (cone) hipLaunchKernelGGL((k_project_T<true, float>), grid, block, 0, s, g->k, g->pad, (const float *)y, vx, vy, stop);
-        else hipLaunchKernelGGL((k_project_T<false, float>), grid, block, 0, s, g->k, g->pad, (const float *)y, vx, vy, stop);
-    } else {
-        if (cone) hipLaunchKernelGGL((k_project_T<true, __half>), grid, block, 0, s, g->k, g->pad, (const __half *)y, vx, vy, stop);
-        else hipLaunchKernelGGL((k_project_T<false, __half>), grid, block, 0, s, g->k, g->pad, (const __half *)y, vx, vy, stop);
-    }
+    dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16), block(16, 16);
+    if (y_dtype == CT_F32)
+        hipLaunchKernelGGL(k_project_T_par<float>, grid, block, 0, s, g->k, (const float *)y, x, scale, stop);
+    else
+        hipLaunchKernelGGL(k_project_T_par<__half>, grid, block, 0, s, g->k, (const __half *)y, x, scale, stop);
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
+
 
 
 int launch_siddon(const ct_geometry *g, const float *x, void *y, int y_dtype, const float *out_scale,
@@ -2245,8 +2305,9 @@ static size_t dtype_size(int dt) { return dt == CT_F16 ? 2 : 4; }
 size_t op_scratch_bytes(const ct_geometry *g, int op, int data_dtype) {
     switch (op) {
     case CT_OP_A:
-    case CT_OP_AT:
         return align_up(g->pad.nvx * 4) + align_up(g->pad.nvy * 4);
+    case CT_OP_AT:   // step-weighted data of the cone-beam transpose (2D: none)
+        return g->k.kind == CT_CONE_CIRCULAR_3D ? align_up(g->n_rays * 4) : 0;
     case CT_OP_B_RAMP:
         return align_up(g->n_rays * dtype_size(data_dtype));
     case CT_OP_FBP:
@@ -2259,10 +2320,12 @@ size_t op_scratch_bytes(const ct_geometry *g, int op, int data_dtype) {
 OpScratch carve_op_scratch(const ct_geometry *g, int op, int data_dtype, void *ws) {
     OpScratch sc;
     char *p = (char *)ws;
-    if (op == CT_OP_A || op == CT_OP_AT) {
+    if (op == CT_OP_A) {
         sc.vx = (float *)p;
         p += align_up(g->pad.nvx * 4);
         sc.vy = (float *)p;
+    } else if (op == CT_OP_AT) {
+        if (g->k.kind == CT_CONE_CIRCULAR_3D) sc.filt = p;
     } else if (op == CT_OP_B_RAMP) {
         sc.filt = p;
     }
@@ -2291,19 +2354,15 @@ int apply_B(const ct_geometry *g, int which, const void *y, int y_dtype, float *
         CT_TRY(launch_ramp(g, y, y_dtype, sc.filt, y_dtype, (size_t)g->k.P * g->k.nv, stop, s));
         return launch_backproject(g, sc.filt, y_dtype, x, in_scale, stop, s);
     }
-    if (g->k.kind == CT_CONE_CIRCULAR_3D) return launch_project_T_gather(g, y, y_dtype, x, in_scale, stop, s);
+    if (g->k.kind == CT_CONE_CIRCULAR_3D)
+        return launch_project_T_gather(g, y, y_dtype, x, in_scale, stop, s, (float *)sc.filt);
     if (g->k.proj == CT_SIDDON) {
         // the 2D line-intersection transpose scatters straight into x
         CT_TRY(launch_fill(x, g->n_vox, 0.0f, s));
         return launch_siddon_T(g, y, y_dtype, x, in_scale, stop, s);
     }
-    // 2D A^T: scatter into zeroed padded copies, then fold back.  The
-    // scatter also writes border cells, so a following A must re-zero the
-    // border.
-    CT_TRY(launch_fill(sc.vx, g->pad.nvx, 0.0f, s));
-    CT_TRY(launch_fill(sc.vy, g->pad.nvy, 0.0f, s));
-    CT_TRY(launch_project_T(g, y, y_dtype, sc.vx, sc.vy, stop, s));
-    return launch_unpad_sum(g, sc.vx, sc.vy, x, in_scale, stop, s);
+    // 2D Joseph A^T: gathered per pixel
+    return launch_project_T_par(g, y, y_dtype, x, in_scale, stop, s);
 }
 
 }  // namespace ct
@@ -2449,7 +2508,7 @@ extern "C" int ct_backproject_AT(const ct_geometry *g, const void *y, int y_dtyp
     if (batch == 0) return CT_OK;
     CT_ARG_CHECK(x && y, "ct_backproject_AT: NULL array");
     const size_t need = op_scratch_bytes(g, CT_OP_AT, CT_F32);
-    CT_ARG_CHECK(ws && ws_bytes >= need, "ct_backproject_AT: workspace too small");
+    CT_ARG_CHECK(need == 0 || (ws && ws_bytes >= need), "ct_backproject_AT: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     OpScratch sc = carve_op_scratch(g, CT_OP_AT, CT_F32, ws);
     const size_t es = y_dtype == CT_F16 ? 2 : 4;
