@@ -65,6 +65,16 @@ struct ColT {
     float ar, is, sxy, pad;
 };
 
+// Per (view, detector column) part of a cone-beam ray's set-up for the
+// projector (see ray_column): 1 / r_a, the plane offset, r_x^2 + r_y^2, the
+// plane range allowed by the in-plane coordinate, that coordinate's offset
+// (padding included) and slope, and the dominant axis.
+struct RayCol {
+    double inv_ra, base, sxy, jlo, jhi;
+    float fb0, gb;
+    int ax, pad;
+};
+
 struct GeomK {
     int kind;          // 0 = 2D parallel, 1 = 3D cone
     int proj;          // CT_JOSEPH or CT_SIDDON
@@ -75,6 +85,7 @@ struct GeomK {
     const float *cs32; // device: the same table rounded to FP32
     const int *axis;   // device: per-view dominant axis for 2D (0 = x, 1 = y)
     const ColT *colT;  // device: per (view, column) table of cone-beam rays, P x nu
+    const RayCol *rcol;  // device, cone: per (view, column) part of the projector's ray set-up, P x nu
     const int *vdom;   // device: per view, bit 0 / bit 1 set if any column is x- / y-dominant
     const int4 *vrect; // device, cone: per view, detector columns [x, y] and rows [z, w] outside
                        // of which no ray meets the volume (bounding box of its shadow)
@@ -118,6 +129,7 @@ struct ct_geometry {
     double *d_cs = nullptr;
     float *d_cs32 = nullptr;
     ct::ColT *d_colT = nullptr;
+    ct::RayCol *d_rcol = nullptr;
     int *d_vdom = nullptr;
     int4 *d_vrect = nullptr;
     int *d_vshift = nullptr;
@@ -161,7 +173,7 @@ int launch_pad_copy(const ct_geometry *g, const void *x, int x_dtype, float *vx,
                     const int *stop, hipStream_t s);
 int launch_project(const ct_geometry *g, const float *vx, const float *vy, void *y,
                    int y_dtype, const float *out_scale, const int *stop, hipStream_t s);
-// fills g->d_colT (cone geometries) from the kernel view; synchronous
+// fills g->d_rcol and g->d_colT (cone geometries) from the kernel view
 int launch_col_table(ct_geometry *g);
 // cone-beam A^T gathered per voxel straight into x (times *scale if given);
 // ys: n_rays floats of scratch for the step-weighted data

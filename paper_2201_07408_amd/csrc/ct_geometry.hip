@@ -279,12 +279,14 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
     k.cs32 = g->d_cs32;
     k.axis = g->d_axis;
     k.colT = nullptr;
+    k.rcol = nullptr;
     k.vdom = nullptr;
     k.vrect = nullptr;
     k.vshift = nullptr;
     g->pad = pad_layout(k);
     if (d.kind == CT_CONE_CIRCULAR_3D) {
         if (hipMalloc(&g->d_colT, sizeof(ColT) * (size_t)P * d.nu) != hipSuccess ||
+            hipMalloc(&g->d_rcol, sizeof(RayCol) * (size_t)P * d.nu) != hipSuccess ||
             hipMalloc(&g->d_vdom, sizeof(int) * (size_t)P) != hipSuccess ||
             hipMalloc(&g->d_vrect, sizeof(int4) * (size_t)P) != hipSuccess ||
             hipMalloc(&g->d_vshift, sizeof(int) * (size_t)P) != hipSuccess) {
@@ -299,6 +301,7 @@ extern "C" int ct_geometry_create(const ct_geometry_desc *desc, ct_geometry **ou
             return CT_ERR_HIP;
         }
         k.colT = g->d_colT;
+        k.rcol = g->d_rcol;
         k.vdom = g->d_vdom;
         k.vrect = g->d_vrect;
         k.vshift = g->d_vshift;
@@ -317,6 +320,7 @@ extern "C" void ct_geometry_destroy(ct_geometry *g) {
     if (g->d_cs) (void)hipFree(g->d_cs);
     if (g->d_cs32) (void)hipFree(g->d_cs32);
     if (g->d_colT) (void)hipFree(g->d_colT);
+    if (g->d_rcol) (void)hipFree(g->d_rcol);
     if (g->d_vdom) (void)hipFree(g->d_vdom);
     if (g->d_vrect) (void)hipFree(g->d_vrect);
     if (g->d_vshift) (void)hipFree(g->d_vshift);

@@ -148,60 +148,91 @@ __device__ __forceinline__ void cone_ray_xy(const GeomK &g, double c, double s, 
     ry = -g.sdd * s + u * c;
 }
 
-template <bool CONE>
-__device__ __forceinline__ RaySetup ray_setup(const GeomK &g, const PadLayout &L, int p, int av, int au) {
+// Clip [jlo, jhi] to the planes where f(j) = f0 + j g lies in (-1, N), the
+// support of the interpolation along one in-plane axis.
+__device__ __forceinline__ void clip_planes(double f0, double gg, int N, double &jlo, double &jhi) {
+    if (gg == 0.0) {
+        if (!(f0 > -1.0 && f0 < (double)N)) { jlo = 1.0; jhi = 0.0; }
+        return;
+    }
+    const double t1 = (-1.0 - f0) / gg, t2 = ((double)N - f0) / gg;
+    jlo = fmax(jlo, floor(fmin(t1, t2)) + 1.0);
+    jhi = fmin(jhi, ceil(fmax(t1, t2)) - 1.0);
+}
+
+// The part of a ray's set-up that depends on its detector column only: the
+// dominant axis, the in-plane coordinate along the other axis, the plane
+// range that coordinate allows, 1 / r_a and r_x^2 + r_y^2 (parallel beam:
+// the bin).  On the circular orbit every row of a column shares it.
+__device__ __forceinline__ RayCol ray_column(const GeomK &g, int p, int au, bool cone) {
     const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
-    double ox, oy, rx, ry, rz;
-    if (CONE) {
-        const double v = (av - 0.5 * (g.nv - 1)) * g.dv;
+    double ox, oy, rx, ry;
+    if (cone) {
         ox = g.sod * c;
         oy = g.sod * s;
         cone_ray_xy(g, c, s, au, rx, ry);
-        rz = v;
     } else {
         const double sa = (au - 0.5 * (g.nu - 1)) * g.du;
         ox = sa * c;
         oy = sa * s;
         rx = -s;
         ry = c;
-        rz = 0.0;
     }
-    RaySetup R;
-    R.ax = CONE ? (fabs(rx) >= fabs(ry) ? 0 : 1) : g.axis[p];
-    const double ra = R.ax == 0 ? rx : ry, rb = R.ax == 0 ? ry : rx;
-    const double oa = R.ax == 0 ? ox : oy, ob = R.ax == 0 ? oy : ox;
-    const int Na = R.ax == 0 ? g.nx : g.ny, Nb = R.ax == 0 ? g.ny : g.nx;
+    RayCol Q;
+    Q.ax = cone ? (fabs(rx) >= fabs(ry) ? 0 : 1) : g.axis[p];
+    const double ra = Q.ax == 0 ? rx : ry, rb = Q.ax == 0 ? ry : rx;
+    const double oa = Q.ax == 0 ? ox : oy, ob = Q.ax == 0 ? oy : ox;
+    const int Na = Q.ax == 0 ? g.nx : g.ny, Nb = Q.ax == 0 ? g.ny : g.nx;
     const double inv_vox = 1.0 / g.vox;
-    const double inv_ra = 1.0 / ra;
-    const double base = -0.5 * (Na - 1) - oa * inv_vox;   // plane j at j + base (voxel units from o)
-    const double gb = rb * inv_ra;
-    const double fb0 = ob * inv_vox + 0.5 * (Nb - 1) + gb * base;
+    Q.inv_ra = 1.0 / ra;
+    Q.base = -0.5 * (Na - 1) - oa * inv_vox;   // plane j at j + base (voxel units from o)
+    const double gb = rb * Q.inv_ra;
+    const double fb0 = ob * inv_vox + 0.5 * (Nb - 1) + gb * Q.base;
     double jlo = 0.0, jhi = (double)(Na - 1);
-    auto clip = [&](double f0, double gg, int N) {
-        if (gg == 0.0) {
-            if (!(f0 > -1.0 && f0 < (double)N)) { jlo = 1.0; jhi = 0.0; }
-            return;
-        }
-        const double t1 = (-1.0 - f0) / gg, t2 = ((double)N - f0) / gg;
-        jlo = fmax(jlo, floor(fmin(t1, t2)) + 1.0);
-        jhi = fmin(jhi, ceil(fmax(t1, t2)) - 1.0);
-    };
-    clip(fb0, gb, Nb);
-    double gc = 0.0, fc0 = 0.0;
-    if (CONE) {
-        gc = rz * inv_ra;
-        fc0 = 0.5 * (g.nz - 1) + gc * base;   // source at z = 0
-        clip(fc0, gc, g.nz);
+    clip_planes(fb0, gb, Nb, jlo, jhi);
+    Q.jlo = jlo;
+    Q.jhi = jhi;
+    Q.fb0 = (float)(fb0 + kPad);
+    Q.gb = (float)gb;
+    Q.sxy = rx * rx + ry * ry;
+    return Q;
+}
+
+// The rest of the set-up for detector row av (cone beam: the z slope and
+// offset, the plane range they allow, and the step weight).
+__device__ __forceinline__ RaySetup ray_finish(const GeomK &g, const PadLayout &L, const RayCol &Q, int av, bool cone) {
+    RaySetup R;
+    R.ax = Q.ax;
+    double jlo = Q.jlo, jhi = Q.jhi;
+    double gc = 0.0, fc0 = 0.0, rz = 0.0;
+    if (cone) {
+        rz = (av - 0.5 * (g.nv - 1)) * g.dv;
+        gc = rz * Q.inv_ra;
+        fc0 = 0.5 * (g.nz - 1) + gc * Q.base;   // source at z = 0
+        clip_planes(fc0, gc, g.nz, jlo, jhi);
     }
     if (!(jlo <= jhi)) { jlo = 1.0; jhi = 0.0; }
     R.j0 = (int)jlo;
     R.j1 = (int)jhi;
-    R.fb0 = (float)(fb0 + kPad);
-    R.gb = (float)gb;
+    R.fb0 = Q.fb0;
+    R.gb = Q.gb;
     R.fc0 = (float)(fc0 + L.pz);
     R.gc = (float)gc;
-    R.step = (float)(g.vox * sqrt(rx * rx + ry * ry + rz * rz) * fabs(inv_ra));
+    R.step = (float)(g.vox * sqrt(Q.sxy + rz * rz) * fabs(Q.inv_ra));
     return R;
+}
+
+template <bool CONE>
+__device__ __forceinline__ RaySetup ray_setup(const GeomK &g, const PadLayout &L, int p, int av, int au) {
+    return ray_finish(g, L, ray_column(g, p, au, CONE), av, CONE);
+}
+
+// The per-(view, column) part of the cone-beam ray set-up, tabulated once
+// at geometry creation by the same code the kernels would run.
+__global__ void k_ray_columns(GeomK g, RayCol *__restrict__ T) {
+    const int au = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y;
+    if (au >= g.nu) return;
+    T[(size_t)p * g.nu + au] = ray_column(g, p, au, true);
 }
 
 // Direct (cache-gather) evaluation of the samples of one ray on planes
@@ -464,7 +495,8 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
         }
     }
     __shared__ float4 tile4[kPC * kSR * kSC / 4];
-    __shared__ uint32_t s_box[kMaxChunks];   // (b0 + 1) << 16 | c0 << 6 | rows; b0 = -1: direct
+    // box words: (b0 + 1) << 19 | (cells - 1) << 16 | c0 << 6 | rows; 0: direct
+    __shared__ uint32_t s_box[kMaxChunks];
     // The corner rays and the per-wavefront plane ranges are read only
     // before the first chunk is staged (a barrier lies between), so they
     // share the tile's space: 20,480 bytes of LDS in all, eight workgroups
@@ -478,7 +510,7 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
     // Lanes outside the detector repeat the ray of the tile's nearest
     // detector pixel: their samples are valid (inside the tile's boxes) and
     // are not stored, so no lane needs a separate inactive path.
-    const RaySetup R = ray_setup<true>(g, L, p, min(av, g.nv - 1), min(max(au, 0), g.nu - 1));
+    const RaySetup R = ray_finish(g, L, g.rcol[(size_t)p * g.nu + min(max(au, 0), g.nu - 1)], min(av, g.nv - 1), true);
     {
         const bool ne = R.j0 <= R.j1;
         const int a = wave_min(ne ? R.j0 : 0x7fffffff), b = wave_max(ne ? R.j1 : -1);
@@ -549,8 +581,11 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
         const int c0 = max((int)floorf(cmin) - 1, 0);
         const int c1 = min((int)floorf(cmax) + 2, nrows - 1);
         const int nr = c1 - c0 + 1;
-        const bool fits = nr <= kSR && b1 - b0 < 4 * kNQ && c0 < 1024 && b0 < 65535;
-        s_box[c] = fits ? ((uint32_t)(b0 + 1) << 16) | ((uint32_t)c0 << 6) | (uint32_t)nr : 0u;
+        // only the 16-byte cells that cover the box are staged
+        const int ncl = (b1 - b0) / 4 + 1;
+        const bool fits = nr <= kSR && b1 - b0 < 4 * kNQ && c0 < 1024 && b0 < 8191;
+        s_box[c] = fits ? ((uint32_t)(b0 + 1) << 19) | ((uint32_t)(ncl - 1) << 16) | ((uint32_t)c0 << 6) | (uint32_t)nr
+                        : 0u;
     }
     // Staging: work-item t < kStage owns 16-byte column t % kNQ of box row
     // t / kNQ in every plane of a chunk, so its element offset within the
@@ -568,9 +603,10 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
     // chunk c's loads into registers; bx is its box word (0: not staged)
     auto fetch = [&](int c, uint32_t bx) {
         if (bx == 0u) return;
-        const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u), nr = (int)(bx & 63u);
+        const int b0 = (int)(bx >> 19) - 1, c0 = (int)((bx >> 6) & 1023u), nr = (int)(bx & 63u);
+        const int ncl = (int)((bx >> 16) & 7u) + 1;
         const int ja = jlo + c * kPC;
-        if (stager && r_t < nr) {
+        if (stager && r_t < nr && c4_t < ncl) {
             const uint32_t e0b = 4u * (base + __umul24((uint32_t)ja, S) + __umul24((uint32_t)c0, Rw) + (uint32_t)b0);
 #pragma unroll
             for (int pl = 0; pl < kPC; ++pl) {
@@ -592,11 +628,11 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
     for (int c = 0; c < nch; ++c) {
         const int ja = jlo + c * kPC;
         const uint32_t bx = bx_next;
-        const int b0 = (int)(bx >> 16) - 1, c0 = (int)((bx >> 6) & 1023u);
+        const int b0 = (int)(bx >> 19) - 1, c0 = (int)((bx >> 6) & 1023u);
         if (bx != 0u) {
-            const int nr = (int)(bx & 63u);
+            const int nr = (int)(bx & 63u), ncl = (int)((bx >> 16) & 7u) + 1;
             __syncthreads();   // previous chunk's readers are done with the tile
-            if (stager && r_t < nr) {
+            if (stager && r_t < nr && c4_t < ncl) {
 #pragma unroll
                 for (int pl = 0; pl < kPC; ++pl) tile4[(pl * kSR + r_t) * (kSC / 4) + c4_t] = pre[pl];
             }
@@ -2057,6 +2093,8 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
 
 int launch_col_table(ct_geometry *g) {
     dim3 grid((g->k.nu + 255) / 256, g->k.P), block(256);
+    hipLaunchKernelGGL(k_ray_columns, grid, block, 0, 0, g->k, g->d_rcol);
+    CT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_col_table, grid, block, 0, 0, g->k, g->d_colT);
     CT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_view_dom, dim3((g->k.P + 255) / 256), dim3(256), 0, 0, g->k, g->d_colT, g->d_vdom,
