@@ -1010,6 +1010,362 @@ __global__ __launch_bounds__(256) void k_project_T_staged(GeomK g, const float *
     }
 }
 
+// Detector columns [a_lo, a_hi] of a view whose rays, on the sampling plane
+// at distance D from the source along the dominant axis (axis 0: planes
+// x = const, b = y; axis 1: planes y = const, b = x), have in-plane
+// coordinate f_b with lo < f_b - ib < hi, where e0 = o_b - (ib - C_b) vox
+// so that f_b - ib = (e0 + D t) / vox with t = r_b / r_a.  t is a
+// linear-fractional function of the column, inverted at the two ends; all
+// columns when the inverse interval wraps through infinity, none
+// (a_hi < a_lo) when it misses the detector.
+__device__ __forceinline__ void column_range(const GeomK &g, int axis, double c, double s, double D, double e0,
+                                             double lo, double hi, int &a_lo, int &a_hi) {
+    const double Cu = 0.5 * (g.nu - 1);
+    const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
+    const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
+    const double iD = 1.0 / D, tm = (lo * g.vox - e0) * iD, tp = (hi * g.vox - e0) * iD;
+    const double dm = ga * tm - al, dp = ga * tp - al;
+    a_lo = 0;
+    a_hi = g.nu - 1;
+    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
+        const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
+        const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
+        a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
+        a_hi = ahi < (double)g.nu ? min((int)ceil(ahi), g.nu - 1) : g.nu - 1;
+        if (alo >= (double)g.nu || ahi <= -1.0) a_hi = -1;
+    }
+}
+
+// The cone-beam Joseph transpose, factored by detector column.  On a
+// sampling plane all rows of one detector column share the in-plane
+// coordinate f_b, so a voxel's weight in ray (u, v) is tent(f_b(u) - ib)
+// times tent(f_c(u, v) - iz): per view, the column's rows are first
+// splatted in z onto the plane, z_sheet(u, plane)[iz] = sum over rows of
+// tent(f_c - iz) ys(u, v), once per (plane, column) of the workgroup's
+// block, and each voxel column then gathers its two or three candidate
+// columns' sheets with weight tent(f_b - ib).  The splat, which the
+// per-voxel form repeated for every voxel column that a detector column
+// reaches (two or three), is done once.  Sheets live in LDS (17-float
+// stride, odd across banks); the footprint of the step-weighted data is
+// staged as in k_project_T_staged.  A (view, axis) whose plane needs more
+// than kZU columns falls back to the per-voxel splat, in the same LDS.
+constexpr int kZU = 24;              // detector columns per plane in the z sheets
+constexpr int kZS = kZC + 1;         // floats per sheet
+constexpr int kTG = 2;               // zero guard rows on either side of a staged view
+
+// Eight voxels of one z sheet from the staged rows of a detector column
+// (t[r kTSU] = row bv0 + r, kTG guard rows on either side): voxel zz takes
+// the rows around vc = vcb + zz / a1 with weights 1 - |a1| |v - vc| clipped
+// at zero.  For |a1| < 1 those are rows floor(vc) - 1 .. floor(vc) + 2, the
+// inner two always weighted; for |a1| >= 1 only floor(vc) and floor(vc) + 1.
+template <bool CLAMP>
+__device__ __forceinline__ void sheet_rows(float *out, const float *t, float vcb, float ia1, float aa, float am,
+                                           int bv0) {
+    if (aa < 1.0f) {
+        const float *tb = t - (bv0 + 1) * kTSU;
+#pragma unroll
+        for (int zz = 0; zz < kZC / 2; ++zz) {
+            const float vc = fmaf((float)zz, ia1, vcb);
+            const float fl = floorf(vc), f = vc - fl;
+            const float *tr = CLAMP ? t + min(max((int)fl - 1 - bv0, -kTG), kTSV + kTG - 4) * kTSU
+                                    : tb + (int)fl * kTSU;
+            const float w1 = fmaf(-aa, f, 1.0f), w2 = fmaf(aa, f, am);
+            const float w0 = fmaxf(w1 - aa, 0.0f), w3 = fmaxf(w2 - aa, 0.0f);
+            out[zz] = fmaf(w0, tr[0], fmaf(w1, tr[kTSU], fmaf(w2, tr[2 * kTSU], w3 * tr[3 * kTSU])));
+        }
+    } else {
+        const float *tb = t - bv0 * kTSU;
+#pragma unroll
+        for (int zz = 0; zz < kZC / 2; ++zz) {
+            const float vc = fmaf((float)zz, ia1, vcb);
+            const float fl = floorf(vc), f = vc - fl;
+            const float *tr = CLAMP ? t + min(max((int)fl - bv0, -kTG), kTSV + kTG - 2) * kTSU
+                                    : tb + (int)fl * kTSU;
+            const float w1 = fmaxf(fmaf(-aa, f, 1.0f), 0.0f), w2 = fmaxf(fmaf(aa, f, am), 0.0f);
+            out[zz] = fmaf(w1, tr[0], w2 * tr[kTSU]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const float *__restrict__ ys, float *__restrict__ x,
+                                                          const float *__restrict__ scale,
+                                                          const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    __shared__ float s_z[16 * kZU * kZS];
+    __shared__ double s_fb[16 * kZU];       // f_b of each (plane, column) pair
+    // staged footprint with kTG zero guard rows above and below each view's rows
+    constexpr int kTVS = (kTSV + 2 * kTG) * kTSU;
+    __shared__ float4 tile4[kTVG * kTVS / 4];
+    __shared__ int s_box[kTVG][2];
+    __shared__ int s_rng[kTVG][2][16][2];   // per view, axis, plane: first column, column count
+    // per view, axis, plane: the column (relative to the first) whose ray
+    // meets the plane at f_b (relative to the block's first voxel column),
+    // col(f_b) = (n0 + n1 f_b) / (d0 + d1 f_b) + Cu - first, as (n0, n1, d0, d1)
+    __shared__ float4 s_cf[kTVG][2][16];
+    __shared__ int s_wide[kTVG][2];
+    __shared__ int s_fit;
+    static_assert(256 * kATS <= 16 * kZU * kZS, "per-voxel fallback slots fit the sheets");
+    const float *tile = (const float *)tile4;
+    const int tid = threadIdx.y * 16 + threadIdx.x;
+    const int ix0 = blockIdx.x * 16, iy0 = blockIdx.y * 16, iz0 = blockIdx.z * kZC;
+    const int ix = ix0 + threadIdx.x, iy = iy0 + threadIdx.y;
+    const bool active = ix < g.nx && iy < g.ny;   // the others stage and meet the barriers
+    const int nu = g.nu, nv = g.nv, P = g.P;
+    const double vox = g.vox, ivox = 1.0 / vox;
+    const double Cx = 0.5 * (g.nx - 1), Cy = 0.5 * (g.ny - 1), Cz = 0.5 * (g.nz - 1), Cu = 0.5 * (nu - 1);
+    const float Cvf = (float)(0.5 * (nv - 1));
+    const float zoff = (float)(0.5 * (g.nz - 1) - iz0);   // f_c - iz0 = zoff + a1 (av - Cv)
+    const double bx0 = (ix0 - 1 - Cx) * vox, bx1 = (min(ix0 + 15, g.nx - 1) + 1 - Cx) * vox;
+    const double by0 = (iy0 - 1 - Cy) * vox, by1 = (min(iy0 + 15, g.ny - 1) + 1 - Cy) * vox;
+    const double bz0 = (iz0 - 1 - Cz) * vox, bz1 = (min(iz0 + kZC - 1, g.nz - 1) + 1 - Cz) * vox;
+    constexpr int Q = kTSU / 4;
+    constexpr int kCells = kTVG * kTSV * Q;
+    for (int q = tid; q < kTVG * 2 * kTG * kTSU; q += 256) {   // guard rows, once
+        const int vv = q / (2 * kTG * kTSU), r = (q / kTSU) % (2 * kTG), c = q % kTSU;
+        const_cast<float *>(tile)[vv * kTVS + (r < kTG ? r : kTSV + r) * kTSU + c] = 0.0f;
+    }
+    const int zmax = min(kZC, g.nz - iz0);   // voxels of the chunk inside the volume
+    double acc[kZC];
+    float accz[kZC];
+#pragma unroll
+    for (int z = 0; z < kZC; ++z) { acc[z] = 0.0; accz[z] = 0.0f; }
+    // z splat of detector column au (its table entry T) on the plane at
+    // distance D from the source into the 16 slots at sl (rows feeding the
+    // chunk [iz0 - 1, iz0 + kZC]); w scales every contribution
+    auto splat = [&](float *sl, const ColT &T, double D, int p, int au, float w, bool fit, int bu0, int bv0,
+                     const float *tv) {
+        const float a1 = (float)D * T.ar, ia1 = 1.0f / a1;
+        const float r1 = fmaf(-1.0f - zoff, ia1, Cvf), r2 = fmaf((float)kZC - zoff, ia1, Cvf);
+        const int v0 = max((int)ceilf(fminf(r1, r2)), 0), v1 = min((int)floorf(fmaxf(r1, r2)), nv - 1);
+        const int lu = min(max(au - bu0, 0), kTSU - 1);
+        const float *yp = ys + (size_t)p * nv * nu + au;
+        for (int av = v0; av <= v1; ++av) {
+            const float zf = fmaf(a1, (float)av - Cvf, zoff);
+            const float zl = floorf(zf), w1 = zf - zl;
+            const int zi = (int)zl;
+            const float yv = fit ? tv[min(max(av - bv0, 0), kTSV - 1) * kTSU + lu] : yp[(size_t)av * nu];
+            const float val = w * yv;
+            if ((unsigned)zi < (unsigned)kZC) sl[zi] = fmaf(1.0f - w1, val, sl[zi]);
+            if ((unsigned)(zi + 1) < (unsigned)kZC) sl[zi + 1] = fmaf(w1, val, sl[zi + 1]);
+        }
+    };
+    for (int p0 = 0; p0 < P; p0 += kTVG) {
+        __syncthreads();   // the previous group's readers are done with the tile, sheets and tables
+        if (tid == 0) s_fit = 1;
+        if (tid < kTVG && p0 + tid < P) {
+            const int p = p0 + tid;
+            const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+            for (int k = 0; k < 4; ++k) {
+                const double px = (k & 1) ? bx1 : bx0, py = (k & 2) ? by1 : by0;
+                const double U = g.sod - (px * c + py * s);
+                const double M = g.sdd / U;
+                const double fu = M * (py * c - px * s) / g.du + Cu;
+                umin = fmin(umin, fu); umax = fmax(umax, fu);
+                const double va = M * bz0 / g.dv + 0.5 * (nv - 1), vb = M * bz1 / g.dv + 0.5 * (nv - 1);
+                vmin = fmin(vmin, fmin(va, vb)); vmax = fmax(vmax, fmax(va, vb));
+            }
+            const int u0 = ((int)floor(umin) - 1) & ~3, u1 = (int)floor(umax) + 2;
+            const int v0 = (int)floor(vmin) - 1, v1 = (int)floor(vmax) + 2;
+            s_box[tid][0] = u0;
+            s_box[tid][1] = v0;
+            if (u1 - u0 >= kTSU || v1 - v0 >= kTSV || !(umin > -1e6 && umax < 1e6 && vmin > -1e6 && vmax < 1e6))
+                atomicAnd(&s_fit, 0);
+        }
+        if (tid < kTVG * 2) s_wide[tid / 2][tid % 2] = 0;
+        __syncthreads();
+        // column range of every (view, axis, plane) of the block: the columns
+        // whose f_b at the plane lies within one voxel of the block's b range
+        if (tid >= 64 && tid < 64 + kTVG * 32) {
+            const int q = tid - 64, vv = q / 32, a = (q / 16) % 2, jj = q % 16;
+            const int p = p0 + vv;
+            int first = 0, cnt = 0;
+            if (p < P && (g.vdom[p] & (1 << a)) && (a ? iy0 + jj < g.ny : ix0 + jj < g.nx)) {
+                const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+                const double ox = g.sod * c, oy = g.sod * s;
+                const double D = a ? (iy0 + jj - Cy) * vox - oy : (ix0 + jj - Cx) * vox - ox;
+                const int ib0 = a ? ix0 : iy0, nb = min(16, (a ? g.nx : g.ny) - ib0);
+                const double e0 = (a ? ox : oy) - (ib0 - (a ? Cx : Cy)) * vox;
+                int lo, hi;
+                column_range(g, a, c, s, D, e0, -1.0, (double)nb, lo, hi);
+                first = lo;
+                cnt = hi >= lo ? hi - lo + 1 : 0;
+                if (cnt > kZU) atomicOr(&s_wide[vv][a], 1);
+                // the inverse map of column_range, written out for the gather
+                const double al = a ? -s : c, be = a ? -g.sdd * c : -g.sdd * s;
+                const double ga = a ? c : -s, de = a ? -g.sdd * s : -g.sdd * c;
+                s_cf[vv][a][jj] = make_float4((float)((be * D + de * e0) / g.du), (float)(-de * vox / g.du),
+                                              (float)(-ga * e0 - al * D), (float)(ga * vox));
+            }
+            s_rng[vv][a][jj][0] = first;
+            s_rng[vv][a][jj][1] = cnt;
+        }
+        const bool fit = s_fit != 0;
+        if (fit) {
+            for (int q = tid; q < kCells; q += 256) {
+                const int vv = q / (kTSV * Q), r = (q / Q) % kTSV, c4 = 4 * (q % Q);
+                const int p = p0 + vv;
+                float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (p < P) {
+                    const int v = s_box[vv][1] + r, u = s_box[vv][0] + c4;
+                    if ((unsigned)v < (unsigned)nv) {
+                        const float *row = ys + ((size_t)p * nv + v) * nu;
+                        if ((nu & 3) == 0 && (unsigned)u <= (unsigned)(nu - 4)) {
+                            e = *reinterpret_cast<const float4 *>(row + u);
+                        } else {
+                            float t4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                if (u + k >= 0 && u + k < nu) t4[k] = row[u + k];
+                            e = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                        }
+                    }
+                }
+                tile4[(vv * kTVS + (r + kTG) * kTSU) / 4 + c4 / 4] = e;
+            }
+        }
+        __syncthreads();
+        for (int vv = 0; vv < kTVG && p0 + vv < P; ++vv) {
+            const int p = p0 + vv;
+            const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
+            const double ox = g.sod * c, oy = g.sod * s;
+            const float *tv = tile + vv * kTVS + kTG * kTSU;   // first staged row
+            const int bu0 = s_box[vv][0], bv0 = s_box[vv][1];
+            const ColT *Tp = g.colT + (size_t)p * nu;
+            const int vd = g.vdom[p];
+#pragma unroll 1
+            for (int a = 0; a < 2; ++a) {
+                if (!(vd & (1 << a))) continue;   // uniform: no column of this view has this axis
+                // this work-item's voxel column on the axis's planes
+                const int jj = a ? (int)threadIdx.y : (int)threadIdx.x;
+                const int ib = a ? ix : iy;
+                const double D = a ? (iy - Cy) * vox - oy : (ix - Cx) * vox - ox;
+                const double e0 = (a ? ox : oy) - (ib - (a ? Cx : Cy)) * vox;
+                const double eb0 = (a ? ox : oy) - ((a ? ix0 : iy0) - (a ? Cx : Cy)) * vox;
+                if (!s_wide[vv][a]) {
+                    // splat: (plane, column) pairs of the block, z by z in
+                    // registers.  Voxel z takes the rows with |f_c - z| < 1,
+                    // f_c - z = a1 (v - vc(z)), vc(z) = Cv + (z - zoff) / a1:
+                    // with |a1| in (1/2, 2) (one row per voxel within a factor
+                    // of two) those are among floor(vc) - 1 .. floor(vc) + 2,
+                    // with tent weights 1 - |a1| |v - vc| clipped at zero.
+                    // Half a pair (8 voxels of z) per step: 768 half pairs,
+                    // three per work-item.  The first half also records the
+                    // column's f_b on the plane relative to the block's first
+                    // voxel column (NaN for a column of the other axis).
+                    for (int h = tid; h < 2 * 16 * kZU; h += 256) {
+                        const int q = h >> 1, zh = (h & 1) * (kZC / 2);
+                        const int pj = q / kZU, k = q % kZU;
+                        if (k >= s_rng[vv][a][pj][1]) continue;
+                        const int au = s_rng[vv][a][pj][0] + k;
+                        const ColT T = Tp[au];
+                        const bool other = (T.is > 0.0f) != (a == 0);   // the projector's dominant axis
+                        const double Dp = a ? (iy0 + pj - Cy) * vox - oy : (ix0 + pj - Cx) * vox - ox;
+                        if (zh == 0) s_fb[q] = other ? __builtin_nan("") : (eb0 + Dp * T.t) * ivox;
+                        if (other) continue;
+                        float *sl = s_z + q * kZS;
+                        const float a1 = (float)Dp * T.ar, aa = fabsf(a1);
+                        if (!(aa > 0.5f && aa < 2.0f)) {   // steep or flat rows: row by row
+                            if (zh == 0) {
+#pragma unroll
+                                for (int z = 0; z < kZC; ++z) sl[z] = 0.0f;
+                                splat(sl, T, Dp, p, au, 1.0f, fit, bu0, bv0, tv);
+                            }
+                            continue;
+                        }
+                        const float ia1 = 1.0f / a1, vc0 = fmaf(-zoff, ia1, Cvf);
+                        const float am = 1.0f - aa;
+                        if (fit) {
+                            const float vcb = fmaf((float)zh, ia1, vc0);
+                            const float *t = tv + min(max(au - bu0, 0), kTSU - 1);   // row v at t[(v - bv0) kTSU]
+                            float out[kZC / 2];
+                            // The rows of the voxels of the chunk lie in the box and
+                            // the guards; those beyond the volume (last chunk) are
+                            // clamped into them.
+                            if (zmax == kZC) sheet_rows<false>(out, t, vcb, ia1, aa, am, bv0);
+                            else sheet_rows<true>(out, t, vcb, ia1, aa, am, bv0);
+#pragma unroll
+                            for (int zz = 0; zz < kZC / 2; ++zz) sl[zh + zz] = out[zz];
+                        } else {
+                            const float *yp = ys + (size_t)p * nv * nu + au;
+                            const int zend = min(zh + kZC / 2, zmax);
+                            for (int z = zh; z < zend; ++z) {
+                                const float vc = fmaf((float)z, ia1, vc0);
+                                const float fl = floorf(vc), f = vc - fl;
+                                const int iv = (int)fl - 1;
+                                const float w1 = fmaf(-aa, f, 1.0f), w2 = fmaf(aa, f, am);
+                                const float w0 = fmaxf(w1 - aa, 0.0f), w3 = fmaxf(w2 - aa, 0.0f);
+                                const float y0 = (unsigned)iv < (unsigned)nv ? yp[(size_t)iv * nu] : 0.0f;
+                                const float y1 = (unsigned)(iv + 1) < (unsigned)nv ? yp[(size_t)(iv + 1) * nu] : 0.0f;
+                                const float y2 = (unsigned)(iv + 2) < (unsigned)nv ? yp[(size_t)(iv + 2) * nu] : 0.0f;
+                                const float y3 = (unsigned)(iv + 3) < (unsigned)nv ? yp[(size_t)(iv + 3) * nu] : 0.0f;
+                                sl[z] = fmaf(w0, y0, fmaf(fmaxf(w1, 0.0f), y1, fmaf(fmaxf(w2, 0.0f), y2, w3 * y3)));
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    if (active) {
+                        // candidate columns: f_b within one voxel of this column's,
+                        // i.e. strictly between col(jb - 1) and col(jb + 1) where the
+                        // map has no pole in between (FP32, 1e-3 column of margin)
+                        const int first = s_rng[vv][a][jj][0], cnt = s_rng[vv][a][jj][1];
+                        const int jbi = ib - (a ? ix0 : iy0);
+                        const float4 cf = s_cf[vv][a][jj];
+                        const float fm = (float)(jbi - 1), fp = (float)(jbi + 1);
+                        const float dm = fmaf(cf.w, fm, cf.z), dp = fmaf(cf.w, fp, cf.z);
+                        int k0 = 0, k1 = cnt - 1;
+                        if ((dm > 0.0f && dp > 0.0f) || (dm < 0.0f && dp < 0.0f)) {
+                            const float c0 = (float)(Cu - first);
+                            const float um = fmaf(cf.y, fm, cf.x) / dm + c0, up = fmaf(cf.y, fp, cf.x) / dp + c0;
+                            k0 = max(k0, (int)ceilf(fminf(um, up) - 1e-3f));
+                            k1 = min(k1, (int)floorf(fmaxf(um, up) + 1e-3f));
+                        }
+                        const double jb = (double)jbi;
+                        for (int k = k0; k <= k1; ++k) {
+                            const float wb = 1.0f - fabsf((float)(s_fb[jj * kZU + k] - jb));
+                            if (!(wb > 0.0f)) continue;   // NaN: a column of the other axis
+                            const float *sl = s_z + (jj * kZU + k) * kZS;
+#pragma unroll
+                            for (int z = 0; z < kZC; ++z) accz[z] = fmaf(wb, sl[z], accz[z]);
+                        }
+                    }
+                    __syncthreads();   // sheets read before the next splat
+                } else {
+                    // wide planes: each voxel column splats its own candidates
+                    // into private slots (the sheets' LDS)
+                    float *sl = s_z + tid * kATS;
+                    if (active) {
+#pragma unroll
+                        for (int z = 0; z < kZC; ++z) sl[z] = 0.0f;
+                        int a_lo, a_hi;
+                        column_range(g, a, c, s, D, e0, -1.0, 1.0, a_lo, a_hi);
+                        for (int au = a_lo; au <= a_hi; ++au) {
+                            const ColT T = Tp[au];
+                            if ((T.is > 0.0f) != (a == 0)) continue;
+                            const float wb = 1.0f - fabsf((float)((e0 + D * T.t) * ivox));
+                            if (!(wb > 0.0f)) continue;
+                            splat(sl, T, D, p, au, wb, fit, bu0, bv0, tv);
+                        }
+#pragma unroll
+                        for (int z = 0; z < kZC; ++z) accz[z] += sl[z];
+                    }
+                    __syncthreads();   // private slots overlap the next sheets
+                }
+            }
+        }
+        // views summed in FP32 over the group, then in FP64
+#pragma unroll
+        for (int z = 0; z < kZC; ++z) { acc[z] += (double)accz[z]; accz[z] = 0.0f; }
+    }
+    if (!active) return;
+    const double sc = scale ? (double)*scale : 1.0;
+#pragma unroll
+    for (int z = 0; z < kZC; ++z) {
+        const int iz = iz0 + z;
+        if (iz < g.nz) x[((size_t)iz * g.ny + iy) * g.nx + ix] = (float)(acc[z] * sc);
+    }
+}
+
 // --------------------------------------------------------------- B_un
 
 // ------------------------------------------- line-intersection projector
@@ -2125,7 +2481,7 @@ int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, fl
     if (g->k.proj == CT_SIDDON)
         hipLaunchKernelGGL((k_project_T_staged<true>), grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
     else
-        hipLaunchKernelGGL((k_project_T_staged<false>), grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
+        hipLaunchKernelGGL(k_project_T_sheets, grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
     CT_LAUNCH_CHECK();
     return CT_OK;
 }
