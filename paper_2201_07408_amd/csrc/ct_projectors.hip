@@ -725,6 +725,10 @@ __global__ __launch_bounds__(256, 8) void k_project_staged(GeomK g, PadLayout L,
 }
 
 constexpr int kZC = 16;   // z voxels per work-item in the voxel-driven cone kernels
+// per-view classification word (vdom): bit 0 / 1 as in GeomK, then
+constexpr int kVdomX0 = 4;          // column 0 is x-dominant
+constexpr int kVdomOneSwitch = 8;   // the axis changes at most once across the detector,
+constexpr int kVdomSwitchShift = 8; // at the column stored from this bit up (0: never)
 
 // Per (view, column) ray table of a cone geometry (ColT), from the same
 // direction helper as the projector, so the dominant axis matches bit for
@@ -750,18 +754,22 @@ __global__ void k_col_table(GeomK g, ColT *__restrict__ T) {
 // offset of the projector's ray tiles that puts a tile edge at the first
 // column whose dominant axis differs from column 0's (the table's axis is
 // the projector's own decision), so that no tile mixes the two axes where
-// the axis changes once across the detector.
+// the axis changes once across the detector.  vdom also records column 0's
+// axis and, where the axis changes at most once, that column (kVdom*).
 __global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict__ vdom, int *__restrict__ vshift) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.P) return;
-    int f = 0, sw = 0;
+    int f = 0, sw = 0, changes = 0;
     const bool x0 = T[(size_t)p * g.nu].is > 0.0f;
+    bool prev = x0;
     for (int au = 0; au < g.nu; ++au) {
         const bool xd = T[(size_t)p * g.nu + au].is > 0.0f;
         f |= xd ? 1 : 2;
         if (sw == 0 && xd != x0) sw = au;
+        changes += xd != prev;
+        prev = xd;
     }
-    vdom[p] = f;
+    vdom[p] = f | (x0 ? kVdomX0 : 0) | (changes <= 1 ? kVdomOneSwitch | (sw << kVdomSwitchShift) : 0);
     vshift[p] = (kTU - sw % kTU) % kTU;
 }
 
@@ -1046,12 +1054,17 @@ __device__ __forceinline__ void column_range(const GeomK &g, int axis, double c,
 // columns' sheets with weight tent(f_b - ib).  The splat, which the
 // per-voxel form repeated for every voxel column that a detector column
 // reaches (two or three), is done once.  Sheets live in LDS (17-float
-// stride, odd across banks); the footprint of the step-weighted data is
-// staged as in k_project_T_staged.  A (view, axis) whose plane needs more
-// than kZU columns falls back to the per-voxel splat, in the same LDS.
+// stride and an odd plane stride, across banks); the footprint of the
+// step-weighted data and the column table entries of its columns are
+// staged as in k_project_T_staged.  Per (view, axis) the pairs to splat are
+// listed (each plane's column range cut to the axis's columns), so that
+// views whose fan spans both axes split the work instead of doubling it.  A
+// (view, axis) whose plane needs more than kZU columns falls back to the
+// per-voxel splat, in the same LDS.
 constexpr int kZU = 24;              // detector columns per plane in the z sheets
 constexpr int kZS = kZC + 1;         // floats per sheet
 constexpr int kTG = 2;               // zero guard rows on either side of a staged view
+constexpr int kPS = kZU * kZS + 1;   // floats per plane of sheets (odd: planes on distinct banks)
 
 // Eight voxels of one z sheet from the staged rows of a detector column
 // (t[r kTSU] = row bv0 + r, kTG guard rows on either side): voxel zz takes
@@ -1091,7 +1104,7 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ stop) {
     if (stop && *stop) return;
-    __shared__ float s_z[16 * kZU * kZS];
+    __shared__ float s_z[16 * kPS];
     __shared__ double s_fb[16 * kZU];       // f_b of each (plane, column) pair
     // staged footprint with kTG zero guard rows above and below each view's rows
     constexpr int kTVS = (kTSV + 2 * kTG) * kTSU;
@@ -1102,9 +1115,17 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
     // meets the plane at f_b (relative to the block's first voxel column),
     // col(f_b) = (n0 + n1 f_b) / (d0 + d1 f_b) + Cu - first, as (n0, n1, d0, d1)
     __shared__ float4 s_cf[kTVG][2][16];
+    // the (plane, column) pairs of each view and axis, plane << 8 | column
+    // within the plane's range, and their count
+    __shared__ unsigned short s_list[kTVG][2][16 * kZU];
+    __shared__ int s_npairs[kTVG][2];
+    // column table entries (t, then a_r and the signed step factor) of the
+    // staged columns of each view
+    __shared__ double s_Tt[kTVG][kTSU];
+    __shared__ float2 s_Tai[kTVG][kTSU];
     __shared__ int s_wide[kTVG][2];
     __shared__ int s_fit;
-    static_assert(256 * kATS <= 16 * kZU * kZS, "per-voxel fallback slots fit the sheets");
+    static_assert(256 * kATS <= 16 * kPS, "per-voxel fallback slots fit the sheets");
     const float *tile = (const float *)tile4;
     const int tid = threadIdx.y * 16 + threadIdx.x;
     const int ix0 = blockIdx.x * 16, iy0 = blockIdx.y * 16, iz0 = blockIdx.z * kZC;
@@ -1113,6 +1134,7 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
     const int nu = g.nu, nv = g.nv, P = g.P;
     const double vox = g.vox, ivox = 1.0 / vox;
     const double Cx = 0.5 * (g.nx - 1), Cy = 0.5 * (g.ny - 1), Cz = 0.5 * (g.nz - 1), Cu = 0.5 * (nu - 1);
+    const double Cv = 0.5 * (nv - 1), inv_du = 1.0 / g.du, inv_dv = 1.0 / g.dv;
     const float Cvf = (float)(0.5 * (nv - 1));
     const float zoff = (float)(0.5 * (g.nz - 1) - iz0);   // f_c - iz0 = zoff + a1 (av - Cv)
     const double bx0 = (ix0 - 1 - Cx) * vox, bx1 = (min(ix0 + 15, g.nx - 1) + 1 - Cx) * vox;
@@ -1132,9 +1154,9 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
     // z splat of detector column au (its table entry T) on the plane at
     // distance D from the source into the 16 slots at sl (rows feeding the
     // chunk [iz0 - 1, iz0 + kZC]); w scales every contribution
-    auto splat = [&](float *sl, const ColT &T, double D, int p, int au, float w, bool fit, int bu0, int bv0,
+    auto splat = [&](float *sl, float ar, double D, int p, int au, float w, bool fit, int bu0, int bv0,
                      const float *tv) {
-        const float a1 = (float)D * T.ar, ia1 = 1.0f / a1;
+        const float a1 = (float)D * ar, ia1 = 1.0f / a1;
         const float r1 = fmaf(-1.0f - zoff, ia1, Cvf), r2 = fmaf((float)kZC - zoff, ia1, Cvf);
         const int v0 = max((int)ceilf(fminf(r1, r2)), 0), v1 = min((int)floorf(fmaxf(r1, r2)), nv - 1);
         const int lu = min(max(au - bu0, 0), kTSU - 1);
@@ -1152,25 +1174,36 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
     for (int p0 = 0; p0 < P; p0 += kTVG) {
         __syncthreads();   // the previous group's readers are done with the tile, sheets and tables
         if (tid == 0) s_fit = 1;
-        if (tid < kTVG && p0 + tid < P) {
-            const int p = p0 + tid;
+        if (tid < 4 * kTVG) {
+            // footprint of each view from the block's four corner columns,
+            // one corner per lane, reduced over the view's four lanes
+            const int vv = tid >> 2, k = tid & 3;
+            const int p = min(p0 + vv, P - 1);
             const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
-            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
-            for (int k = 0; k < 4; ++k) {
-                const double px = (k & 1) ? bx1 : bx0, py = (k & 2) ? by1 : by0;
-                const double U = g.sod - (px * c + py * s);
-                const double M = g.sdd / U;
-                const double fu = M * (py * c - px * s) / g.du + Cu;
-                umin = fmin(umin, fu); umax = fmax(umax, fu);
-                const double va = M * bz0 / g.dv + 0.5 * (nv - 1), vb = M * bz1 / g.dv + 0.5 * (nv - 1);
-                vmin = fmin(vmin, fmin(va, vb)); vmax = fmax(vmax, fmax(va, vb));
+            const double px = (k & 1) ? bx1 : bx0, py = (k & 2) ? by1 : by0;
+            const double U = g.sod - (px * c + py * s);
+            const double M = g.sdd / U;
+            const double fu = M * (py * c - px * s) * inv_du + Cu;
+            const double va = M * bz0 * inv_dv + Cv, vb = M * bz1 * inv_dv + Cv;
+            const double vlo = fmin(va, vb), vhi = fmax(va, vb);
+            int bad = !(fu > -1e6 && fu < 1e6 && vlo > -1e6 && vhi < 1e6);
+            int ulo = bad ? 0 : (int)floor(fu), uhi = ulo;
+            int vl = bad ? 0 : (int)floor(vlo), vh = bad ? 0 : (int)floor(vhi);
+#pragma unroll
+            for (int m = 1; m < 4; m <<= 1) {
+                ulo = min(ulo, __shfl_xor(ulo, m));
+                uhi = max(uhi, __shfl_xor(uhi, m));
+                vl = min(vl, __shfl_xor(vl, m));
+                vh = max(vh, __shfl_xor(vh, m));
+                bad |= __shfl_xor(bad, m);
             }
-            const int u0 = ((int)floor(umin) - 1) & ~3, u1 = (int)floor(umax) + 2;
-            const int v0 = (int)floor(vmin) - 1, v1 = (int)floor(vmax) + 2;
-            s_box[tid][0] = u0;
-            s_box[tid][1] = v0;
-            if (u1 - u0 >= kTSU || v1 - v0 >= kTSV || !(umin > -1e6 && umax < 1e6 && vmin > -1e6 && vmax < 1e6))
-                atomicAnd(&s_fit, 0);
+            if (k == 0 && p0 + vv < P) {
+                const int u0 = (ulo - 1) & ~3, u1 = uhi + 2;
+                const int v0 = vl - 1, v1 = vh + 2;
+                s_box[vv][0] = u0;
+                s_box[vv][1] = v0;
+                if (bad || u1 - u0 >= kTSU || v1 - v0 >= kTSV) atomicAnd(&s_fit, 0);
+            }
         }
         if (tid < kTVG * 2) s_wide[tid / 2][tid % 2] = 0;
         __syncthreads();
@@ -1180,7 +1213,8 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
             const int q = tid - 64, vv = q / 32, a = (q / 16) % 2, jj = q % 16;
             const int p = p0 + vv;
             int first = 0, cnt = 0;
-            if (p < P && (g.vdom[p] & (1 << a)) && (a ? iy0 + jj < g.ny : ix0 + jj < g.nx)) {
+            const int vd = p < P ? g.vdom[p] : 0;
+            if (p < P && (vd & (1 << a)) && (a ? iy0 + jj < g.ny : ix0 + jj < g.nx)) {
                 const double c = g.cs[2 * p], s = g.cs[2 * p + 1];
                 const double ox = g.sod * c, oy = g.sod * s;
                 const double D = a ? (iy0 + jj - Cy) * vox - oy : (ix0 + jj - Cx) * vox - ox;
@@ -1188,17 +1222,38 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                 const double e0 = (a ? ox : oy) - (ib0 - (a ? Cx : Cy)) * vox;
                 int lo, hi;
                 column_range(g, a, c, s, D, e0, -1.0, (double)nb, lo, hi);
+                if (vd & kVdomOneSwitch) {
+                    // the axis's columns are one interval: keep the range within it
+                    const int sw = vd >> kVdomSwitchShift;
+                    const bool first_is_a = ((vd & kVdomX0) != 0) == (a == 0);
+                    if (first_is_a) {
+                        if (sw > 0) hi = min(hi, sw - 1);
+                    } else {
+                        lo = max(lo, sw);
+                    }
+                }
                 first = lo;
                 cnt = hi >= lo ? hi - lo + 1 : 0;
                 if (cnt > kZU) atomicOr(&s_wide[vv][a], 1);
                 // the inverse map of column_range, written out for the gather
                 const double al = a ? -s : c, be = a ? -g.sdd * c : -g.sdd * s;
                 const double ga = a ? c : -s, de = a ? -g.sdd * s : -g.sdd * c;
-                s_cf[vv][a][jj] = make_float4((float)((be * D + de * e0) / g.du), (float)(-de * vox / g.du),
+                s_cf[vv][a][jj] = make_float4((float)((be * D + de * e0) * inv_du), (float)(-de * vox * inv_du),
                                               (float)(-ga * e0 - al * D), (float)(ga * vox));
             }
             s_rng[vv][a][jj][0] = first;
             s_rng[vv][a][jj][1] = cnt;
+            // list of the pairs: exclusive scan of the planes' counts over
+            // the 16 lanes of (view, axis)
+            const int cl = min(cnt, kZU);
+            int inc = cl;
+#pragma unroll
+            for (int d = 1; d < 16; d <<= 1) {
+                const int o = __shfl_up(inc, d, 16);
+                if (jj >= d) inc += o;
+            }
+            for (int kk = 0; kk < cl; ++kk) s_list[vv][a][inc - cl + kk] = (unsigned short)(jj << 8 | kk);
+            if (jj == 15) s_npairs[vv][a] = inc;
         }
         const bool fit = s_fit != 0;
         if (fit) {
@@ -1222,6 +1277,19 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                     }
                 }
                 tile4[(vv * kTVS + (r + kTG) * kTSU) / 4 + c4 / 4] = e;
+            }
+            for (int q = tid; q < kTVG * kTSU; q += 256) {
+                const int vv = q / kTSU, cc = q % kTSU;
+                const int p = p0 + vv, u = s_box[vv][0] + cc;
+                double t = 0.0;
+                float2 ai = make_float2(0.0f, 0.0f);
+                if (p < P && (unsigned)u < (unsigned)nu) {
+                    const ColT &T = g.colT[(size_t)p * nu + u];
+                    t = T.t;
+                    ai = make_float2(T.ar, T.is);
+                }
+                s_Tt[vv][cc] = t;
+                s_Tai[vv][cc] = ai;
             }
         }
         __syncthreads();
@@ -1249,27 +1317,44 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                     // with |a1| in (1/2, 2) (one row per voxel within a factor
                     // of two) those are among floor(vc) - 1 .. floor(vc) + 2,
                     // with tent weights 1 - |a1| |v - vc| clipped at zero.
-                    // Half a pair (8 voxels of z) per step: 768 half pairs,
-                    // three per work-item.  The first half also records the
-                    // column's f_b on the plane relative to the block's first
-                    // voxel column (NaN for a column of the other axis).
-                    for (int h = tid; h < 2 * 16 * kZU; h += 256) {
-                        const int q = h >> 1, zh = (h & 1) * (kZC / 2);
-                        const int pj = q / kZU, k = q % kZU;
-                        if (k >= s_rng[vv][a][pj][1]) continue;
+                    // Half a pair (8 voxels of z) per step, over the listed
+                    // pairs, first halves then second halves.  The first half
+                    // also records the column's f_b on the plane relative to
+                    // the block's first voxel column (NaN for a column of the
+                    // other axis, possible where the axis changes twice).
+                    const int npairs = s_npairs[vv][a];
+                    for (int h = tid; h < 2 * npairs; h += 256) {
+                        const int half = h >= npairs;
+                        const int e = s_list[vv][a][half ? h - npairs : h];
+                        const int pj = e >> 8, k = e & 255, zh = half * (kZC / 2);
+                        const int q = pj * kZU + k;
                         const int au = s_rng[vv][a][pj][0] + k;
-                        const ColT T = Tp[au];
-                        const bool other = (T.is > 0.0f) != (a == 0);   // the projector's dominant axis
+                        // the column's table entry, staged with the data when it fits
+                        const int lc = au - bu0;
+                        double Tt;
+                        float Tar, Tis;
+                        if (fit && (unsigned)lc < (unsigned)kTSU) {
+                            Tt = s_Tt[vv][lc];
+                            const float2 ai = s_Tai[vv][lc];
+                            Tar = ai.x;
+                            Tis = ai.y;
+                        } else {
+                            const ColT &T = Tp[au];
+                            Tt = T.t;
+                            Tar = T.ar;
+                            Tis = T.is;
+                        }
+                        const bool other = (Tis > 0.0f) != (a == 0);   // the projector's dominant axis
                         const double Dp = a ? (iy0 + pj - Cy) * vox - oy : (ix0 + pj - Cx) * vox - ox;
-                        if (zh == 0) s_fb[q] = other ? __builtin_nan("") : (eb0 + Dp * T.t) * ivox;
+                        if (zh == 0) s_fb[q] = other ? __builtin_nan("") : (eb0 + Dp * Tt) * ivox;
                         if (other) continue;
-                        float *sl = s_z + q * kZS;
-                        const float a1 = (float)Dp * T.ar, aa = fabsf(a1);
+                        float *sl = s_z + pj * kPS + k * kZS;
+                        const float a1 = (float)Dp * Tar, aa = fabsf(a1);
                         if (!(aa > 0.5f && aa < 2.0f)) {   // steep or flat rows: row by row
                             if (zh == 0) {
 #pragma unroll
                                 for (int z = 0; z < kZC; ++z) sl[z] = 0.0f;
-                                splat(sl, T, Dp, p, au, 1.0f, fit, bu0, bv0, tv);
+                                splat(sl, Tar, Dp, p, au, 1.0f, fit, bu0, bv0, tv);
                             }
                             continue;
                         }
@@ -1324,7 +1409,7 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                         for (int k = k0; k <= k1; ++k) {
                             const float wb = 1.0f - fabsf((float)(s_fb[jj * kZU + k] - jb));
                             if (!(wb > 0.0f)) continue;   // NaN: a column of the other axis
-                            const float *sl = s_z + (jj * kZU + k) * kZS;
+                            const float *sl = s_z + jj * kPS + k * kZS;
 #pragma unroll
                             for (int z = 0; z < kZC; ++z) accz[z] = fmaf(wb, sl[z], accz[z]);
                         }
@@ -1344,7 +1429,7 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                             if ((T.is > 0.0f) != (a == 0)) continue;
                             const float wb = 1.0f - fabsf((float)((e0 + D * T.t) * ivox));
                             if (!(wb > 0.0f)) continue;
-                            splat(sl, T, D, p, au, wb, fit, bu0, bv0, tv);
+                            splat(sl, T.ar, D, p, au, wb, fit, bu0, bv0, tv);
                         }
 #pragma unroll
                         for (int z = 0; z < kZC; ++z) accz[z] += sl[z];
