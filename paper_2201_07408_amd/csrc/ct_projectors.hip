@@ -1066,35 +1066,45 @@ constexpr int kZS = kZC + 1;         // floats per sheet
 constexpr int kTG = 2;               // zero guard rows on either side of a staged view
 constexpr int kPS = kZU * kZS + 1;   // floats per plane of sheets (odd: planes on distinct banks)
 
+// LDS-qualified view of staged data: rows are addressed by 32-bit byte offsets
+typedef __attribute__((address_space(3))) const float lds_cfloat;
+
 // Eight voxels of one z sheet from the staged rows of a detector column
-// (t[r kTSU] = row bv0 + r, kTG guard rows on either side): voxel zz takes
-// the rows around vc = vcb + zz / a1 with weights 1 - |a1| |v - vc| clipped
-// at zero.  For |a1| < 1 those are rows floor(vc) - 1 .. floor(vc) + 2, the
-// inner two always weighted; for |a1| >= 1 only floor(vc) and floor(vc) + 1.
+// (t: LDS byte address of tile row 0 of the column, the first kTG rows
+// guards; rows kTSU floats apart): voxel zz takes the
+// rows around tile position vr = vrb + zz / a1 (row position relative to
+// the first guard row) with weights 1 - |a1| |v - vr| clipped at zero.  For
+// |a1| < 1 those are rows floor(vr) - 1 .. floor(vr) + 2, the inner two
+// always weighted; for |a1| >= 1 only floor(vr) and floor(vr) + 1.  Inside
+// the volume vr >= 1 (the box holds the rows with a row of margin), so
+// truncation is the floor; CLAMP keeps the rows of voxels beyond the volume
+// (last chunk) in the tile.  Weights lie in [0, 1], so clipping at zero is
+// the FMA's clamp.
 template <bool CLAMP>
-__device__ __forceinline__ void sheet_rows(float *out, const float *t, float vcb, float ia1, float aa, float am,
-                                           int bv0) {
+__device__ __forceinline__ void sheet_rows(float *out, uint32_t t, float vrb, float ia1, float aa, float am) {
+    constexpr int kRows = kTSV + 2 * kTG;
+    constexpr uint32_t kRB = kTSU * sizeof(float);   // bytes per tile row
     if (aa < 1.0f) {
-        const float *tb = t - (bv0 + 1) * kTSU;
+        const float am2 = am - aa;
 #pragma unroll
         for (int zz = 0; zz < kZC / 2; ++zz) {
-            const float vc = fmaf((float)zz, ia1, vcb);
-            const float fl = floorf(vc), f = vc - fl;
-            const float *tr = CLAMP ? t + min(max((int)fl - 1 - bv0, -kTG), kTSV + kTG - 4) * kTSU
-                                    : tb + (int)fl * kTSU;
-            const float w1 = fmaf(-aa, f, 1.0f), w2 = fmaf(aa, f, am);
-            const float w0 = fmaxf(w1 - aa, 0.0f), w3 = fmaxf(w2 - aa, 0.0f);
+            const float vr = fmaf((float)zz, ia1, vrb);
+            const float f = __builtin_amdgcn_fractf(vr);
+            const uint32_t iv = CLAMP ? (uint32_t)min(max((int)vr, 1), kRows - 3) : (uint32_t)(int)vr;
+            lds_cfloat *tr = (lds_cfloat *)(size_t)(__umul24(iv, kRB) + (t - kRB));
+            const float w0 = __builtin_amdgcn_fmed3f(fmaf(-aa, f, am), 0.0f, 1.0f), w1 = fmaf(-aa, f, 1.0f);
+            const float w2 = fmaf(aa, f, am), w3 = __builtin_amdgcn_fmed3f(fmaf(aa, f, am2), 0.0f, 1.0f);
             out[zz] = fmaf(w0, tr[0], fmaf(w1, tr[kTSU], fmaf(w2, tr[2 * kTSU], w3 * tr[3 * kTSU])));
         }
     } else {
-        const float *tb = t - bv0 * kTSU;
 #pragma unroll
         for (int zz = 0; zz < kZC / 2; ++zz) {
-            const float vc = fmaf((float)zz, ia1, vcb);
-            const float fl = floorf(vc), f = vc - fl;
-            const float *tr = CLAMP ? t + min(max((int)fl - bv0, -kTG), kTSV + kTG - 2) * kTSU
-                                    : tb + (int)fl * kTSU;
-            const float w1 = fmaxf(fmaf(-aa, f, 1.0f), 0.0f), w2 = fmaxf(fmaf(aa, f, am), 0.0f);
+            const float vr = fmaf((float)zz, ia1, vrb);
+            const float f = __builtin_amdgcn_fractf(vr);
+            const uint32_t iv = CLAMP ? (uint32_t)min(max((int)vr, 0), kRows - 2) : (uint32_t)(int)vr;
+            lds_cfloat *tr = (lds_cfloat *)(size_t)(__umul24(iv, kRB) + t);
+            const float w1 = __builtin_amdgcn_fmed3f(fmaf(-aa, f, 1.0f), 0.0f, 1.0f);
+            const float w2 = __builtin_amdgcn_fmed3f(fmaf(aa, f, am), 0.0f, 1.0f);
             out[zz] = fmaf(w1, tr[0], w2 * tr[kTSU]);
         }
     }
@@ -1115,8 +1125,8 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
     // meets the plane at f_b (relative to the block's first voxel column),
     // col(f_b) = (n0 + n1 f_b) / (d0 + d1 f_b) + Cu - first, as (n0, n1, d0, d1)
     __shared__ float4 s_cf[kTVG][2][16];
-    // the (plane, column) pairs of each view and axis, plane << 8 | column
-    // within the plane's range, and their count
+    // the (plane, column) pairs of each view and axis (see the range phase
+    // for the packing), and their count
     __shared__ unsigned short s_list[kTVG][2][16 * kZU];
     __shared__ int s_npairs[kTVG][2];
     // column table entries (t, then a_r and the signed step factor) of the
@@ -1252,7 +1262,16 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                 const int o = __shfl_up(inc, d, 16);
                 if (jj >= d) inc += o;
             }
-            for (int kk = 0; kk < cl; ++kk) s_list[vv][a][inc - cl + kk] = (unsigned short)(jj << 8 | kk);
+            // entry: column within the plane's range | plane << 5 | column
+            // within the staged box << 9; a column outside the box sends the
+            // (view, axis) to the per-voxel path
+            bool outside = false;
+            for (int kk = 0; kk < cl; ++kk) {
+                const int lc = first + kk - s_box[vv][0];
+                outside |= (unsigned)lc >= (unsigned)kTSU;
+                s_list[vv][a][inc - cl + kk] = (unsigned short)(kk | jj << 5 | (lc & 127) << 9);
+            }
+            if (outside) atomicOr(&s_wide[vv][a], 1);
             if (jj == 15) s_npairs[vv][a] = inc;
         }
         const bool fit = s_fit != 0;
@@ -1310,7 +1329,8 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                 const double D = a ? (iy - Cy) * vox - oy : (ix - Cx) * vox - ox;
                 const double e0 = (a ? ox : oy) - (ib - (a ? Cx : Cy)) * vox;
                 const double eb0 = (a ? ox : oy) - ((a ? ix0 : iy0) - (a ? Cx : Cy)) * vox;
-                if (!s_wide[vv][a]) {
+                const double Dp0 = a ? (iy0 - Cy) * vox - oy : (ix0 - Cx) * vox - ox;   // the block's first plane
+                if (fit && !s_wide[vv][a]) {
                     // splat: (plane, column) pairs of the block, z by z in
                     // registers.  Voxel z takes the rows with |f_c - z| < 1,
                     // f_c - z = a1 (v - vc(z)), vc(z) = Cv + (z - zoff) / a1:
@@ -1326,26 +1346,15 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                     for (int h = tid; h < 2 * npairs; h += 256) {
                         const int half = h >= npairs;
                         const int e = s_list[vv][a][half ? h - npairs : h];
-                        const int pj = e >> 8, k = e & 255, zh = half * (kZC / 2);
+                        const int k = e & 31, pj = (e >> 5) & 15, lc = e >> 9, zh = half * (kZC / 2);
                         const int q = pj * kZU + k;
-                        const int au = s_rng[vv][a][pj][0] + k;
-                        // the column's table entry, staged with the data when it fits
-                        const int lc = au - bu0;
-                        double Tt;
-                        float Tar, Tis;
-                        if (fit && (unsigned)lc < (unsigned)kTSU) {
-                            Tt = s_Tt[vv][lc];
-                            const float2 ai = s_Tai[vv][lc];
-                            Tar = ai.x;
-                            Tis = ai.y;
-                        } else {
-                            const ColT &T = Tp[au];
-                            Tt = T.t;
-                            Tar = T.ar;
-                            Tis = T.is;
-                        }
+                        // the column's table entry, staged with the data
+                        const double Tt = s_Tt[vv][lc];
+                        const float2 ai = s_Tai[vv][lc];
+                        const float Tar = ai.x, Tis = ai.y;
+                        const int au = bu0 + lc;
                         const bool other = (Tis > 0.0f) != (a == 0);   // the projector's dominant axis
-                        const double Dp = a ? (iy0 + pj - Cy) * vox - oy : (ix0 + pj - Cx) * vox - ox;
+                        const double Dp = fma((double)pj, vox, Dp0);
                         if (zh == 0) s_fb[q] = other ? __builtin_nan("") : (eb0 + Dp * Tt) * ivox;
                         if (other) continue;
                         float *sl = s_z + pj * kPS + k * kZS;
@@ -1354,39 +1363,22 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                             if (zh == 0) {
 #pragma unroll
                                 for (int z = 0; z < kZC; ++z) sl[z] = 0.0f;
-                                splat(sl, Tar, Dp, p, au, 1.0f, fit, bu0, bv0, tv);
+                                splat(sl, Tar, Dp, p, au, 1.0f, true, bu0, bv0, tv);
                             }
                             continue;
                         }
-                        const float ia1 = 1.0f / a1, vc0 = fmaf(-zoff, ia1, Cvf);
+                        // 1 / a1: the hardware reciprocal and one Newton step
+                        const float r0 = __builtin_amdgcn_rcpf(a1);
+                        const float ia1 = fmaf(fmaf(-a1, r0, 1.0f), r0, r0);
                         const float am = 1.0f - aa;
-                        if (fit) {
-                            const float vcb = fmaf((float)zh, ia1, vc0);
-                            const float *t = tv + min(max(au - bu0, 0), kTSU - 1);   // row v at t[(v - bv0) kTSU]
-                            float out[kZC / 2];
-                            // The rows of the voxels of the chunk lie in the box and
-                            // the guards; those beyond the volume (last chunk) are
-                            // clamped into them.
-                            if (zmax == kZC) sheet_rows<false>(out, t, vcb, ia1, aa, am, bv0);
-                            else sheet_rows<true>(out, t, vcb, ia1, aa, am, bv0);
+                        // row positions relative to the first guard row
+                        const float vrb = fmaf((float)zh, ia1, fmaf(-zoff, ia1, Cvf - (float)(bv0 - kTG)));
+                        const uint32_t t = (uint32_t)(size_t)(lds_cfloat *)(tv - kTG * kTSU + lc);
+                        float out[kZC / 2];
+                        if (zmax == kZC) sheet_rows<false>(out, t, vrb, ia1, aa, am);
+                        else sheet_rows<true>(out, t, vrb, ia1, aa, am);
 #pragma unroll
-                            for (int zz = 0; zz < kZC / 2; ++zz) sl[zh + zz] = out[zz];
-                        } else {
-                            const float *yp = ys + (size_t)p * nv * nu + au;
-                            const int zend = min(zh + kZC / 2, zmax);
-                            for (int z = zh; z < zend; ++z) {
-                                const float vc = fmaf((float)z, ia1, vc0);
-                                const float fl = floorf(vc), f = vc - fl;
-                                const int iv = (int)fl - 1;
-                                const float w1 = fmaf(-aa, f, 1.0f), w2 = fmaf(aa, f, am);
-                                const float w0 = fmaxf(w1 - aa, 0.0f), w3 = fmaxf(w2 - aa, 0.0f);
-                                const float y0 = (unsigned)iv < (unsigned)nv ? yp[(size_t)iv * nu] : 0.0f;
-                                const float y1 = (unsigned)(iv + 1) < (unsigned)nv ? yp[(size_t)(iv + 1) * nu] : 0.0f;
-                                const float y2 = (unsigned)(iv + 2) < (unsigned)nv ? yp[(size_t)(iv + 2) * nu] : 0.0f;
-                                const float y3 = (unsigned)(iv + 3) < (unsigned)nv ? yp[(size_t)(iv + 3) * nu] : 0.0f;
-                                sl[z] = fmaf(w0, y0, fmaf(fmaxf(w1, 0.0f), y1, fmaf(fmaxf(w2, 0.0f), y2, w3 * y3)));
-                            }
-                        }
+                        for (int zz = 0; zz < kZC / 2; ++zz) sl[zh + zz] = out[zz];
                     }
                     __syncthreads();
                     if (active) {
@@ -1401,7 +1393,8 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                         int k0 = 0, k1 = cnt - 1;
                         if ((dm > 0.0f && dp > 0.0f) || (dm < 0.0f && dp < 0.0f)) {
                             const float c0 = (float)(Cu - first);
-                            const float um = fmaf(cf.y, fm, cf.x) / dm + c0, up = fmaf(cf.y, fp, cf.x) / dp + c0;
+                            const float um = fmaf(cf.y, fm, cf.x) * __builtin_amdgcn_rcpf(dm) + c0;
+                            const float up = fmaf(cf.y, fp, cf.x) * __builtin_amdgcn_rcpf(dp) + c0;
                             k0 = max(k0, (int)ceilf(fminf(um, up) - 1e-3f));
                             k1 = min(k1, (int)floorf(fmaxf(um, up) + 1e-3f));
                         }
@@ -1416,8 +1409,10 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                     }
                     __syncthreads();   // sheets read before the next splat
                 } else {
-                    // wide planes: each voxel column splats its own candidates
-                    // into private slots (the sheets' LDS)
+                    // planes wider than the sheets, a column outside the staged
+                    // box, or a group that does not fit: each voxel column
+                    // splats its own candidates into private slots (the
+                    // sheets' LDS), from the staged data where it has them
                     float *sl = s_z + tid * kATS;
                     if (active) {
 #pragma unroll
@@ -1429,7 +1424,7 @@ __global__ __launch_bounds__(256, 3) void k_project_T_sheets(GeomK g, const floa
                             if ((T.is > 0.0f) != (a == 0)) continue;
                             const float wb = 1.0f - fabsf((float)((e0 + D * T.t) * ivox));
                             if (!(wb > 0.0f)) continue;
-                            splat(sl, T.ar, D, p, au, wb, fit, bu0, bv0, tv);
+                            splat(sl, T.ar, D, p, au, wb, fit && (unsigned)(au - bu0) < (unsigned)kTSU, bu0, bv0, tv);
                         }
 #pragma unroll
                         for (int z = 0; z < kZC; ++z) accz[z] += sl[z];
