@@ -174,6 +174,42 @@ def test_project_A_volume_beyond_last_level_cache(projector):
     assert_close(y, ref, TOL, "A beyond the last-level cache", op_elem_tol(desc))
 
 
+# Geometries that send the cone-beam transpose down each of its paths:
+#   fine_pitch     four detector columns and rows per voxel: planes wider than
+#                  the sheets and boxes larger than the staged tile (the
+#                  per-voxel fallback reading the data from global memory);
+#   coarse_pitch   a third of a column and row per voxel: |a1| = 3, rows
+#                  splatted one by one inside the sheet path;
+#   short_sod      magnification 3 at the near face and 1.5 at the far one:
+#                  some blocks with planes wider than the sheets, the others
+#                  on the sheet path with |a1| on both sides of 1;
+#   wide_fan       a 127 degree fan (12 rows, so that no ray is z-dominant):
+#                  the dominant axis changes twice across the detector, so
+#                  plane ranges are not cut to one axis.
+AT_PATH_GEOMS = {
+    "fine_pitch": dict(n=20, views=12, det=100, pitch=0.5),
+    "coarse_pitch": dict(n=24, views=12, det=12, pitch=6.0),
+    "short_sod": dict(n=32, views=16, det=64, sod_factor=1.5, sdd_factor=3.0),
+    "wide_fan": dict(n=16, views=8, det=64, sod_factor=1.5, sdd_factor=2.0, pitch=2.0, nv=12, nz=8),
+}
+
+
+@pytest.mark.parametrize("projector", [0, 1])
+@pytest.mark.parametrize("name", list(AT_PATH_GEOMS))
+def test_transpose_paths(name, projector):
+    kw = dict(AT_PATH_GEOMS[name])
+    desc = cone3d(kw.pop("n"), kw.pop("views"), kw.pop("det"), projector=projector, **kw)
+    g = ct.Geometry(desc)
+    say("A and A^T paths", name, projector)
+    rng = np.random.default_rng(11)
+    y = f32(rng.uniform(0, 1, size=desc.sino_shape))
+    x = host(ct.ct_backproject_AT(g, dev(y)))
+    assert_close(x, oracle.backproject_AT(desc, y), TOL, "A^T %s (model %d)" % (name, projector), op_elem_tol(desc))
+    v = f32(rng.uniform(0, 1, size=desc.vol_shape))
+    assert_close(host(ct.ct_project_A(g, dev(v))), oracle.project_A(desc, v), TOL,
+                 "A %s (model %d)" % (name, projector), op_elem_tol(desc))
+
+
 def test_batch_equals_single_calls(geoms):
     desc, g = geoms["cone_24"]
     rng = np.random.default_rng(6)
