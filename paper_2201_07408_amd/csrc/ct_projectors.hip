@@ -773,30 +773,29 @@ __global__ void k_view_dom(GeomK g, const ColT *__restrict__ T, int *__restrict_
     vshift[p] = (kTU - sw % kTU) % kTU;
 }
 
-// Exact transpose of the cone-beam Joseph projector (k_project_T_staged),
-// gathered per voxel instead of scattered per sample.  Voxel (ix, iy, iz) receives, from every
-// ray that samples its plane (x = ix for x-dominant rays, y = iy for
-// y-dominant ones) within one voxel of it in both in-plane coordinates, the
-// ray's value times the bilinear weight tent(f_b - i_b) tent(f_c - iz) and
-// the ray's step length: the A_ij of the forward model, summed over i.
-// Along a plane a ray's b coordinate depends on its detector column only,
-// f_b = (o_b + D t(u)) / vox + C_b with D the plane's distance from the
-// source along the dominant axis and t = r_b / r_a a linear-fractional
-// function of u; inverting it at f_b = i_b -+ 1 gives the few candidate
-// columns (all columns where the inverse interval wraps through infinity),
-// each of which is tested exactly with the projector's dominant axis from
-// the column table.  Its c coordinate is linear in the detector row: each
-// row of a candidate column feeds the two voxels of the work-item's z
-// chunk around its f_c, accumulated in per-work-item LDS slots.  Views are
-// summed in FP32 in groups of four and added to FP64, as in B_un; no
-// atomics, so the result is deterministic.
-// SID: the transpose of the line-intersection model instead.  The weight of
-// a voxel is then the fraction of the ray's slab (plane coordinate ix -+ 1/2,
-// or iy -+ 1/2) spent inside it: with the slab parameter s in [0, 1], the
-// ray is inside the voxel's b range on one interval of s and inside its c
-// range on another (the coordinates are linear in s), and the weight is the
-// length of their intersection.  Such rays have |f_b - i_b| < 1 and
-// |f_c - iz| < 1 at the plane, so the candidates are the same.
+// Exact transpose of the cone-beam line-intersection projector
+// (k_project_T_slab), gathered per voxel instead of scattered per sample.
+// Voxel (ix, iy, iz) receives, from every ray that crosses the slab of its
+// plane (x = ix -+ 1/2 for x-dominant rays, y = iy -+ 1/2 for y-dominant
+// ones) through it, the ray's value times the fraction of the slab spent
+// inside the voxel and the ray's step length: the A_ij of the forward
+// model, summed over i.  With the slab parameter s in [0, 1], the ray is
+// inside the voxel's b range on one interval of s and inside its c range on
+// another (the coordinates are linear in s), and the weight is the length
+// of their intersection.  Such rays have |f_b - i_b| < 1 and |f_c - iz| < 1
+// at the plane.  Along a plane a ray's b coordinate depends on its detector
+// column only, f_b = (o_b + D t(u)) / vox + C_b with D the plane's distance
+// from the source along the dominant axis and t = r_b / r_a a
+// linear-fractional function of u; inverting it at f_b = i_b -+ 1 gives the
+// few candidate columns (all columns where the inverse interval wraps
+// through infinity), each of which is tested exactly with the projector's
+// dominant axis from the column table.  Its c coordinate is linear in the
+// detector row: each row of a candidate column feeds the voxels of the
+// work-item's z chunk its slab crosses, accumulated in per-work-item LDS
+// slots.  Views are summed in FP32 over a group and added to FP64, as in
+// B_un; no atomics, so the result is deterministic.  (The Joseph transpose,
+// k_project_T_sheets below, shares the staging, the column table and the
+// candidate columns.)
 constexpr int kATS = kZC + 1;   // LDS slots per work-item (odd stride across banks)
 
 // The s in [0, 1] on which lo <= d + (s - 1/2) g < lo + 1: the slab
@@ -846,8 +845,7 @@ __global__ __launch_bounds__(256) void k_ray_step_scale(GeomK g, const InT *__re
 constexpr int kTVG = 3;               // views per staged group
 constexpr int kTSU = 36, kTSV = 32;   // staged detector columns / rows per view
 
-template <bool SID>
-__global__ __launch_bounds__(256) void k_project_T_staged(GeomK g, const float *__restrict__ ys, float *__restrict__ x,
+__global__ __launch_bounds__(256) void k_project_T_slab(GeomK g, const float *__restrict__ ys, float *__restrict__ x,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ stop) {
     if (stop && *stop) return;
@@ -960,14 +958,10 @@ __global__ __launch_bounds__(256) void k_project_T_staged(GeomK g, const float *
                         const ColT T = Tp[au];
                         if ((T.is > 0.0f) != (axis == 0)) continue;
                         const float db = (float)((e0 + D * T.t) * ivox);
-                        float wb, lb = 0.0f, hb = 0.0f;
-                        if (SID) {
-                            slab_interval(db, (float)T.t, lb, hb);
-                            wb = hb > lb ? 1.0f : 0.0f;
-                        } else {
-                            wb = 1.0f - fabsf(db);
-                        }
-                        if (!(wb > 0.0f)) continue;
+                        float lb, hb;
+                        slab_interval(db, (float)T.t, lb, hb);
+                        if (!(hb > lb)) continue;
+                        const float wb = 1.0f;
                         const float a1 = Df * T.ar, ia1 = 1.0f / a1;
                         const float r1 = fmaf(-1.0f - zoff, ia1, Cvf), r2 = fmaf((float)kZC - zoff, ia1, Cvf);
                         const int v0 = max((int)ceilf(fminf(r1, r2)), 0), v1 = min((int)floorf(fmaxf(r1, r2)), nv - 1);
@@ -977,29 +971,21 @@ __global__ __launch_bounds__(256) void k_project_T_staged(GeomK g, const float *
                         const int lu = min(max(au - bu0, 0), kTSU - 1);
                         for (int av = v0; av <= v1; ++av) {
                             const float dv = (float)av - Cvf;
-                            const float zf = fmaf(a1, dv, zoff);
-                            const float zl = floorf(zf), w1 = zf - zl;
-                            const int zi = (int)zl;
                             const float yv = fit ? tv[min(max(av - bv0, 0), kTSV - 1) * kTSU + lu] : yp[(size_t)av * nu + au];
                             const float val = wb * yv;
-                            if (SID) {
-                                // the slab's c range, [zc + q -+ gc/2] with zc = zoff + 1/2
-                                // (an exact integer or half-integer) and q = a1 dv: the
-                                // crossing is taken relative to zc, so that a small slope
-                                // does not divide the rounding of the absolute coordinate
-                                const float gc = T.ar * (float)vox * dv, q = a1 * dv, zc = zoff + 0.5f;
-                                const float r0 = fmaf(-0.5f, gc, q), r1 = fmaf(0.5f, gc, q);
-                                const float k0f = floorf(zc + r0), k1f = floorf(zc + r1);
-                                const float sc = k0f == k1f ? 1.0f : ((fmaxf(k0f, k1f) - zc) - r0) / gc;
-                                const float f0 = fmaxf(fminf(sc, hb) - lb, 0.0f);
-                                const float f1 = k0f == k1f ? 0.0f : fmaxf(hb - fmaxf(sc, lb), 0.0f);
-                                const int k0 = (int)k0f, k1 = (int)k1f;
-                                if ((unsigned)k0 < (unsigned)kZC) slot[k0] = fmaf(f0, val, slot[k0]);
-                                if ((unsigned)k1 < (unsigned)kZC && k1 != k0) slot[k1] = fmaf(f1, val, slot[k1]);
-                            } else {
-                                if ((unsigned)zi < (unsigned)kZC) slot[zi] = fmaf(1.0f - w1, val, slot[zi]);
-                                if ((unsigned)(zi + 1) < (unsigned)kZC) slot[zi + 1] = fmaf(w1, val, slot[zi + 1]);
-                            }
+                            // the slab's c range, [zc + q -+ gc/2] with zc = zoff + 1/2
+                            // (an exact integer or half-integer) and q = a1 dv: the
+                            // crossing is taken relative to zc, so that a small slope
+                            // does not divide the rounding of the absolute coordinate
+                            const float gc = T.ar * (float)vox * dv, q = a1 * dv, zc = zoff + 0.5f;
+                            const float r0 = fmaf(-0.5f, gc, q), r1 = fmaf(0.5f, gc, q);
+                            const float k0f = floorf(zc + r0), k1f = floorf(zc + r1);
+                            const float sc = k0f == k1f ? 1.0f : ((fmaxf(k0f, k1f) - zc) - r0) / gc;
+                            const float f0 = fmaxf(fminf(sc, hb) - lb, 0.0f);
+                            const float f1 = k0f == k1f ? 0.0f : fmaxf(hb - fmaxf(sc, lb), 0.0f);
+                            const int k0 = (int)k0f, k1 = (int)k1f;
+                            if ((unsigned)k0 < (unsigned)kZC) slot[k0] = fmaf(f0, val, slot[k0]);
+                            if ((unsigned)k1 < (unsigned)kZC && k1 != k0) slot[k1] = fmaf(f1, val, slot[k1]);
                         }
                     }
                 }
@@ -1056,7 +1042,7 @@ __device__ __forceinline__ void column_range(const GeomK &g, int axis, double c,
 // reaches (two or three), is done once.  Sheets live in LDS (17-float
 // stride and an odd plane stride, across banks); the footprint of the
 // step-weighted data and the column table entries of its columns are
-// staged as in k_project_T_staged.  Per (view, axis) the pairs to splat are
+// staged as in k_project_T_slab.  Per (view, axis) the pairs to splat are
 // listed (each plane's column range cut to the axis's columns), so that
 // views whose fan spans both axes split the work instead of doubling it.  A
 // (view, axis) whose plane needs more than kZU columns falls back to the
@@ -2559,7 +2545,7 @@ int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, fl
     CT_LAUNCH_CHECK();
     dim3 grid((g->k.nx + 15) / 16, (g->k.ny + 15) / 16, (g->k.nz + kZC - 1) / kZC), block(16, 16);
     if (g->k.proj == CT_SIDDON)
-        hipLaunchKernelGGL((k_project_T_staged<true>), grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
+        hipLaunchKernelGGL(k_project_T_slab, grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
     else
         hipLaunchKernelGGL(k_project_T_sheets, grid, block, 0, s, g->k, (const float *)ys, x, scale, stop);
     CT_LAUNCH_CHECK();
