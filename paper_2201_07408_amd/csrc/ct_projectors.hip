@@ -833,6 +833,32 @@ __global__ __launch_bounds__(256) void k_ray_step_scale(GeomK g, const InT *__re
     }
 }
 
+// Detector columns [a_lo, a_hi] of a view whose rays, on the sampling plane
+// at distance D from the source along the dominant axis (axis 0: planes
+// x = const, b = y; axis 1: planes y = const, b = x), have in-plane
+// coordinate f_b with lo < f_b - ib < hi, where e0 = o_b - (ib - C_b) vox
+// so that f_b - ib = (e0 + D t) / vox with t = r_b / r_a.  t is a
+// linear-fractional function of the column, inverted at the two ends; all
+// columns when the inverse interval wraps through infinity, none
+// (a_hi < a_lo) when it misses the detector.
+__device__ __forceinline__ void column_range(const GeomK &g, int axis, double c, double s, double D, double e0,
+                                             double lo, double hi, int &a_lo, int &a_hi) {
+    const double Cu = 0.5 * (g.nu - 1);
+    const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
+    const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
+    const double iD = 1.0 / D, tm = (lo * g.vox - e0) * iD, tp = (hi * g.vox - e0) * iD;
+    const double dm = ga * tm - al, dp = ga * tp - al;
+    a_lo = 0;
+    a_hi = g.nu - 1;
+    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
+        const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
+        const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
+        a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
+        a_hi = ahi < (double)g.nu ? min((int)ceil(ahi), g.nu - 1) : g.nu - 1;
+        if (alo >= (double)g.nu || ahi <= -1.0) a_hi = -1;
+    }
+}
+
 // The cone-beam transpose with each view's footprint of the step-weighted
 // data staged in LDS (as the back-projector stages its footprint): per
 // group of kTVG views, the box of detector cells whose rays can sample the
@@ -941,18 +967,8 @@ __global__ __launch_bounds__(256) void k_project_T_slab(GeomK g, const float *__
                     const double D = axis ? yc - oy : xc - ox;
                     const int ib = axis ? ix : iy;
                     const double e0 = (axis ? ox : oy) - (ib - (axis ? Cx : Cy)) * vox;
-                    const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
-                    const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
-                    const double iD = 1.0 / D, tm = (-vox - e0) * iD, tp = (vox - e0) * iD;
-                    const double dm = ga * tm - al, dp = ga * tp - al;
-                    int a_lo = 0, a_hi = nu - 1;
-                    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
-                        const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
-                        const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
-                        a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
-                        a_hi = ahi < (double)nu ? min((int)ceil(ahi), nu - 1) : nu - 1;
-                        if (alo >= (double)nu || ahi <= -1.0) a_hi = -1;
-                    }
+                    int a_lo, a_hi;
+                    column_range(g, axis, c, s, D, e0, -1.0, 1.0, a_lo, a_hi);
                     const float Df = (float)D;
                     for (int au = a_lo; au <= a_hi; ++au) {
                         const ColT T = Tp[au];
@@ -1004,31 +1020,6 @@ __global__ __launch_bounds__(256) void k_project_T_slab(GeomK g, const float *__
     }
 }
 
-// Detector columns [a_lo, a_hi] of a view whose rays, on the sampling plane
-// at distance D from the source along the dominant axis (axis 0: planes
-// x = const, b = y; axis 1: planes y = const, b = x), have in-plane
-// coordinate f_b with lo < f_b - ib < hi, where e0 = o_b - (ib - C_b) vox
-// so that f_b - ib = (e0 + D t) / vox with t = r_b / r_a.  t is a
-// linear-fractional function of the column, inverted at the two ends; all
-// columns when the inverse interval wraps through infinity, none
-// (a_hi < a_lo) when it misses the detector.
-__device__ __forceinline__ void column_range(const GeomK &g, int axis, double c, double s, double D, double e0,
-                                             double lo, double hi, int &a_lo, int &a_hi) {
-    const double Cu = 0.5 * (g.nu - 1);
-    const double al = axis ? -s : c, be = axis ? -g.sdd * c : -g.sdd * s;
-    const double ga = axis ? c : -s, de = axis ? -g.sdd * s : -g.sdd * c;
-    const double iD = 1.0 / D, tm = (lo * g.vox - e0) * iD, tp = (hi * g.vox - e0) * iD;
-    const double dm = ga * tm - al, dp = ga * tp - al;
-    a_lo = 0;
-    a_hi = g.nu - 1;
-    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
-        const double um = (be - de * tm) / dm, up = (be - de * tp) / dp;
-        const double alo = fmin(um, up) / g.du + Cu, ahi = fmax(um, up) / g.du + Cu;
-        a_lo = alo > -1.0 ? max((int)floor(alo), 0) : 0;
-        a_hi = ahi < (double)g.nu ? min((int)ceil(ahi), g.nu - 1) : g.nu - 1;
-        if (alo >= (double)g.nu || ahi <= -1.0) a_hi = -1;
-    }
-}
 
 // The cone-beam Joseph transpose, factored by detector column.  On a
 // sampling plane all rows of one detector column share the in-plane
