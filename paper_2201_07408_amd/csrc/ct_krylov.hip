@@ -102,13 +102,17 @@ __global__ __launch_bounds__(256) void k_maxpy(const WT *__restrict__ W, size_t 
 // z' = zs z - sum_j coef[j] W[j] and partial d[j] = W[j] . z' for one chunk
 // in a single sweep (the second pass of CGS2 for the chunk that completes
 // z'; the dots of earlier chunks need the finished z' and take k_mdot).
-// With an FP16 basis it also sums ||z'||^2 into column ncol.
+// With an FP16 basis it also sums ||z'||^2 into column ncol.  It holds a
+// chunk's basis groups in registers, so fewer of its blocks are resident
+// than of the other sweeps; it may run on fewer blocks than the nslot
+// partial slots the reductions read, and the slots past its grid get zeros.
 template <int NV, typename WT>
 __global__ __launch_bounds__(256) void k_maxpy_dot(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
                                                    const float *zin, float *zout, size_t n,
                                                    const double *__restrict__ coef,
                                                    const double *__restrict__ zscale, int ncol,
-                                                   double *__restrict__ partials, const int *__restrict__ stop) {
+                                                   double *__restrict__ partials, int nslot,
+                                                   const int *__restrict__ stop) {
     constexpr bool kNrm = std::is_same<WT, __half>::value;
     if (stop && *stop) return;
     __shared__ double cf[NV];
@@ -135,6 +139,10 @@ __global__ __launch_bounds__(256) void k_maxpy_dot(const WT *__restrict__ W, siz
                 if (j < cnt) acc[j] += (double)ld_elem(Wc + (size_t)j * ldw, i) * (double)o;
         }
     block_partials<NV>(acc, cnt, nacc, kNrm, vlo, ncol, partials, kMaxBlk, blockIdx.x);
+    for (int slot = gridDim.x + blockIdx.x; slot < nslot; slot += gridDim.x) {
+        for (int j = threadIdx.x; j < cnt; j += 256) partials[(size_t)(vlo + j) * kMaxBlk + slot] = 0.0;
+        if (kNrm && threadIdx.x == 0) partials[(size_t)ncol * kMaxBlk + slot] = 0.0;
+    }
 }
 
 __global__ void k_gmres_init(KState st, int nblk, double qscale_c, double blen) {
@@ -364,9 +372,10 @@ __global__ __launch_bounds__(256) void k_cgls_p(float *__restrict__ p, const flo
 // ===================================================================== host
 namespace {
 
+constexpr int kSweepBlk = 1024;
 int sweep_blocks(size_t n) {
     size_t t = (n + kTile - 1) / kTile;
-    return (int)(t < (size_t)kMaxBlk ? (t == 0 ? 1 : t) : (size_t)kMaxBlk);
+    return (int)(t < (size_t)kSweepBlk ? (t == 0 ? 1 : t) : (size_t)kSweepBlk);
 }
 
 int grid_1d(size_t n) {
@@ -503,14 +512,32 @@ static int launch_maxpy(const GmresBufs &b, int vlo, int cnt, const float *zin, 
     return CT_OK;
 }
 
+// Blocks of `kern` (256 threads) resident on the current device at once.
+template <typename Kern>
+static int resident_blocks(Kern kern) {
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
 static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *zin, float *zout, const double *coef,
                             const double *zscale, int ncol, hipStream_t s) {
     ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
+    // one round of resident blocks where the sweep's grid would take a
+    // second, partly filled one (16 FP32 basis vectors: 768 of 1024 blocks
+    // resident on 256 CUs, 276 -> 211 us at 256^3)
 #define CT_MAXPY_DOT(NVV, WT, WP) \
-    hipLaunchKernelGGL((k_maxpy_dot<NVV, WT>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, zout, b.len, \
-                       coef, zscale, ncol, b.st.partials, stop)
+    do { \
+        const int res = resident_blocks(k_maxpy_dot<NVV, WT>); \
+        const int nb = res > 0 && res < nblk ? res : nblk; \
+        hipLaunchKernelGGL((k_maxpy_dot<NVV, WT>), dim3(nb), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, zout, \
+                           b.len, coef, zscale, ncol, b.st.partials, nblk, stop); \
+    } while (0)
 #define CT_MAXPY_DOT_NV(WT, WP) \
     if (cnt <= 1) CT_MAXPY_DOT(1, WT, WP); \
     else if (cnt <= 4) CT_MAXPY_DOT(4, WT, WP); \

@@ -51,12 +51,16 @@ def _compare(res_gpu, ref, x_tol=TOL, what="", hist_tol=TOL):
 
 
 def _compare_in_envelope(res_gpu, ref, desc, b, K, B, solver, what):
-    """Noisy data: the iterate and each residual entry within three times
-    the move that FP32-sized perturbations of the oracle's own operators
-    cause (fp32_envelopes), and never looser than 1e-4."""
+    """Noisy data: the iterate's elements and each residual entry within
+    three times the move that FP32-sized perturbations of the oracle's own
+    operators cause (fp32_envelopes), and never looser than 1e-4; the
+    iterate as a whole (relative 2-norm) within 1e-4 of the oracle's, the
+    reconstruction accuracy asked of the FP32 path at a fixed iteration
+    count (measured 2.6e-6 .. 3.8e-5 here)."""
     ex, er = fp32_envelopes(desc, b, K, B, solver)
     say("%s FP32 envelope: iterate %.3e, residual entries %.3e" % (what, ex, er))
     _compare(res_gpu, ref, max(TOL, 3.0 * ex), what, max(TOL, 3.0 * er))
+    assert rel(host(res_gpu.x), ref.x) <= TOL, (what, rel(host(res_gpu.x), ref.x))
 
 
 # On the noisy 64^2 problem FP32-sized perturbations of the oracle's own
@@ -64,7 +68,8 @@ def _compare_in_envelope(res_gpu, ref, desc, b, K, B, solver, what):
 # at k = 30 (B_un, A^T; 9e-6 and 8e-5 with B_FBP), and its residual entries,
 # which lie 1e2..1e4 below the first one, by up to 7.8e-3 at k = 15 and 18 %
 # at k = 30 (mid-history entries, which recover by the last iteration).
-# Both are held to three times the envelope measured on the spot.
+# Both are held to three times the envelope measured on the spot, and the
+# iterate's relative 2-norm distance to 1e-4 besides.
 @pytest.mark.parametrize("B", ["un", "ramp", "AT"])
 def test_ba_gmres_w1(w1, B):
     desc, g, b = w1
