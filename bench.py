@@ -434,9 +434,12 @@ def bench_paper_scale(ct, torch, lib):
         n_l, t_l = C.c_long(), C.c_double()
         lib.ct_profile_read(name.encode(), C.byref(n_l), C.byref(t_l))
         kern[name] = t_l.value / max(n_l.value, 1)
+    # Joseph samples per application of A at this size, counted by the oracle
+    n_a = json.load(open(os.path.join(ROOT, "tests", "golden", "update_counts.json")))["paper"]["A_updates"]
     out["full"] = {"iters": r.iters_done, "s": dt, "iters_per_s": r.iters_done / dt,
                    "image_rmse": rmse(r.x), "workspace_GB": ws_bytes(ct.api.L.CT_SOLVER_BA, ITERS) / 1e9,
-                   "kernel_ms_per_launch": {"A": kern["A"], "B_un": kern["B"], "F": kern["F"]}}
+                   "kernel_ms_per_launch": {"A": kern["A"], "B_un": kern["B"], "F": kern["F"]},
+                   "A_samples_per_launch": n_a, "A_samples_per_s": n_a / (kern["A"] * 1e-3)}
     del r
     t0 = time.perf_counter()
     rr = ct.ct_ba_gmres_restarted(g, b, 10, 3, B="ramp")

@@ -29,6 +29,10 @@ def main():
     g3s = dataclasses.replace(workloads.w3_geometry(), projector=1)
     out["w3_siddon"] = {"A_updates": oracle.count_A_updates(g3s)}
     print("w3_siddon", out["w3_siddon"], flush=True)
+    gp = workloads.paper_geometry()
+    out["paper"] = {"A_updates": oracle.count_A_updates(gp), "B_updates": oracle.count_B_updates(gp),
+                    "n_vox": gp.n_vox, "n_rays": gp.n_rays}
+    print("paper", out["paper"], flush=True)
     w5 = [oracle.count_A_updates(d) for d, _, _ in workloads.w5_slices()]
     out["w5"] = {"A_updates": int(sum(w5)),
                  "B_updates": int(sum(d.n_vox * d.n_views for d, _, _ in workloads.w5_slices()))}
