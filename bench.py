@@ -455,6 +455,15 @@ def bench_paper_scale(ct, torch, lib):
     xf = ct.ct_fbp(g, b, out=xf)
     torch.cuda.synchronize()
     out["FDK"] = {"s": time.perf_counter() - t0, "image_rmse": rmse(xf)}
+    del xf
+    # the projector's launch settings at this size (the solves above ran
+    # with the size heuristic, which is restored afterwards)
+    out["projector_setting"] = dict(zip(("view_group", "wg_per_cu"), ct.ct_projector_get_config(g)))
+    timed, chosen = ct.ct_tune_projector(g, reps=2)
+    ct.ct_projector_config(g, 0, 0)
+    out["projector_tuning"] = {"candidates": [{"view_group": v, "wg_per_cu": w, "ms": round(t, 3)}
+                                              for v, w, t in timed],
+                               "fastest": dict(zip(("view_group", "wg_per_cu"), chosen))}
     return out
 
 
@@ -582,7 +591,18 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom[0], "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic},
+        # the forward projector's launch setting in the timed solves (the
+        # size heuristic; the stored traffic figure was measured with it)
+        "projector_setting": dict(zip(("view_group", "wg_per_cu"), ct.ct_projector_get_config(g))),
     }
+    # the autotuner's view of the same setting: every candidate timed on this
+    # geometry, after which the heuristic is restored for the other legs
+    log("bench: projector launch settings")
+    timed, chosen = ct.ct_tune_projector(g, reps=3)
+    ct.ct_projector_config(g, 0, 0)
+    line["projector_tuning"] = {"candidates": [{"view_group": v, "wg_per_cu": w, "ms": round(t, 4)}
+                                               for v, w, t in timed],
+                                "fastest": dict(zip(("view_group", "wg_per_cu"), chosen))}
     if sdt == torch.float32:
         log("bench: FP16 data storage")
         line["fp16_data_storage"] = bench_f16_data(ct, torch, g, b, x_phantom, x32)

@@ -315,6 +315,51 @@ int ct_ba_gmres_batched(const ct_geometry *const *g, int count,
 int ct_batched_config(int use_graph, int a_variant, int b_variant);
 int ct_batched_last_config(int *use_graph, int *a_variant, int *b_variant);
 
+/* Launch setting of the cone-beam forward projector (the staged Joseph and
+ * line-intersection kernels behind ct_project_A and the solvers).  Its
+ * workgroups are 16 x 16 ray tiles of one view; a setting picks the order
+ * they are dealt to the eight XCDs and how many stay resident per CU:
+ *   vgrp in 1..64: XCD-contiguous order, groups of vgrp views (the same
+ *       tile of a group's views on one XCD, sharing its L2);
+ *   vgrp in -16..-1: band order, groups of -vgrp views (all XCDs on one
+ *       band of detector rows, for volumes beyond the last-level cache);
+ *   wg_per_cu in 1..8: at most that many resident workgroups per CU
+ *       (dynamic LDS), 0: as many as fit.
+ * Every setting gives bit-identical results; only the time differs.
+ * ct_projector_config stores a setting in the geometry handle (0, 0: the
+ * size heuristic, which is the default: groups of 10 views in XCD order
+ * while both padded volume copies fit the 256 MB last-level cache, else
+ * the band order in groups of 4 at 4 workgroups per CU); it may be called
+ * while other threads use the handle (they see the old or the new
+ * setting).  ct_projector_get_config returns the setting in use (0, 0 for
+ * 2D geometries, which have no such setting).
+ * Errors: CT_ERR_ARG (NULL, out of range), CT_ERR_UNSUPPORTED (a non-zero
+ * setting for a 2D geometry). */
+int ct_projector_config(ct_geometry *g, int vgrp, int wg_per_cu);
+int ct_projector_get_config(const ct_geometry *g, int *vgrp, int *wg_per_cu);
+
+/* Autotuner of that setting: times each candidate on this geometry (one
+ * warm-up and `reps` timed launches of the forward projector, hipEvents on
+ * `stream`, on a scratch volume of pseudo-random values and a scratch
+ * sinogram that this call allocates with hipMalloc and frees before it
+ * returns; `stream` is synchronised) and stores the fastest with
+ * ct_projector_config.  Candidates: groups of 4, 6, 8, 10, 12 and 16 views
+ * in XCD order at full occupancy, and where the padded copies exceed the
+ * last-level cache also the band order with groups of 2, 4 and 6 views at
+ * 3, 4 and 5 workgroups per CU.  Launches made by other threads with this
+ * handle meanwhile run with one of the candidates.
+ *   reps: 1..100.
+ *   cap, vgrp, wg_per_cu, ms: HOST arrays of `cap` entries (may be NULL
+ *       when cap == 0) receiving the first min(cap, count) candidates'
+ *       settings and mean milliseconds per launch.
+ *   count: HOST, may be NULL: the number of candidates (0 for 2D
+ *       geometries, which are left as they are).
+ * Not for graph capture (kernel timing with events, allocation).  On an
+ * error the previous setting is kept.  Errors: CT_ERR_ARG, CT_ERR_ALLOC,
+ * CT_ERR_HIP. */
+int ct_tune_projector(ct_geometry *g, int reps, int cap, int *vgrp, int *wg_per_cu, double *ms, int *count,
+                      void *stream);
+
 /* Kernel timing (opt-in tracing).  When enabled, every projector,
  * back-projector, filter and orthogonalisation kernel launched by the
  * library is bracketed by two hipEvents recorded on the stream it runs on.

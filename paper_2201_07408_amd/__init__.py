@@ -25,6 +25,9 @@ from .api import (  # noqa: F401
     ct_ba_gmres_batched,
     ct_batched_config,
     ct_batched_last_config,
+    ct_projector_config,
+    ct_projector_get_config,
+    ct_tune_projector,
     ct_last_error,
     CtError,
     SolveResult,

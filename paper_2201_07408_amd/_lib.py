@@ -25,6 +25,7 @@ EXPORTS = [
     "ct_profile_enable", "ct_profile_reset", "ct_profile_read",
     "ct_ba_gmres_batched_workspace_bytes", "ct_ba_gmres_batched",
     "ct_batched_config", "ct_batched_last_config",
+    "ct_projector_config", "ct_projector_get_config", "ct_tune_projector",
 ]
 
 
@@ -92,6 +93,9 @@ def load(path: str = LIBPATH):
                                  ctypes.POINTER(SolverOpts), vp, sz, dp, ip, vp], i),
         "ct_batched_config": ([i, i, i], i),
         "ct_batched_last_config": ([ip, ip, ip], i),
+        "ct_projector_config": ([gp, i, i], i),
+        "ct_projector_get_config": ([gp, ip, ip], i),
+        "ct_tune_projector": ([gp, i, i, ip, ip, dp, ip, vp], i),
         "ct_profile_enable": ([i], i),
         "ct_profile_reset": ([], i),
         "ct_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp], i),

@@ -358,6 +358,35 @@ def ct_batched_config(use_graph: bool = True, a_variant: int = -1, b_variant: in
     _check(L.load().ct_batched_config(int(bool(use_graph)), int(a_variant), int(b_variant)), "ct_batched_config")
 
 
+def ct_projector_config(g: Geometry, vgrp: int = 0, wg_per_cu: int = 0) -> None:
+    """Launch setting of the cone-beam forward projector of `g` (0, 0: the
+    size heuristic); every setting gives bit-identical results."""
+    _check(L.load().ct_projector_config(g.handle, int(vgrp), int(wg_per_cu)), "ct_projector_config")
+
+
+def ct_projector_get_config(g: Geometry):
+    """(vgrp, wg_per_cu) in use by the forward projector of `g`."""
+    v, w = ctypes.c_int(), ctypes.c_int()
+    _check(L.load().ct_projector_get_config(g.handle, ctypes.byref(v), ctypes.byref(w)), "ct_projector_get_config")
+    return v.value, w.value
+
+
+def ct_tune_projector(g: Geometry, reps: int = 3, cap: int = 32):
+    """Time the forward projector's launch settings on `g` (on the current
+    stream of g's device) and keep the fastest; returns the list of
+    (vgrp, wg_per_cu, ms per launch) timed and the setting chosen."""
+    v = (ctypes.c_int * cap)()
+    w = (ctypes.c_int * cap)()
+    t = (ctypes.c_double * cap)()
+    n = ctypes.c_int()
+    with torch.cuda.device(g.device):
+        st = ctypes.c_void_p(torch.cuda.current_stream(g.device).cuda_stream)
+        _check(L.load().ct_tune_projector(g.handle, int(reps), int(cap), v, w, t, ctypes.byref(n), st),
+               "ct_tune_projector")
+    timed = [(v[i], w[i], t[i]) for i in range(min(n.value, cap))]
+    return timed, ct_projector_get_config(g)
+
+
 def ct_batched_last_config():
     g, a, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(L.load().ct_batched_last_config(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b)),

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -138,6 +139,12 @@ struct ct_geometry {
     size_t n_vox = 0, n_rays = 0;
     ct::GeomK k;                   // kernel view
     ct::PadLayout pad;
+    // Launch setting of the cone-beam projector: its view grouping and
+    // workgroup order in the low 32 bits, resident workgroups per CU in the
+    // high 32 (0: the size heuristic).  Written by ct_projector_config and
+    // ct_tune_projector, read once per launch; every setting gives the same
+    // results.
+    std::atomic<uint64_t> a_cfg{0};
 };
 
 namespace ct {

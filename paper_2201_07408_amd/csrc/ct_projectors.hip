@@ -2399,14 +2399,14 @@ static void ray_grid(const ct_geometry *g, dim3 &grid, dim3 &block) {
 
 // Dynamic LDS that holds a 256-work-item kernel to at most `target`
 // resident workgroups per CU (0 if it already is), found with the runtime's
-// occupancy calculator and cached per device and kernel.
+// occupancy calculator and cached per device, kernel and target.
 static unsigned lds_for_occupancy(const void *kernel, int target) {
     static std::mutex mu;
-    static std::map<std::pair<int, const void *>, unsigned> cache;
+    static std::map<std::pair<std::pair<int, int>, const void *>, unsigned> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     std::lock_guard<std::mutex> lk(mu);
-    const auto key = std::make_pair(dev, kernel);
+    const auto key = std::make_pair(std::make_pair(dev, target), kernel);
     const auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     unsigned extra = 0;
@@ -2442,18 +2442,42 @@ constexpr int kVGrpCached = 10;
 constexpr int kVGrpBig = -4;   // band order, groups of four views
 constexpr int kBigVolumeWgPerCu = 4;
 
-static int staged_view_group(const ct_geometry *g) {
-    return 4.0 * (double)(g->pad.nvx + g->pad.nvy) > kLlcBytes ? kVGrpBig : kVGrpCached;
+// Launch setting of the staged projector: vgrp > 0 deals the workgroups in
+// the XCD-contiguous order with groups of vgrp views, vgrp < 0 in the band
+// order with groups of -vgrp views (xcd_tile); wgcu > 0 holds the resident
+// workgroups per CU to wgcu with dynamic LDS, 0 leaves as many as fit.
+// Only the order and residency of the workgroups change, not what any of
+// them computes.
+struct StagedCfg {
+    int vgrp, wgcu;
+};
+constexpr int kMaxVGrp = 64, kMaxBandGrp = 16, kMaxWgPerCu = 8;
+
+static bool staged_cfg_valid(int vgrp, int wgcu) {
+    return ((vgrp >= 1 && vgrp <= kMaxVGrp) || (vgrp <= -1 && vgrp >= -kMaxBandGrp)) && wgcu >= 0 &&
+           wgcu <= kMaxWgPerCu;
+}
+
+static uint64_t pack_cfg(StagedCfg c) { return (uint64_t)(uint32_t)c.vgrp | (uint64_t)(uint32_t)c.wgcu << 32; }
+
+// The geometry's setting, or the size heuristic: while the padded copies
+// fit the last-level cache, groups of ten views in the XCD order at full
+// occupancy; beyond it, the band order with groups of four at four
+// workgroups per CU.
+static StagedCfg staged_cfg(const ct_geometry *g) {
+    const uint64_t v = g->a_cfg.load(std::memory_order_relaxed);
+    if (v != 0) return StagedCfg{(int)(uint32_t)v, (int)(uint32_t)(v >> 32)};
+    return 4.0 * (double)(g->pad.nvx + g->pad.nvy) > kLlcBytes ? StagedCfg{kVGrpBig, kBigVolumeWgPerCu}
+                                                               : StagedCfg{kVGrpCached, 0};
 }
 
 template <typename OutT, bool SID>
-static int launch_staged(const ct_geometry *g, dim3 grid, const float *vx, uint32_t offy, void *y,
+static int launch_staged(const ct_geometry *g, StagedCfg cfg, dim3 grid, const float *vx, uint32_t offy, void *y,
                          const float *out_scale, const int *stop, hipStream_t s) {
     const void *kern = (const void *)&k_project_staged<OutT, SID>;
-    const int vgrp = staged_view_group(g);
-    const unsigned lds = vgrp == kVGrpBig ? lds_for_occupancy(kern, kBigVolumeWgPerCu) : 0u;
+    const unsigned lds = cfg.wgcu > 0 ? lds_for_occupancy(kern, cfg.wgcu) : 0u;
     hipLaunchKernelGGL((k_project_staged<OutT, SID>), grid, dim3(kTU, kTV), lds, s, g->k, g->pad, vx, offy,
-                       (OutT *)y, out_scale, stop, vgrp);
+                       (OutT *)y, out_scale, stop, cfg.vgrp);
     return CT_OK;
 }
 
@@ -2473,7 +2497,8 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
     if (cone) {
         // 16 x 16 ray tiles, flat grid remapped per XCD inside the kernel
         const long ntiles = (long)staged_tile_cols(g->k.nu) * ((g->k.nv + kTV - 1) / kTV);
-        const int vgrp = staged_view_group(g);
+        const StagedCfg cfg = staged_cfg(g);   // read once: the grid and the kernel agree
+        const int vgrp = cfg.vgrp;
         long per;   // workgroups per XCD
         if (vgrp < 0) {
             // band order: whole runs of one group's tile row per XCD
@@ -2490,11 +2515,11 @@ int launch_project(const ct_geometry *g, const float *vx, const float *vy, void 
         }
         const dim3 sgrid((unsigned)(8 * per));
         if (g->k.proj == CT_SIDDON) {
-            if (y_dtype == CT_F32) launch_staged<float, true>(g, sgrid, vx, offy, y, out_scale, stop, s);
-            else launch_staged<__half, true>(g, sgrid, vx, offy, y, out_scale, stop, s);
+            if (y_dtype == CT_F32) launch_staged<float, true>(g, cfg, sgrid, vx, offy, y, out_scale, stop, s);
+            else launch_staged<__half, true>(g, cfg, sgrid, vx, offy, y, out_scale, stop, s);
         } else {
-            if (y_dtype == CT_F32) launch_staged<float, false>(g, sgrid, vx, offy, y, out_scale, stop, s);
-            else launch_staged<__half, false>(g, sgrid, vx, offy, y, out_scale, stop, s);
+            if (y_dtype == CT_F32) launch_staged<float, false>(g, cfg, sgrid, vx, offy, y, out_scale, stop, s);
+            else launch_staged<__half, false>(g, cfg, sgrid, vx, offy, y, out_scale, stop, s);
         }
     } else {
         if (y_dtype == CT_F32) hipLaunchKernelGGL((k_project<false, float>), grid, block, 0, s, g->k, g->pad, vx, offy, (float *)y, out_scale, stop);
@@ -3011,5 +3036,133 @@ extern "C" int ct_fbp(const ct_geometry *g, const void *y, int y_dtype, float *x
         CT_TRY(launch_ramp(g, wy, CT_F32, fy, CT_F32, (size_t)k.P * k.nv, nullptr, s));
         CT_TRY(launch_backproject(g, fy, CT_F32, x + (size_t)b * g->n_vox, nullptr, nullptr, s));
     }
+    return CT_OK;
+}
+
+// ------------------------------------------- projector launch setting
+namespace {
+// pseudo-random values in [0, 1) for the tuner's scratch volume (a hash of
+// the index; the projector's time depends a little on the data)
+__global__ void k_fill_hash(float *__restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 2654435761u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        p[i] = (float)(h >> 8) * (1.0f / 16777216.0f);
+    }
+}
+
+// the tuner's device scratch and events, released on every return path
+// (after the stream has drained)
+struct TuneScratch {
+    hipStream_t s = nullptr;
+    float *vol = nullptr, *y = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch() {
+        (void)hipStreamSynchronize(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (vol) (void)hipFree(vol);
+        if (y) (void)hipFree(y);
+    }
+};
+
+// puts the setting back unless the tuner finished
+struct RestoreCfg {
+    ct_geometry *g;
+    uint64_t v;
+    bool done = false;
+    ~RestoreCfg() {
+        if (!done) g->a_cfg.store(v);
+    }
+};
+}  // namespace
+
+extern "C" int ct_projector_config(ct_geometry *g, int vgrp, int wg_per_cu) {
+    clear_error();
+    CT_ARG_CHECK(g, "ct_projector_config: geometry is NULL");
+    if (vgrp == 0 && wg_per_cu == 0) {
+        g->a_cfg.store(0);
+        return CT_OK;
+    }
+    if (g->k.kind != CT_CONE_CIRCULAR_3D) {
+        set_error("ct_projector_config: only cone-beam geometries have a staged projector setting");
+        return CT_ERR_UNSUPPORTED;
+    }
+    CT_ARG_CHECK(staged_cfg_valid(vgrp, wg_per_cu),
+                 "ct_projector_config: vgrp must be 1..64 or -16..-1 and wg_per_cu 0..8");
+    g->a_cfg.store(pack_cfg(StagedCfg{vgrp, wg_per_cu}));
+    return CT_OK;
+}
+
+extern "C" int ct_projector_get_config(const ct_geometry *g, int *vgrp, int *wg_per_cu) {
+    clear_error();
+    CT_ARG_CHECK(g && vgrp && wg_per_cu, "ct_projector_get_config: NULL argument");
+    if (g->k.kind != CT_CONE_CIRCULAR_3D) {
+        *vgrp = 0;
+        *wg_per_cu = 0;
+        return CT_OK;
+    }
+    const StagedCfg c = staged_cfg(g);
+    *vgrp = c.vgrp;
+    *wg_per_cu = c.wgcu;
+    return CT_OK;
+}
+
+extern "C" int ct_tune_projector(ct_geometry *g, int reps, int cap, int *vgrp, int *wg_per_cu, double *ms, int *count,
+                                 void *stream) {
+    clear_error();
+    CT_ARG_CHECK(g, "ct_tune_projector: geometry is NULL");
+    CT_ARG_CHECK(reps >= 1 && reps <= 100, "ct_tune_projector: reps must be 1..100");
+    CT_ARG_CHECK(cap >= 0, "ct_tune_projector: negative cap");
+    CT_ARG_CHECK(cap == 0 || (vgrp && wg_per_cu && ms), "ct_tune_projector: NULL output array");
+    if (count) *count = 0;
+    if (g->k.kind != CT_CONE_CIRCULAR_3D) return CT_OK;
+    std::vector<StagedCfg> cands = {{4, 0}, {6, 0}, {8, 0}, {10, 0}, {12, 0}, {16, 0}};
+    if (4.0 * (double)(g->pad.nvx + g->pad.nvy) > kLlcBytes)
+        for (int grp : {2, 4, 6})
+            for (int w : {3, 4, 5}) cands.push_back(StagedCfg{-grp, w});
+    TuneScratch sc;
+    sc.s = (hipStream_t)stream;
+    const size_t nvol = g->pad.nvx + g->pad.nvy;
+    if (hipMalloc((void **)&sc.vol, nvol * sizeof(float)) != hipSuccess ||
+        hipMalloc((void **)&sc.y, g->n_rays * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("ct_tune_projector: device allocation of the scratch volume and sinogram failed");
+        return CT_ERR_ALLOC;
+    }
+    CT_HIP_CHECK(hipEventCreate(&sc.e0));
+    CT_HIP_CHECK(hipEventCreate(&sc.e1));
+    hipLaunchKernelGGL(k_fill_hash, dim3(4096), dim3(256), 0, sc.s, sc.vol, nvol);
+    CT_LAUNCH_CHECK();
+    NoProfile np;   // the tuner's launches stay out of the kernel timing
+    RestoreCfg restore{g, g->a_cfg.load()};
+    double best = 0.0;
+    StagedCfg win = cands[0];
+    for (size_t i = 0; i < cands.size(); ++i) {
+        g->a_cfg.store(pack_cfg(cands[i]));
+        CT_TRY(launch_project(g, sc.vol, sc.vol + g->pad.nvx, sc.y, CT_F32, nullptr, nullptr, sc.s));   // warm-up
+        CT_HIP_CHECK(hipEventRecord(sc.e0, sc.s));
+        for (int r = 0; r < reps; ++r)
+            CT_TRY(launch_project(g, sc.vol, sc.vol + g->pad.nvx, sc.y, CT_F32, nullptr, nullptr, sc.s));
+        CT_HIP_CHECK(hipEventRecord(sc.e1, sc.s));
+        CT_HIP_CHECK(hipEventSynchronize(sc.e1));
+        float t = 0.0f;
+        CT_HIP_CHECK(hipEventElapsedTime(&t, sc.e0, sc.e1));
+        const double m = (double)t / reps;
+        if ((int)i < cap) {
+            vgrp[i] = cands[i].vgrp;
+            wg_per_cu[i] = cands[i].wgcu;
+            ms[i] = m;
+        }
+        if (i == 0 || m < best) {
+            best = m;
+            win = cands[i];
+        }
+    }
+    g->a_cfg.store(pack_cfg(win));
+    restore.done = true;
+    if (count) *count = (int)cands.size();
     return CT_OK;
 }

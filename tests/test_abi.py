@@ -89,3 +89,14 @@ def test_invalid_descriptor_rejected_on_host():
     d = _lib.GeometryDesc(0, 16, 16, 1, 1.0, 10, None, 24, 1, 1.0, 1.0, 0.0, 0.0, 7)
     assert lib.ct_geometry_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_ARG
     assert b"projector" in lib.ct_last_error()
+
+
+def test_projector_setting_calls_reject_bad_arguments_on_host():
+    """The projector setting calls and the autotuner validate their
+    arguments before any device call."""
+    lib = _lib.load()
+    v, w = ctypes.c_int(), ctypes.c_int()
+    assert lib.ct_projector_config(None, 10, 0) == _lib.CT_ERR_ARG
+    assert lib.ct_projector_get_config(None, ctypes.byref(v), ctypes.byref(w)) == _lib.CT_ERR_ARG
+    assert lib.ct_tune_projector(None, 3, 0, None, None, None, None, None) == _lib.CT_ERR_ARG
+    assert b"geometry is NULL" in lib.ct_last_error()
