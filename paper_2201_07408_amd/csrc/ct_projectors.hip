@@ -1717,8 +1717,10 @@ __global__ __launch_bounds__(256, 5) void k_bp_cone_staged(GeomK g, const InT *_
         const float sodf = (float)g.sod, sddf = (float)g.sdd, inv_duf = (float)(1.0 / g.du);
         const float cuf = (float)(0.5 * (nu - 1)), cvf = (float)cv;
         const float dzf = (float)(g.vox * inv_dv), pz0f = (float)(pz0 * inv_dv), wcf = (float)wconst;
-        // FP32 data with rows a multiple of four: 16-byte staging loads
+        // rows a multiple of four: 16-byte staging loads of FP32 data,
+        // 8-byte loads of four FP16 values
         const bool vec4 = sizeof(InT) == 4 && (nu & 3) == 0 && ((uintptr_t)y & 15) == 0;
+        const bool vec4h = sizeof(InT) == 2 && (nu & 3) == 0 && ((uintptr_t)y & 7) == 0;
         // Each work-item stages the same cells (view within the group, row,
         // 16-byte column) of every view group, so their coordinates are
         // computed once; a view's box is one LDS word (u0 low, v0 high).
@@ -1746,6 +1748,11 @@ __global__ __launch_bounds__(256, 5) void k_bp_cone_staged(GeomK g, const InT *_
                         const InT *row = y + (size_t)(uint32_t)(p * nv + v) * (uint32_t)nu;
                         if (vec4 && (unsigned)u <= (unsigned)(nu - 4)) {
                             e = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(row) + u);
+                        } else if (vec4h && (unsigned)u <= (unsigned)(nu - 4)) {
+                            const uint2 h = *reinterpret_cast<const uint2 *>(row + u);
+                            const float2 lo = __half22float2(__builtin_bit_cast(__half2, h.x));
+                            const float2 hi = __half22float2(__builtin_bit_cast(__half2, h.y));
+                            e = make_float4(lo.x, lo.y, hi.x, hi.y);
                         } else {
                             float t4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
