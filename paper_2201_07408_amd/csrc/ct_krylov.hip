@@ -372,10 +372,9 @@ __global__ __launch_bounds__(256) void k_cgls_p(float *__restrict__ p, const flo
 // ===================================================================== host
 namespace {
 
-constexpr int kSweepBlk = 1024;
 int sweep_blocks(size_t n) {
     size_t t = (n + kTile - 1) / kTile;
-    return (int)(t < (size_t)kSweepBlk ? (t == 0 ? 1 : t) : (size_t)kSweepBlk);
+    return (int)(t < (size_t)kMaxBlk ? (t == 0 ? 1 : t) : (size_t)kMaxBlk);
 }
 
 int grid_1d(size_t n) {
@@ -530,7 +529,7 @@ static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *z
     const int *stop = b.st.flags + F_STOP;
     // one round of resident blocks where the sweep's grid would take a
     // second, partly filled one (16 FP32 basis vectors: 768 of 1024 blocks
-    // resident on 256 CUs, 276 -> 211 us at 256^3)
+    // resident on 256 CUs, 276 -> 212 us at 256^3)
 #define CT_MAXPY_DOT(NVV, WT, WP) \
     do { \
         const int res = resident_blocks(k_maxpy_dot<NVV, WT>); \
