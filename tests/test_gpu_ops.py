@@ -112,6 +112,12 @@ def test_fp16_storage(geoms, name):
     assert_close(xb, ref_b, TOL, "B_un FP16 data " + name)
     xt = host(ct.ct_backproject_AT(g, y16))
     assert_close(xt, oracle.backproject_AT(desc, host(y16)), TOL, "A^T FP16 data " + name)
+    # FP16 data are widened exactly when staged (four per 8-byte load where
+    # the rows allow it, one by one at the detector's edges): the same
+    # values given as FP32 must give the same bits
+    y32 = y16.float()
+    assert torch.equal(ct.ct_backproject_B(g, y16), ct.ct_backproject_B(g, y32)), "B_un " + name
+    assert torch.equal(ct.ct_backproject_AT(g, y16), ct.ct_backproject_AT(g, y32)), "A^T " + name
 
 
 @pytest.mark.parametrize("projector", [0, 1])
