@@ -97,6 +97,25 @@ def test_ba_gmres_finite_termination_k_equals_n(oracle):
     assert rel(r.x, x_ref) <= 1e-15 * cond, cond
 
 
+def test_ba_gmres_ramp_finite_termination_k_equals_n(oracle):
+    """With B = B_un F (the ramp-filtered back-projector, Sec. III) and B A
+    nonsingular, BA-GMRES at k = n solves B A x = B b exactly: the dense
+    system built column by column from unit vectors decides the iterate."""
+    g = parallel2d(16, 24, 24)
+    n, m = g.n_vox, g.n_rays
+    A = np.stack([oracle.project_A(g, np.eye(n)[j]) for j in range(n)], axis=1)
+    Bf = oracle.back_projector(g, "ramp")
+    B = np.stack([Bf(np.eye(m)[i]) for i in range(m)], axis=1)
+    rng = np.random.default_rng(15)
+    b = A @ rng.uniform(size=n) + 0.01 * rng.standard_normal(m)
+    S = B @ A
+    cond = np.linalg.cond(S)
+    x_ref = np.linalg.solve(S, B @ b)
+    r = oracle.ba_gmres(g, b, n, B="ramp")
+    assert r.iters_done <= n
+    assert rel(r.x, x_ref) <= 1e-15 * cond, cond
+
+
 def test_ab_gmres_finite_termination_k_equals_m(oracle):
     """With m <= n and A B nonsingular, AB-GMRES at k = m solves A x = b.
     The detector is narrower than the image and the angles avoid 0/90 deg,
