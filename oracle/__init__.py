@@ -17,7 +17,9 @@ follow the algorithm description of Sec. II of the paper:
 * BA-GMRES is GMRES on B A x = B b (Eq. 5); AB-GMRES is GMRES on A B y = b
   with x = B y (Eq. 4);
 * CGLS is the textbook conjugate-gradient recurrence for min ||A x - b||
-  (Eq. 2) with A^T replaced by the chosen back-projector;
+  (Eq. 2) with A^T replaced by the chosen back-projector (with B = A^T it is
+  pinned against LSQR; with B = B_un it minimises nothing and its iterates
+  are parity unpinned beyond the recurrence's own residual identity);
 * optionally GMRES keeps its basis as FP16 values (``basis="f16"``, a storage
   option of this implementation, see ``gmres``).
 """
@@ -371,7 +373,9 @@ class CglsResult:
 
 
 def cgls(g, b, iters: int, B: str = "AT") -> CglsResult:
-    """CGLS for Eq. 2 with the back-projector B in the place of A^T."""
+    """CGLS for Eq. 2 with the back-projector B in the place of A^T.
+    B = "AT": pinned (equals LSQR); B = "un": parity unpinned beyond the
+    recursive residual tracking ||b - A x_k||."""
     g = _geom(g)
     Bop = back_projector(g, B)
     b = _f64(b).reshape(-1)
