@@ -120,9 +120,10 @@ def cpu_baseline(desc3, b3, K=2):
 
 def cpu_small_configs(desc1, b1, desc2, b2):
     """The oracle's BA-GMRES (B_un) rate on the 64^2 workload (30
-    iterations) and the 128^3 workload (2 iterations) at one thread and at
-    all threads; at one thread the 128^3 solve runs on every 10th view and
-    its seconds are scaled by 10 (operator cost is linear in views)."""
+    iterations), the 128^3 workload (2 iterations) and one 256^2 slice of
+    the batched 2D workload, at one thread and at all threads; at one thread
+    the 128^3 solve runs on every 10th view and its seconds are scaled by 10
+    (operator cost is linear in views), and the slice runs 10 iterations."""
     import oracle
     from synth.geometry import GeometryDesc
     nthr = oracle.num_threads()
@@ -147,6 +148,18 @@ def cpu_small_configs(desc1, b1, desc2, b2):
         oracle.set_threads(1)
         out["C2_128cube_iters_per_s"]["1_thread"] = rate(gs, bs, 2) / sub
         out["C2_128cube_iters_per_s"]["1_thread_sample"] = "every %dth view, seconds scaled by %d" % (sub, sub)
+        # one slice of the batched 2D workload (256^2, 180 views, 384 bins,
+        # 1 % noise), as the batch solves it (B_un, 40 iterations) on all
+        # threads and for 10 iterations on one thread
+        from synth import workloads
+        g5, ps5, ns5 = next(t for t in workloads.w5_slices() if t[0].nx == 256 and t[0].n_views == 180)
+        c5 = np.asarray(oracle.project_A(g5, workloads.w5_phantom(g5, ps5)))
+        b5 = c5 + workloads.relative_gaussian_noise(c5, 0.01, ns5)
+        s5 = out.setdefault("C5_slice_256x256_180views_iters_per_s", {})
+        s5["1_thread"] = rate(g5, b5, 10)
+        oracle.set_threads(nthr)
+        s5["all_threads"] = rate(g5, b5, 40)
+        s5["sample"] = "one slice of the 64-slice batch; 10 iterations at one thread, 40 at all threads"
     finally:
         oracle.set_threads(nthr)
     return out
