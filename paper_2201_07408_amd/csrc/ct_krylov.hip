@@ -42,7 +42,7 @@ constexpr int kTile = 256;       // float4 groups per block per grid-stride step
 // Work-items stride over 16-byte groups of four elements (the last partial
 // group goes element by element), every basis vector of the chunk is read
 // once per pass with 16-byte loads, and all sums accumulate in FP64.
-template <int NV, typename WT>
+template <int NV, typename WT, bool NT>
 __global__ __launch_bounds__(256) void k_mdot(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
                                               const float *__restrict__ z, size_t n, int nrm, int ncol,
                                               double *__restrict__ partials, const int *__restrict__ stop) {
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_mdot(const WT *__restrict__ W, size_t l
     const WT *Wc = W + (size_t)vlo * ldw;
     constexpr int GE = Group<WT>::n;   // elements per group
     const size_t n4 = n / GE;
-    mdot_groups<NV>(Wc, ldw, cnt, z, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc, nacc);
+    mdot_groups<NV, WT, NT>(Wc, ldw, cnt, z, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256, acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)   // tail of fewer than four elements
         for (size_t i = n4 * GE; i < n; ++i) {
             const double zd = z[i];
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_mdot(const WT *__restrict__ W, size_t l
 
 // OT = __half stores the result as FP16 of oscale[0] * z' (the last pass of
 // an FP16-basis CGS2 step writing the new basis vector).
-template <int NV, typename WT, typename OT>
+template <int NV, typename WT, typename OT, bool NT>
 __global__ __launch_bounds__(256) void k_maxpy(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
                                                const float *zin, OT *zout, size_t n,
                                                const double *__restrict__ coef, const double *__restrict__ zscale,
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_maxpy(const WT *__restrict__ W, size_t 
     const WT *Wc = W + (size_t)vlo * ldw;
     constexpr int GE = Group<WT>::n;   // elements per group
     const size_t n4 = n / GE;
-    maxpy_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, os, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
+    maxpy_groups<NV, WT, OT, NT>(Wc, ldw, cnt, cf, zs, zin, zout, os, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
                      nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (size_t i = n4 * GE; i < n; ++i) {
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_maxpy(const WT *__restrict__ W, size_t 
 // chunk's basis groups in registers, so fewer of its blocks are resident
 // than of the other sweeps; it may run on fewer blocks than the nslot
 // partial slots the reductions read, and the slots past its grid get zeros.
-template <int NV, typename WT>
+template <int NV, typename WT, bool NT>
 __global__ __launch_bounds__(256) void k_maxpy_dot(const WT *__restrict__ W, size_t ldw, int vlo, int cnt,
                                                    const float *zin, float *zout, size_t n,
                                                    const double *__restrict__ coef,
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_maxpy_dot(const WT *__restrict__ W, siz
     const WT *Wc = W + (size_t)vlo * ldw;
     constexpr int GE = Group<WT>::n;   // elements per group
     const size_t n4 = n / GE;
-    maxpy_dot_groups<NV>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
+    maxpy_dot_groups<NV, WT, NT>(Wc, ldw, cnt, cf, zs, zin, zout, (size_t)blockIdx.x * 256, n4, (size_t)gridDim.x * 256,
                          acc, nacc);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (size_t i = n4 * GE; i < n; ++i) {
@@ -467,13 +467,26 @@ size_t carve_gmres(const ct_geometry *g, int solver, const ct_solver_opts &o, vo
 
 constexpr int kCgsChunk = 16;   // basis vectors per streaming pass (register budget)
 
+// Whether the basis vectors 0 .. nvec-1 exceed the 256 MB last-level cache:
+// then a sweep's loads of them are non-temporal (measured at 256^3: sweeps
+// 0.795 -> 0.777 ms per iteration; where the basis fits, as for 2D slices,
+// the ordinary loads keep it cached between the passes).
+static bool basis_beyond_llc(const GmresBufs &b, int nvec) {
+    return (double)nvec * (double)b.len * (b.w16 ? 2.0 : 4.0) > 256.0 * 1024 * 1024;
+}
+
 static int launch_mdot(const GmresBufs &b, int vlo, int cnt, const float *z, bool nrm, int ncol, hipStream_t s) {
     ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
+    const bool nt = basis_beyond_llc(b, vlo + cnt);
 #define CT_MDOT(NVV, WT, WP) \
-    hipLaunchKernelGGL((k_mdot<NVV, WT>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, z, b.len, (int)nrm, ncol, \
-                       b.st.partials, stop)
+    do { \
+        if (nt) hipLaunchKernelGGL((k_mdot<NVV, WT, true>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, z, \
+                                   b.len, (int)nrm, ncol, b.st.partials, stop); \
+        else hipLaunchKernelGGL((k_mdot<NVV, WT, false>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, z, \
+                                b.len, (int)nrm, ncol, b.st.partials, stop); \
+    } while (0)
 #define CT_MDOT_NV(WT, WP) \
     if (cnt <= 1) CT_MDOT(1, WT, WP); \
     else if (cnt <= 4) CT_MDOT(4, WT, WP); \
@@ -494,9 +507,14 @@ static int launch_maxpy(const GmresBufs &b, int vlo, int cnt, const float *zin, 
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
     const double *os = b.st.misc + M_BT;
+    const bool nt = basis_beyond_llc(b, vlo + cnt);
 #define CT_MAXPY(NVV, WT, OT, WP, ZO) \
-    hipLaunchKernelGGL((k_maxpy<NVV, WT, OT>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, ZO, b.len, \
-                       coef, zscale, os, (int)nrm, ncol, b.st.partials, stop)
+    do { \
+        if (nt) hipLaunchKernelGGL((k_maxpy<NVV, WT, OT, true>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, \
+                                   zin, ZO, b.len, coef, zscale, os, (int)nrm, ncol, b.st.partials, stop); \
+        else hipLaunchKernelGGL((k_maxpy<NVV, WT, OT, false>), dim3(nblk), dim3(256), 0, s, WP, b.ldw, vlo, cnt, \
+                                zin, ZO, b.len, coef, zscale, os, (int)nrm, ncol, b.st.partials, stop); \
+    } while (0)
 #define CT_MAXPY_NV(WT, OT, WP, ZO) \
     if (cnt <= 1) CT_MAXPY(1, WT, OT, WP, ZO); \
     else if (cnt <= 4) CT_MAXPY(4, WT, OT, WP, ZO); \
@@ -527,15 +545,21 @@ static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *z
     ProfScope prof(PROF_CGS, s);
     const int nblk = sweep_blocks(b.len / 4 + 1);
     const int *stop = b.st.flags + F_STOP;
+    const bool nt = basis_beyond_llc(b, vlo + cnt);
     // one round of resident blocks where the sweep's grid would take a
     // second, partly filled one (16 FP32 basis vectors: 768 of 1024 blocks
     // resident on 256 CUs, 276 -> 212 us at 256^3)
+#define CT_MAXPY_DOT_K(NVV, WT, NTV, WP) \
+    do { \
+        const int res = resident_blocks(k_maxpy_dot<NVV, WT, NTV>); \
+        const int nb = res > 0 && res < nblk ? res : nblk; \
+        hipLaunchKernelGGL((k_maxpy_dot<NVV, WT, NTV>), dim3(nb), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, zout, \
+                           b.len, coef, zscale, ncol, b.st.partials, nblk, stop); \
+    } while (0)
 #define CT_MAXPY_DOT(NVV, WT, WP) \
     do { \
-        const int res = resident_blocks(k_maxpy_dot<NVV, WT>); \
-        const int nb = res > 0 && res < nblk ? res : nblk; \
-        hipLaunchKernelGGL((k_maxpy_dot<NVV, WT>), dim3(nb), dim3(256), 0, s, WP, b.ldw, vlo, cnt, zin, zout, \
-                           b.len, coef, zscale, ncol, b.st.partials, nblk, stop); \
+        if (nt) CT_MAXPY_DOT_K(NVV, WT, true, WP); \
+        else CT_MAXPY_DOT_K(NVV, WT, false, WP); \
     } while (0)
 #define CT_MAXPY_DOT_NV(WT, WP) \
     if (cnt <= 1) CT_MAXPY_DOT(1, WT, WP); \
@@ -545,6 +569,7 @@ static int launch_maxpy_dot(const GmresBufs &b, int vlo, int cnt, const float *z
     if (b.w16) { CT_MAXPY_DOT_NV(__half, b.wh(0)) } else { CT_MAXPY_DOT_NV(float, b.wf(0)) }
 #undef CT_MAXPY_DOT_NV
 #undef CT_MAXPY_DOT
+#undef CT_MAXPY_DOT_K
     CT_LAUNCH_CHECK();
     return CT_OK;
 }

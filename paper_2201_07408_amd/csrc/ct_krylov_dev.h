@@ -71,12 +71,23 @@ template <typename WT> struct Group;
 template <> struct Group<float> { static constexpr int n = 4; };
 template <> struct Group<__half> { static constexpr int n = 8; };
 
+// NT: a non-temporal load, for sweeps whose basis vectors exceed the
+// last-level cache (each is read once per pass and would only evict what
+// the next pass could reuse)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <bool NT = false>
 __device__ __forceinline__ void ld_group(const float *p, size_t q, float (&v)[4]) {
-    const float4 t = reinterpret_cast<const float4 *>(p)[q];
+    f32x4 t;
+    if constexpr (NT) t = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p) + q);
+    else t = reinterpret_cast<const f32x4 *>(p)[q];
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
+template <bool NT = false>
 __device__ __forceinline__ void ld_group(const __half *p, size_t q, float (&v)[8]) {
-    const uint4 r = reinterpret_cast<const uint4 *>(p)[q];
+    u32x4 r;
+    if constexpr (NT) r = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p) + q);
+    else r = reinterpret_cast<const u32x4 *>(p)[q];
     const uint32_t w[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -119,7 +130,7 @@ __device__ __forceinline__ void st_elem(__half *p, size_t i, float v, float scal
 // Multi-dot over groups q0 + tid, q0 + tid + qstep, ... < q1 (groups of
 // Group<WT>::n elements): acc[j] += W[vlo+j] . z, nacc += z . z, all in
 // FP64 (products of FP32 values are exact in FP64).
-template <int NV, typename WT>
+template <int NV, typename WT, bool NT = false>
 __device__ __forceinline__ void mdot_groups(const WT *__restrict__ Wc, size_t ldw, int cnt,
                                             const float *__restrict__ z, size_t q0, size_t q1, size_t qstep,
                                             double (&acc)[NV], double &nacc) {
@@ -135,7 +146,7 @@ __device__ __forceinline__ void mdot_groups(const WT *__restrict__ Wc, size_t ld
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
                 float w[GE];
-                ld_group(Wc + (size_t)j * ldw, q, w);
+                ld_group<NT>(Wc + (size_t)j * ldw, q, w);
                 double d = 0.0;
 #pragma unroll
                 for (int e = 0; e < GE; ++e) d += (double)w[e] * zd[e];
@@ -147,7 +158,7 @@ __device__ __forceinline__ void mdot_groups(const WT *__restrict__ Wc, size_t ld
 // Multi-axpy over groups: z' = zs z - sum_j cf[j] W[vlo+j] (FP64), rounded
 // to FP32; nacc += z' . z' (of the FP32 values); stored as OT (FP16 output:
 // oscale * z').
-template <int NV, typename WT, typename OT>
+template <int NV, typename WT, typename OT, bool NT = false>
 __device__ __forceinline__ void maxpy_groups(const WT *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
                                              double zs, const float *zin, OT *zout, float oscale, size_t q0,
                                              size_t q1, size_t qstep, double &nacc) {
@@ -162,7 +173,7 @@ __device__ __forceinline__ void maxpy_groups(const WT *__restrict__ Wc, size_t l
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
                 float w[GE];
-                ld_group(Wc + (size_t)j * ldw, q, w);
+                ld_group<NT>(Wc + (size_t)j * ldw, q, w);
                 const double c = cf[j];
 #pragma unroll
                 for (int e = 0; e < GE; ++e) u[e] -= c * (double)w[e];
@@ -180,7 +191,7 @@ __device__ __forceinline__ void maxpy_groups(const WT *__restrict__ Wc, size_t l
 // W[vlo+j] (FP64, rounded to FP32 and stored), then acc[j] += W[vlo+j] . z'
 // with the same W values still in registers, so the chunk of basis vectors
 // is read once for both; nacc += z' . z'.
-template <int NV, typename WT>
+template <int NV, typename WT, bool NT = false>
 __device__ __forceinline__ void maxpy_dot_groups(const WT *__restrict__ Wc, size_t ldw, int cnt, const double *cf,
                                                  double zs, const float *zin, float *zout, size_t q0, size_t q1,
                                                  size_t qstep, double (&acc)[NV], double &nacc) {
@@ -195,7 +206,7 @@ __device__ __forceinline__ void maxpy_dot_groups(const WT *__restrict__ Wc, size
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (j < cnt) {
-                ld_group(Wc + (size_t)j * ldw, q, w[j]);
+                ld_group<NT>(Wc + (size_t)j * ldw, q, w[j]);
                 const double c = cf[j];
 #pragma unroll
                 for (int e = 0; e < GE; ++e) u[e] -= c * (double)w[j][e];
