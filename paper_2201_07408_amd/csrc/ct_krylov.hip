@@ -230,6 +230,59 @@ __global__ __launch_bounds__(256) void k_mon_resid(const float *__restrict__ bas
     if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The same sums with four consecutive elements per work-item: 16-byte
+// loads of every vector, four vectors' loads in flight, and per element the
+// same order of FP64 operations (base, then the terms j = 0, 1, ...).  base
+// (if any) and V 16-byte aligned, ldv a multiple of four.
+__global__ __launch_bounds__(256) void k_mon_resid4(const float *__restrict__ base, const float *__restrict__ V,
+                                                    size_t ldv, size_t n, int k, KState st,
+                                                    const double *__restrict__ cd, double *__restrict__ partials) {
+    if (!mon_active(st, k)) return;
+    __shared__ double cf[kMaxVec];
+    __shared__ double red[4];
+    const int kd = k + 1;
+    for (int j = threadIdx.x; j < kd; j += 256) cf[j] = cd[j];
+    __syncthreads();
+    double acc = 0.0;
+    const size_t n4 = n / 4;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += (size_t)gridDim.x * 256) {
+        double r[4] = {0.0, 0.0, 0.0, 0.0};
+        if (base) {
+            const float4 bb = reinterpret_cast<const float4 *>(base)[q];
+            r[0] = bb.x; r[1] = bb.y; r[2] = bb.z; r[3] = bb.w;
+        }
+        int j = 0;
+        for (; j + 4 <= kd; j += 4) {
+            float4 v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = reinterpret_cast<const float4 *>(V + (size_t)(j + t) * ldv)[q];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double c = cf[j + t];
+                r[0] -= c * (double)v[t].x; r[1] -= c * (double)v[t].y;
+                r[2] -= c * (double)v[t].z; r[3] -= c * (double)v[t].w;
+            }
+        }
+        for (; j < kd; ++j) {
+            const float4 v = reinterpret_cast<const float4 *>(V + (size_t)j * ldv)[q];
+            const double c = cf[j];
+            r[0] -= c * (double)v.x; r[1] -= c * (double)v.y;
+            r[2] -= c * (double)v.z; r[3] -= c * (double)v.w;
+        }
+        acc += (r[0] * r[0] + r[1] * r[1]) + (r[2] * r[2] + r[3] * r[3]);
+    }
+    if (blockIdx.x == 0 && (size_t)threadIdx.x < n - 4 * n4) {   // the last n mod 4 elements
+        const size_t i = 4 * n4 + threadIdx.x;
+        double r = base ? (double)base[i] : 0.0;
+        for (int j = 0; j < kd; ++j) r -= cf[j] * (double)V[(size_t)j * ldv + i];
+        acc += r * r;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // out[k+1] = sqrt(sum / div)
 __global__ void k_mon_store(const double *__restrict__ partials, int nblk, int k, KState st, double div,
                             double *__restrict__ out) {
@@ -708,8 +761,15 @@ struct MonitorOut {
 // b_i - sum c_j V[j]_i over n elements -> out[k+1] (divided by div inside the root)
 static int mon_curve(const GmresBufs &bf, const float *base, const float *V, size_t ldv, size_t n, int k,
                      double div, double *out, hipStream_t s) {
-    const int nblk = grid_1d(n) < kMaxBlk ? grid_1d(n) : kMaxBlk;
-    hipLaunchKernelGGL(k_mon_resid, dim3(nblk), dim3(256), 0, s, base, V, ldv, n, k, bf.st, bf.mon_c, bf.mon_part);
+    const bool vec = ((uintptr_t)base & 15) == 0 && ((uintptr_t)V & 15) == 0 && ldv % 4 == 0;
+    const int ng = grid_1d(vec ? n / 4 + 1 : n);
+    const int nblk = ng < kMaxBlk ? ng : kMaxBlk;
+    if (vec)
+        hipLaunchKernelGGL(k_mon_resid4, dim3(nblk), dim3(256), 0, s, base, V, ldv, n, k, bf.st, bf.mon_c,
+                           bf.mon_part);
+    else
+        hipLaunchKernelGGL(k_mon_resid, dim3(nblk), dim3(256), 0, s, base, V, ldv, n, k, bf.st, bf.mon_c,
+                           bf.mon_part);
     CT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mon_store, dim3(1), dim3(64), 0, s, bf.mon_part, nblk, k, bf.st, div, out);
     CT_LAUNCH_CHECK();
