@@ -23,7 +23,7 @@ import oracle
 import paper_2201_07408_amd as ct
 from paper_2201_07408_amd import _lib as L
 from synth import workloads
-from synth.geometry import cone3d
+from synth.geometry import cone3d, GeometryDesc, PARALLEL_2D
 from tests.gpu_helpers import dev, f32, host, rel, say
 
 pytestmark = pytest.mark.gpu
@@ -100,6 +100,33 @@ def test_monitor_curves_cone_siddon():
     for k in range(K + 1):
         assert abs(r.data_res[k] - d_ref[k]) <= TOL * d_ref[0]
         assert abs(r.img_rmse[k] - i_ref[k]) <= TOL * i_ref[0]
+
+
+def test_monitor_curves_ragged_and_unaligned():
+    """Vector lengths that are not multiples of four (1073 pixels, 3050
+    rays: the four-element kernel's tail) and a reference image that is not
+    16-byte aligned (the one-element kernel) give the oracle's curves."""
+    desc = GeometryDesc(PARALLEL_2D, 37, 29, 1, 0.9, 50, 61, 1, 1.1, 1.0)
+    assert desc.n_vox % 4 != 0 and desc.n_rays % 4 != 0
+    g = ct.Geometry(desc)
+    x_true = f32(np.random.default_rng(21).uniform(0, 1, size=desc.vol_shape))
+    b = f32(oracle.project_A(desc, x_true))
+    K = 8
+    d_ref, i_ref = oracle_curves(desc, b, x_true, K, "un")
+    r = ct.ct_ba_gmres_monitor(g, dev(b), K, x_ref=dev(x_true))
+    buf = torch.zeros(desc.n_vox + 1, device="cuda")
+    buf[1:] = dev(x_true).reshape(-1)
+    x_off = buf[1:].view(desc.vol_shape)   # 4 bytes past a 16-byte boundary
+    assert x_off.data_ptr() % 16 != 0
+    r2 = ct.ct_ba_gmres_monitor(g, dev(b), K, x_ref=x_off)
+    say("monitor ragged: data", r.data_res[-1], d_ref[-1], "image", r.img_rmse[-1], r2.img_rmse[-1], i_ref[-1])
+    for rr in (r, r2):
+        assert rr.iters_done == K
+        for k in range(K + 1):
+            assert abs(rr.data_res[k] - d_ref[k]) <= TOL * d_ref[0]
+            assert abs(rr.img_rmse[k] - i_ref[k]) <= TOL * i_ref[0]
+    assert r.data_res == r2.data_res
+    assert np.allclose(r.img_rmse, r2.img_rmse, rtol=1e-12, atol=0.0)
 
 
 def test_monitor_without_reference_and_errors():
