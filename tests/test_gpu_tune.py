@@ -74,6 +74,28 @@ def test_tuner_keeps_its_fastest_candidate():
     assert torch.equal(ct.ct_project_A(g, x), ref)
 
 
+def test_allocation_free_projection_under_other_settings():
+    """ct_project_A_noalloc reads the same setting: under the band order
+    with an occupancy cap (dynamic LDS) and under a small XCD group it
+    still gives the workspace entry point's bits."""
+    import ctypes
+    from paper_2201_07408_amd import _lib as L
+    desc = _geometry(0)
+    g = ct.Geometry(desc)
+    gen = torch.Generator(device="cuda").manual_seed(8)
+    x = torch.rand(g.vol_shape, device="cuda", generator=gen)
+    ref = ct.ct_project_A(g, x)
+    lib = L.load()
+    for v, w in [(-4, 3), (6, 2), (0, 0)]:
+        ct.ct_projector_config(g, v, w)
+        out = torch.empty(g.sino_shape, device="cuda")
+        st = lib.ct_project_A_noalloc(g.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      L.CT_F32, 1, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == L.CT_OK, lib.ct_last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (v, w)
+
+
 def test_settings_rejected_or_ignored_where_they_do_not_apply():
     g = ct.Geometry(_geometry(0))
     for v, w in [(0, 4), (65, 0), (-17, 0), (10, 9), (10, -1)]:
