@@ -57,8 +57,11 @@ A_TRAFFIC_BYTES = 6816395059
 A_TRAFFIC_SRC = "f19e6b0276162d7f"
 
 
+_T_START = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[%6.1f s]" % (time.perf_counter() - _T_START), *a, file=sys.stderr, flush=True)
 
 
 def phantom_scaled_data(vol, clean, seed=303):
