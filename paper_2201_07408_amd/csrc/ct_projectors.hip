@@ -55,6 +55,19 @@ __device__ __forceinline__ float to_f(__half v) { return __half2float(v); }
 template <typename T> __device__ __forceinline__ T from_f(float v);
 template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
 template <> __device__ __forceinline__ __half from_f<__half>(float v) { return __float2half_rn(v); }
+// four consecutive elements as floats, from a 16-byte (FP32) or 8-byte
+// (FP16) aligned address
+template <typename InT>
+__device__ __forceinline__ float4 ld4f(const InT *p);
+template <> __device__ __forceinline__ float4 ld4f<float>(const float *p) {
+    return *reinterpret_cast<const float4 *>(p);
+}
+template <> __device__ __forceinline__ float4 ld4f<__half>(const __half *p) {
+    const uint2 h = *reinterpret_cast<const uint2 *>(p);
+    const float2 lo = __half22float2(__builtin_bit_cast(__half2, h.x));
+    const float2 hi = __half22float2(__builtin_bit_cast(__half2, h.y));
+    return make_float4(lo.x, lo.y, hi.x, hi.y);
+}
 
 // ------------------------------------------------------------- padding
 // Zero only the border cells of both padded copies.
@@ -2189,10 +2202,11 @@ __global__ __launch_bounds__(256) void k_bramp(const BSlice *__restrict__ sl, in
 template <typename InT, typename OutT, int NRG>
 __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, OutT *__restrict__ out,
                                                    const float *__restrict__ taps, int nu, size_t rows,
-                                                   const int *__restrict__ stop) {
+                                                   int vec_in, const int *__restrict__ stop) {
     if (stop && *stop) return;
     extern __shared__ float sm[];
     constexpr int R = 16 * NRG;
+    constexpr int TPR = 256 / R;   // staging work-items per row
     const int ne = (nu + 1) / 2, no = nu / 2;
     const int nep = (ne + 15) & ~15, nop = (no + 15) & ~15;
     const int ss = ((nep > nop ? nep : nop) + 31 & ~31) + 2;   // half-row stride = 2 (mod 32 banks)
@@ -2212,11 +2226,26 @@ __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, Ou
         // inputs of the other parity: q[2m + 1 - par], m < K
         const int K = par ? nep : nop, kcnt = par ? ne : no;
         __syncthreads();   // previous phase's readers are done; taps written
-        for (int t = tid; t < R * ss; t += 256) {
-            const int r = t / ss, m = t - r * ss;
-            float v = 0.0f;
-            if (m < kcnt && r0 + r < rows) v = to_f(q[(r0 + r) * nu + 2 * m + 1 - par]);
-            Qs[t] = v;
+        {
+            const int r = tid / TPR, c = tid % TPR;
+            float *dst = Qs + r * ss;
+            if (r0 + r < rows) {
+                const InT *src = q + (r0 + r) * nu;
+                int m = 0;
+                if (vec_in) {
+                    // this parity's two elements of each 4-element load
+                    // (nu divisible by 4, so kcnt = nu / 2)
+                    for (int j = c; 4 * j < nu; j += TPR) {
+                        const float4 v = ld4f(src + 4 * j);
+                        dst[2 * j] = par ? v.x : v.y;
+                        dst[2 * j + 1] = par ? v.z : v.w;
+                    }
+                    m = nu / 2;
+                }
+                for (m += c; m < ss; m += TPR) dst[m] = m < kcnt ? to_f(src[2 * m + 1 - par]) : 0.0f;
+            } else {
+                for (int m = c; m < ss; m += TPR) dst[m] = 0.0f;
+            }
         }
         __syncthreads();
         const float h0 = hsym[lmax];
@@ -2262,22 +2291,26 @@ __global__ __launch_bounds__(256) void k_ramp_mfma(const InT *__restrict__ q, Ou
 }
 
 // The same filter with whole rows staged: for rows short enough that 16 of
-// them (both parities) fit in LDS, a wavefront computes the even and the odd
-// outputs of a 16-output block back to back, adds the h0 terms from LDS, and
-// stores the 32 interleaved outputs of each row as contiguous 16-byte
-// vectors.  Input and output then move once, in full lines, where the
-// one-parity kernel reads each input twice and writes stride-2.
+// them (both parities) fit in LDS, 16 work-items stage each row with 16-byte
+// loads where the row allows (no index division), and a wavefront computes
+// two adjacent 16-output blocks of both parities, adds the h0 terms from LDS
+// and stores the interleaved outputs of each row as contiguous 16-byte
+// vectors.  Input and output move once, in full lines.  The two blocks share
+// the input operand, and the Toeplitz block of the upper outputs at input m
+// is the lower block's at input m - 16, so its operand comes from a four-step
+// register ring rather than from LDS.  Outputs per parity are padded to 32;
+// the padded outputs are computed from zeros and not stored.
 template <typename InT, typename OutT>
 __global__ __launch_bounds__(256) void k_ramp_rows(const InT *__restrict__ q, OutT *__restrict__ out,
                                                    const float *__restrict__ taps, int nu, size_t rows,
-                                                   int vec_out, const int *__restrict__ stop) {
+                                                   int vec_in, int vec_out, const int *__restrict__ stop) {
     if (stop && *stop) return;
     extern __shared__ float sm[];
     const int ne = (nu + 1) / 2, no = nu / 2;
     const int nep = (ne + 15) & ~15, nop = (no + 15) & ~15;
-    const int P2 = nep > nop ? nep : nop;      // outputs per parity, padded to 16
-    const int ss = 2 * P2 + 1;                 // odd row stride: rows start on different banks
-    const int lmax = 2 * P2 + 1;
+    const int P2 = ((nep > nop ? nep : nop) + 31) & ~31;   // outputs per parity, padded to 32
+    const int ss = 2 * P2 + 1;                             // odd row stride: rows start on different banks
+    const int lmax = 2 * P2 + 33;                          // the ring reaches 16 inputs before m = 0
     float *Qs = sm, *hsym = sm + 16 * ss;
     const size_t r0 = (size_t)blockIdx.x * 16;
     const int tid = threadIdx.x;
@@ -2285,11 +2318,26 @@ __global__ __launch_bounds__(256) void k_ramp_rows(const InT *__restrict__ q, Ou
         const int L = t - lmax, aL = L < 0 ? -L : L;
         hsym[t] = aL < nu ? taps[aL] : 0.0f;
     }
-    for (int t = tid; t < 16 * ss; t += 256) {
-        const int r = t / ss, m = t - r * ss;
-        float v = 0.0f;
-        if (m < nu && r0 + r < rows) v = to_f(q[(r0 + r) * nu + m]);
-        Qs[t] = v;
+    {
+        const int r = tid >> 4, c = tid & 15;   // 16 work-items per row
+        float *dst = Qs + r * ss;
+        if (r0 + r < rows) {
+            const InT *src = q + (r0 + r) * nu;
+            int m = 0;
+            if (vec_in) {
+                for (int m4 = 4 * c; m4 < nu; m4 += 64) {
+                    const float4 v = ld4f(src + m4);
+                    dst[m4] = v.x;
+                    dst[m4 + 1] = v.y;
+                    dst[m4 + 2] = v.z;
+                    dst[m4 + 3] = v.w;
+                }
+                m = nu;
+            }
+            for (m += c; m < ss; m += 16) dst[m] = m < nu ? to_f(src[m]) : 0.0f;
+        } else {
+            for (int m = c; m < ss; m += 16) dst[m] = 0.0f;
+        }
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -2297,43 +2345,69 @@ __global__ __launch_bounds__(256) void k_ramp_rows(const InT *__restrict__ q, Ou
     const float h0 = hsym[lmax];
     const size_t row = r0 + li;
     typedef float f4 __attribute__((ext_vector_type(4)));
-    for (int task = wave; task < P2 / 16; task += 4) {
-        const int i0 = 16 * task;
-        // outputs 2i + par from the inputs of the other parity, q[2m + 1 - par];
-        // the two parities' chains are interleaved so that the matrix core
-        // has two independent accumulations in flight (nop <= nep <= nop + 16)
+    for (int task = wave; task < P2 / 32; task += 4) {
+        const int i0 = 32 * task;
+        // outputs 2i + par from the inputs of the other parity, q[2m + 1 - par]
+        // (nop <= nep <= nop + 16); four independent accumulation chains
         const float *ap0 = hsym + lmax + 2 * (i0 + li - lk) - 1, *ap1 = ap0 + 2;
         const float *bp0 = Qs + li * ss + 2 * lk + 1, *bp1 = bp0 - 1;
-        f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 2
-        for (int m0 = 0; m0 < nop; m0 += 4) {
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap0[-2 * m0], bp0[2 * m0], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1[-2 * m0], bp1[2 * m0], acc1, 0, 0, 0);
+        f4 e0 = {0.0f, 0.0f, 0.0f, 0.0f}, o0 = e0, e1 = e0, o1 = e0;
+        float ra0 = ap0[32], rb0 = ap0[24], rc0 = ap0[16], rd0 = ap0[8];
+        float ra1 = ap1[32], rb1 = ap1[24], rc1 = ap1[16], rd1 = ap1[8];
+#define CT_RAMP_STEP(M, R0, R1)                                             \
+    {                                                                       \
+        const float x0 = ap0[-2 * (M)], x1 = ap1[-2 * (M)];                 \
+        const float b0 = bp0[2 * (M)], b1 = bp1[2 * (M)];                   \
+        e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, b0, e0, 0, 0, 0);     \
+        o0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, b1, o0, 0, 0, 0);     \
+        e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(R0, b0, e1, 0, 0, 0);     \
+        o1 = __builtin_amdgcn_mfma_f32_16x16x4f32(R1, b1, o1, 0, 0, 0);     \
+        R0 = x0;                                                            \
+        R1 = x1;                                                            \
+    }
+        int m0 = 0;
+        for (; m0 + 16 <= nop; m0 += 16) {
+            CT_RAMP_STEP(m0, ra0, ra1)
+            CT_RAMP_STEP(m0 + 4, rb0, rb1)
+            CT_RAMP_STEP(m0 + 8, rc0, rc1)
+            CT_RAMP_STEP(m0 + 12, rd0, rd1)
         }
-        for (int m0 = nop; m0 < nep; m0 += 4)
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1[-2 * m0], bp1[2 * m0], acc1, 0, 0, 0);
-        float o[8];
+#undef CT_RAMP_STEP
+        for (int m = m0; m < nep; m += 4) {
+            if (m < nop) {
+                e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap0[-2 * m], bp0[2 * m], e0, 0, 0, 0);
+                e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap0[32 - 2 * m], bp0[2 * m], e1, 0, 0, 0);
+            }
+            o0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1[-2 * m], bp1[2 * m], o0, 0, 0, 0);
+            o1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1[32 - 2 * m], bp1[2 * m], o1, 0, 0, 0);
+        }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = li * ss + 2 * (i0 + 4 * lk + r);
-            o[2 * r] = acc0[r] + h0 * Qs[c];
-            o[2 * r + 1] = acc1[r] + h0 * Qs[c + 1];
-        }
-        if (row < rows) {
-            const int col0 = 2 * (i0 + 4 * lk);   // this lane's 8 consecutive outputs of the row
-            OutT *dst = out + row * nu + col0;
-            if (vec_out && col0 + 8 <= nu) {
-                if (sizeof(OutT) == 4) {
-                    reinterpret_cast<float4 *>(dst)[0] = make_float4(o[0], o[1], o[2], o[3]);
-                    reinterpret_cast<float4 *>(dst)[1] = make_float4(o[4], o[5], o[6], o[7]);
+        for (int h = 0; h < 2; ++h) {
+            const f4 ev = h ? e1 : e0, od = h ? o1 : o0;
+            const int ib = i0 + 16 * h;
+            float o[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = li * ss + 2 * (ib + 4 * lk + r);
+                o[2 * r] = ev[r] + h0 * Qs[c];
+                o[2 * r + 1] = od[r] + h0 * Qs[c + 1];
+            }
+            if (row < rows) {
+                const int col0 = 2 * (ib + 4 * lk);   // this lane's 8 consecutive outputs of the row
+                OutT *dst = out + row * nu + col0;
+                if (vec_out && col0 + 8 <= nu) {
+                    if (sizeof(OutT) == 4) {
+                        reinterpret_cast<float4 *>(dst)[0] = make_float4(o[0], o[1], o[2], o[3]);
+                        reinterpret_cast<float4 *>(dst)[1] = make_float4(o[4], o[5], o[6], o[7]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) dst[k] = from_f<OutT>(o[k]);
+                    }
                 } else {
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) dst[k] = from_f<OutT>(o[k]);
+                    for (int k = 0; k < 8; ++k)
+                        if (col0 + k < nu) dst[k] = from_f<OutT>(o[k]);
                 }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (col0 + k < nu) dst[k] = from_f<OutT>(o[k]);
             }
         }
     }
@@ -2341,8 +2415,9 @@ __global__ __launch_bounds__(256) void k_ramp_rows(const InT *__restrict__ q, Ou
 
 static size_t ramp_rows_lds(int nu) {
     const int ne = (nu + 1) / 2, no = nu / 2;
-    const int P2 = ((ne + 15) & ~15) > ((no + 15) & ~15) ? ((ne + 15) & ~15) : ((no + 15) & ~15);
-    return sizeof(float) * ((size_t)16 * (2 * P2 + 1) + 2 * (size_t)(2 * P2 + 1) + 1);
+    const int nep = (ne + 15) & ~15, nop = (no + 15) & ~15;
+    const int P2 = ((nep > nop ? nep : nop) + 31) & ~31;
+    return sizeof(float) * ((size_t)16 * (2 * P2 + 1) + 2 * (size_t)(2 * P2 + 33) + 1);
 }
 
 // LDS bytes of k_ramp_mfma for a row length and row-group count
@@ -2656,9 +2731,11 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
         dim3 rgrid((unsigned)((rows + 15) / 16)), rblock(256);
         const size_t es = out_dtype == CT_F16 ? 2 : 4;
         const int vec_out = (nu % 4 == 0) && ((uintptr_t)out % 16 == 0) && (es == 4 || nu % 8 == 0);
+        const size_t is = q_dtype == CT_F16 ? 2 : 4;
+        const int vec_in = (nu % 4 == 0) && ((uintptr_t)q % (4 * is) == 0);
 #define CT_RAMP_ROWS(IT, OT) \
     hipLaunchKernelGGL((k_ramp_rows<IT, OT>), rgrid, rblock, lds, s, (const IT *)q, (OT *)out, g->d_ramp, nu, rows, \
-                       vec_out, stop)
+                       vec_in, vec_out, stop)
         if (q_dtype == CT_F32 && out_dtype == CT_F32) CT_RAMP_ROWS(float, float);
         else if (q_dtype == CT_F16 && out_dtype == CT_F16) CT_RAMP_ROWS(__half, __half);
         else if (q_dtype == CT_F16 && out_dtype == CT_F32) CT_RAMP_ROWS(__half, float);
@@ -2677,21 +2754,22 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
         const size_t lds = ramp_mfma_lds(nu, nrg);
         if (lds <= 64 * 1024) {
             const size_t rpb = 16 * (size_t)nrg;
+            const int vec_in = (nu % 4 == 0) && ((uintptr_t)q % (q_dtype == CT_F16 ? 8 : 16) == 0);
             dim3 mgrid((unsigned)((rows + rpb - 1) / rpb)), mblock(256);
 #define CT_RAMP_MFMA(NRGV)                                                                                        \
     do {                                                                                                          \
         if (q_dtype == CT_F32 && out_dtype == CT_F32)                                                             \
             hipLaunchKernelGGL((k_ramp_mfma<float, float, NRGV>), mgrid, mblock, lds, s, (const float *)q,        \
-                               (float *)out, g->d_ramp, nu, rows, stop);                                          \
+                               (float *)out, g->d_ramp, nu, rows, vec_in, stop);                                  \
         else if (q_dtype == CT_F16 && out_dtype == CT_F16)                                                        \
             hipLaunchKernelGGL((k_ramp_mfma<__half, __half, NRGV>), mgrid, mblock, lds, s, (const __half *)q,     \
-                               (__half *)out, g->d_ramp, nu, rows, stop);                                         \
+                               (__half *)out, g->d_ramp, nu, rows, vec_in, stop);                                 \
         else if (q_dtype == CT_F16 && out_dtype == CT_F32)                                                        \
             hipLaunchKernelGGL((k_ramp_mfma<__half, float, NRGV>), mgrid, mblock, lds, s, (const __half *)q,      \
-                               (float *)out, g->d_ramp, nu, rows, stop);                                          \
+                               (float *)out, g->d_ramp, nu, rows, vec_in, stop);                                  \
         else                                                                                                      \
             hipLaunchKernelGGL((k_ramp_mfma<float, __half, NRGV>), mgrid, mblock, lds, s, (const float *)q,       \
-                               (__half *)out, g->d_ramp, nu, rows, stop);                                         \
+                               (__half *)out, g->d_ramp, nu, rows, vec_in, stop);                                 \
     } while (0)
             CT_RAMP_MFMA(nrg);
 #undef CT_RAMP_MFMA
@@ -2703,7 +2781,21 @@ int launch_ramp(const ct_geometry *g, const void *q, int q_dtype, void *out, int
         // register-blocked path: RB outputs per lane, four rows per workgroup
         const int rb = nu <= 128 ? 2 : nu <= 256 ? 4 : nu <= 384 ? 6 : 8;
         dim3 rgrid((unsigned)((rows + 3) / 4)), rblock(256);
-#define CT_RAMP_RB(RBV)                                                                                           do {                                                                                                              if (q_dtype == CT_F32 && out_dtype == CT_F32)                                                                     hipLaunchKernelGGL((k_ramp_rb<RBV, float, float>), rgrid, rblock, 0, s, (const float *)q, (float *)out, g->d_ramp, nu, rows, stop);         else if (q_dtype == CT_F16 && out_dtype == CT_F16)                                                                hipLaunchKernelGGL((k_ramp_rb<RBV, __half, __half>), rgrid, rblock, 0, s, (const __half *)q, (__half *)out, g->d_ramp, nu, rows, stop);         else if (q_dtype == CT_F16 && out_dtype == CT_F32)                                                                hipLaunchKernelGGL((k_ramp_rb<RBV, __half, float>), rgrid, rblock, 0, s, (const __half *)q, (float *)out, g->d_ramp, nu, rows, stop);         else                                                                                                              hipLaunchKernelGGL((k_ramp_rb<RBV, float, __half>), rgrid, rblock, 0, s, (const float *)q, (__half *)out, g->d_ramp, nu, rows, stop);     } while (0)
+#define CT_RAMP_RB(RBV)                                                                                   \
+    do {                                                                                                  \
+        if (q_dtype == CT_F32 && out_dtype == CT_F32)                                                     \
+            hipLaunchKernelGGL((k_ramp_rb<RBV, float, float>), rgrid, rblock, 0, s, (const float *)q,     \
+                               (float *)out, g->d_ramp, nu, rows, stop);                                  \
+        else if (q_dtype == CT_F16 && out_dtype == CT_F16)                                                \
+            hipLaunchKernelGGL((k_ramp_rb<RBV, __half, __half>), rgrid, rblock, 0, s, (const __half *)q,  \
+                               (__half *)out, g->d_ramp, nu, rows, stop);                                 \
+        else if (q_dtype == CT_F16 && out_dtype == CT_F32)                                                \
+            hipLaunchKernelGGL((k_ramp_rb<RBV, __half, float>), rgrid, rblock, 0, s, (const __half *)q,   \
+                               (float *)out, g->d_ramp, nu, rows, stop);                                  \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_ramp_rb<RBV, float, __half>), rgrid, rblock, 0, s, (const float *)q,    \
+                               (__half *)out, g->d_ramp, nu, rows, stop);                                 \
+    } while (0)
         switch (rb) {
         case 2: CT_RAMP_RB(2); break;
         case 4: CT_RAMP_RB(4); break;
