@@ -834,15 +834,17 @@ template <typename InT>
 __global__ __launch_bounds__(256) void k_ray_step_scale(GeomK g, const InT *__restrict__ y, float *__restrict__ ys,
                                                         const int *__restrict__ stop) {
     if (stop && *stop) return;
-    const size_t n = (size_t)g.P * g.nv * g.nu;
+    // one detector row (view p, row av) per wavefront, lanes along the row
+    const int rows = g.P * g.nv;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const float Cvf = (float)(0.5 * (g.nv - 1)), dvf = (float)g.dv;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int au = (int)(i % (size_t)g.nu);
-        const size_t pv = i / (size_t)g.nu;
-        const int av = (int)(pv % (size_t)g.nv), p = (int)(pv / (size_t)g.nv);
-        const ColT &T = g.colT[(size_t)p * g.nu + au];
+    for (int row = (int)blockIdx.x * 4 + wave; row < rows; row += (int)gridDim.x * 4) {
+        const int p = row / g.nv, av = row - p * g.nv;
         const float vv = ((float)av - Cvf) * dvf;
-        ys[i] = fabsf(T.is) * sqrtf(fmaf(vv, vv, T.sxy)) * to_f(y[i]);
+        const ColT *T = g.colT + (size_t)p * g.nu;
+        const size_t base = (size_t)row * g.nu;
+        for (int au = lane; au < g.nu; au += 64)
+            ys[base + au] = fabsf(T[au].is) * sqrtf(fmaf(vv, vv, T[au].sxy)) * to_f(y[base + au]);
     }
 }
 
@@ -2634,7 +2636,7 @@ int launch_project_T_gather(const ct_geometry *g, const void *y, int y_dtype, fl
         return CT_ERR_ARG;
     }
     ProfScope prof(PROF_AT, s);
-    size_t blocks = (g->n_rays + 255) / 256;
+    size_t blocks = ((size_t)g->k.P * g->k.nv + 3) / 4;   // four rows per workgroup
     if (blocks > 16384) blocks = 16384;
     if (y_dtype == CT_F32)
         hipLaunchKernelGGL(k_ray_step_scale<float>, dim3((unsigned)blocks), dim3(256), 0, s, g->k, (const float *)y, ys, stop);
