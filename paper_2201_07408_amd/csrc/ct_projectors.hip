@@ -1800,16 +1800,35 @@ __global__ __launch_bounds__(256, 5) void k_bp_cone_staged(GeomK g, const InT *_
                     const float wu = __builtin_amdgcn_fractf(fur);
                     const int lu = min(max((int)fur, 0), kSU - 2);
                     const float fv0r = fmaf(M, pz0f, cvf - (float)s_box[p][1]);
-                    const float *tv = tile + vv * kSV * kSU + lu;
+                    // the column's byte offset in the tile, kept whole in a
+                    // register so that each row address is one 24-bit
+                    // multiply-add (lv lies in [0, kSV - 2])
+                    uint32_t tvb = (uint32_t)(vv * kSV * kSU + lu) * 4u;
+                    asm("" : "+v"(tvb));
+                    // the rows of voxel z + 1 are read while voxel z is
+                    // interpolated (the scheduling barriers keep that order)
+                    auto rows = [&](int z, float &r0, float &r1, float &r2, float &r3) {
+                        const float fv = fmaf((float)z, dfv, fv0r);
+                        const int lv = kClampRows ? min(max((int)fv, 0), kSV - 2) : (int)fv;
+                        const float *t = reinterpret_cast<const float *>(
+                            reinterpret_cast<const char *>(tile) + (__umul24((uint32_t)lv, (uint32_t)(kSU * 4)) + tvb));
+                        r0 = t[0];
+                        r1 = t[1];
+                        r2 = t[kSU];
+                        r3 = t[kSU + 1];
+                    };
+                    float q0, q1, q2, q3;
+                    rows(0, q0, q1, q2, q3);
 #pragma unroll
                     for (int z = 0; z < kZC; ++z) {
-                        const float fv = fmaf((float)z, dfv, fv0r);
-                        const float wv = __builtin_amdgcn_fractf(fv);
-                        const int lv = kClampRows ? min(max((int)fv, 0), kSV - 2) : (int)fv;
-                        const float *t = tv + lv * kSU;
-                        const float a = fmaf(wu, t[1] - t[0], t[0]);
-                        const float b = fmaf(wu, t[kSU + 1] - t[kSU], t[kSU]);
+                        const float c0 = q0, c1 = q1, c2 = q2, c3 = q3;
+                        if (z + 1 < kZC) rows(z + 1, q0, q1, q2, q3);
+                        __builtin_amdgcn_sched_barrier(0);
+                        const float wv = __builtin_amdgcn_fractf(fmaf((float)z, dfv, fv0r));
+                        const float a = fmaf(wu, c1 - c0, c0);
+                        const float b = fmaf(wu, c3 - c2, c2);
                         grp[z] = fmaf(w, fmaf(wv, b - a, a), grp[z]);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
             };
