@@ -483,6 +483,21 @@ def bench_paper_scale(ct, torch, lib):
     return out
 
 
+def binding_bounds(ceil, g, upd, t_meas, flop_per_upd):
+    """The time a kernel cannot beat on this device, from the measured
+    ceilings: the largest of its algorithmic HBM bytes (4 n + 4 m) at the
+    streaming read rate, its algorithmic FLOP at the FP32 FMA rate and its
+    tap bytes (16 per update) at the conflict-free LDS read rate; the tap
+    bytes at the rate of the bilinear gather pattern are reported beside."""
+    t = {"hbm_ms": 4.0 * (g.n_vox + g.n_rays) / (ceil["hbm_read_gbs"] * 1e9) * 1e3,
+         "valu_ms": upd * flop_per_upd / (ceil["fp32_fma_tflops"] * 1e12) * 1e3,
+         "lds_peak_ms": upd * 16.0 / (ceil["lds_peak_gbs"] * 1e9) * 1e3}
+    bound = max(t.values())
+    t["gather_pattern_ms"] = upd * 16.0 / (ceil["lds_gather_gbs"] * 1e9) * 1e3
+    t.update({"bound_ms": bound, "measured_ms": t_meas * 1e3, "frac": bound / (t_meas * 1e3)})
+    return {k: round(v, 4) for k, v in t.items()}
+
+
 def kernel_times(ct, lib, g, b, sdt, steps):
     """Average duration of each kernel class over `steps` headline solves,
     from the library's event pairs on the solver's stream (a pass of its
@@ -618,6 +633,12 @@ def main():
         # size heuristic; the stored traffic figure was measured with it)
         "projector_setting": dict(zip(("view_group", "wg_per_cu"), ct.ct_projector_get_config(g))),
     }
+    # the device's measured ceilings and the bound each projector cannot beat
+    log("bench: device ceilings")
+    ceil = ct.ct_measure_ceilings()
+    line["ceilings"] = {k: round(v, 1) for k, v in ceil.items()}
+    line["binding_bound"] = {"A": binding_bounds(ceil, g, a_upd, t_a, FLOP_PER_A_UPDATE),
+                             "B_un": binding_bounds(ceil, g, b_upd, t_b, FLOP_PER_B_UPDATE)}
     # the autotuner's view of the same setting: every candidate timed on this
     # geometry, after which the heuristic is restored for the other legs
     log("bench: projector launch settings")

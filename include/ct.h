@@ -372,6 +372,46 @@ int ct_profile_enable(int on);
 int ct_profile_reset(void);
 int ct_profile_read(const char *name, long *launches, double *total_ms);
 
+/* Measured ceilings of the device the calling thread has current, the
+ * constants the kernels' rooflines are measured against (measurement
+ * infrastructure for callers that report a roofline; not an operation of
+ * the method).  Each figure is the best of five timed launches after a
+ * warm-up:
+ *   hbm_copy_gbs:      device-to-device copy of 512 MiB, bytes read plus
+ *                      bytes written per second, in GB/s;
+ *   hbm_read_gbs:      streaming read (sum) of 1 GiB, GB/s;
+ *   fp32_fma_tflops:   independent v_fma_f32 chains, 2 FLOP each, TFLOP/s;
+ *   fp32_add_tflops:   independent v_add_f32 chains, TFLOP/s;
+ *   lds_bilinear_gsps: bilinear samples per second (1e9) of the kind the
+ *                      projectors take (two plane coordinates, integer and
+ *                      fraction parts, four taps, three linear
+ *                      interpolations, an accumulate), taps from an LDS tile;
+ *   l2_bilinear_gsps:  the same samples with the taps gathered from a 1 MiB
+ *                      array resident in L2;
+ *   lds_gather_gbs:    the taps alone (four floats per sample, the address
+ *                      stepping by a row and/or a column), bytes read from
+ *                      LDS per second, GB/s: the gather bandwidth;
+ *   l2_gather_gbs:     the same taps gathered from the L2-resident array;
+ *   lds_peak_gbs:      LDS read bandwidth without bank conflicts (each lane
+ *                      16 consecutive bytes per read), GB/s.
+ *   out: HOST, filled on success (left as it is on an error).
+ *   stream: hipStream_t the kernels run on (NULL: the null stream).
+ * Allocates and frees 1 GiB plus 4 MiB of device memory; takes about a
+ * second.  Not for graph capture.  Errors: CT_ERR_ARG for a NULL out,
+ * CT_ERR_ALLOC, CT_ERR_HIP. */
+typedef struct ct_ceilings {
+    double hbm_copy_gbs;
+    double hbm_read_gbs;
+    double fp32_fma_tflops;
+    double fp32_add_tflops;
+    double lds_bilinear_gsps;
+    double l2_bilinear_gsps;
+    double lds_gather_gbs;
+    double l2_gather_gbs;
+    double lds_peak_gbs;
+} ct_ceilings;
+int ct_measure_ceilings(ct_ceilings *out, void *stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *ct_last_error(void);
 

@@ -28,6 +28,7 @@ from .api import (  # noqa: F401
     ct_projector_config,
     ct_projector_get_config,
     ct_tune_projector,
+    ct_measure_ceilings,
     ct_last_error,
     CtError,
     SolveResult,

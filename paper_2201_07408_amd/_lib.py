@@ -26,6 +26,7 @@ EXPORTS = [
     "ct_ba_gmres_batched_workspace_bytes", "ct_ba_gmres_batched",
     "ct_batched_config", "ct_batched_last_config",
     "ct_projector_config", "ct_projector_get_config", "ct_tune_projector",
+    "ct_measure_ceilings",
 ]
 
 
@@ -41,6 +42,12 @@ class GeometryDesc(ctypes.Structure):
         ("sod", ctypes.c_double), ("sdd", ctypes.c_double),
         ("projector", ctypes.c_int),
     ]
+
+
+class Ceilings(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "hbm_copy_gbs", "hbm_read_gbs", "fp32_fma_tflops", "fp32_add_tflops",
+        "lds_bilinear_gsps", "l2_bilinear_gsps", "lds_gather_gbs", "l2_gather_gbs", "lds_peak_gbs")]
 
 
 class SolverOpts(ctypes.Structure):
@@ -96,6 +103,7 @@ def load(path: str = LIBPATH):
         "ct_projector_config": ([gp, i, i], i),
         "ct_projector_get_config": ([gp, ip, ip], i),
         "ct_tune_projector": ([gp, i, i, ip, ip, dp, ip, vp], i),
+        "ct_measure_ceilings": ([ctypes.POINTER(Ceilings), vp], i),
         "ct_profile_enable": ([i], i),
         "ct_profile_reset": ([], i),
         "ct_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp], i),

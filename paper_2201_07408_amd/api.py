@@ -387,6 +387,18 @@ def ct_tune_projector(g: Geometry, reps: int = 3, cap: int = 32):
     return timed, ct_projector_get_config(g)
 
 
+def ct_measure_ceilings(device=None) -> dict:
+    """Measured ceilings of the device (HBM copy and read rates, FP32 FMA
+    and add rates, bilinear samples per second from LDS and from L2), on
+    the device's current stream."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    c = L.Ceilings()
+    with torch.cuda.device(dev):
+        st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        _check(L.load().ct_measure_ceilings(ctypes.byref(c), st), "ct_measure_ceilings")
+    return {name: getattr(c, name) for name, _ in L.Ceilings._fields_}
+
+
 def ct_batched_last_config():
     g, a, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(L.load().ct_batched_last_config(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b)),

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctabba.so")
-SOURCES = ["ct_geometry.hip", "ct_projectors.hip", "ct_krylov.hip", "ct_batched.hip"]
+SOURCES = ["ct_geometry.hip", "ct_projectors.hip", "ct_krylov.hip", "ct_batched.hip", "ct_microbench.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -100,3 +100,11 @@ def test_projector_setting_calls_reject_bad_arguments_on_host():
     assert lib.ct_projector_get_config(None, ctypes.byref(v), ctypes.byref(w)) == _lib.CT_ERR_ARG
     assert lib.ct_tune_projector(None, 3, 0, None, None, None, None, None) == _lib.CT_ERR_ARG
     assert b"geometry is NULL" in lib.ct_last_error()
+
+
+def test_measure_ceilings_rejects_null_output_on_host():
+    """The ceiling measurement checks its output pointer before any device
+    call."""
+    lib = _lib.load()
+    assert lib.ct_measure_ceilings(None, None) == _lib.CT_ERR_ARG
+    assert b"NULL output" in lib.ct_last_error()
